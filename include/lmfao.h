@@ -1,0 +1,292 @@
+/*
+ * lmfao.h — C ABI of the MI355X (gfx950) aggregate-batch engine.
+ *
+ * The engine evaluates a batch of group-by aggregate queries over the natural
+ * join of an acyclic database (paper, Section 1.1 problem statement and
+ * Section 2, equation (1)):
+ *
+ *     Q(F_1..F_f; alpha_1..alpha_l) += R_1(w_1), ..., R_m(w_m)
+ *
+ * where each alpha_i = sum_j c_j * prod_k X_jk is a sum of products of
+ * identity functions of continuous attributes (the empty product is the
+ * constant 1), a query may carry a conjunction of Kronecker-delta factors
+ * 1[X op t] (Section 1.1) that restricts which join tuples it sums, and every
+ * group-by attribute is categorical (cell = code) or continuous with sorted
+ * thresholds t_0 < ... < t_{T-1} (cell = #{k : t_k < x}, the buckets of the
+ * CART splits X <= t of Section 2).  COUNT is reported for every cell.
+ *
+ * Evaluation follows Section 3: queries are decomposed into directional views
+ * along the join tree towards the root (Section 3.2), identical and
+ * same-group-by views are merged (Section 3.4), views leaving the same
+ * relation form a view group evaluated by one multi-output scan over that
+ * relation (Section 3.5), and independent groups of one tree level run
+ * together (Section 1.2, parallelization).
+ *
+ * Supported join trees: every edge joins its two relations on exactly one
+ * shared int32 attribute, which is a unique key of the child relation (the
+ * star and snowflake schemas of the paper's datasets).  Keys lie in
+ * [0, domain) of the key column.  A fact row whose key has no matching child
+ * row does not join (natural-join semantics).
+ *
+ * Conventions
+ *  - Every function returns lmfao_status: LMFAO_OK (0) or a negative error;
+ *    lmfao_last_error() then describes it.  No C++ exception crosses the ABI.
+ *  - Column data and result/workspace buffers are DEVICE pointers owned by
+ *    the caller, who keeps them alive until lmfao_sync() returns.  The
+ *    library never allocates device memory itself.
+ *  - Column-major relations: each column is a contiguous array of n_rows
+ *    elements (int32 or float32).
+ *  - Call order: create -> add_relation* -> set_join_tree -> add_query* ->
+ *    plan -> workspace_size/result_size -> bind -> (execute -> sync)* ->
+ *    destroy.  Calls out of order fail with LMFAO_ERR_STATE.
+ *  - One context per host thread; a context is not thread-safe.
+ */
+#ifndef LMFAO_H
+#define LMFAO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lmfao_status;
+
+enum {
+    LMFAO_OK = 0,
+    LMFAO_ERR_INVALID_ARG = -1,  /* null pointer, bad enum, size out of range */
+    LMFAO_ERR_NOT_ACYCLIC = -2,  /* edges do not form a tree, or running intersection fails */
+    LMFAO_ERR_UNKNOWN_ATTR = -3, /* query names an attribute no relation holds */
+    LMFAO_ERR_TYPE = -4,         /* attribute kind/type does not fit its use */
+    LMFAO_ERR_DOMAIN = -5,       /* categorical code or key outside its domain (device check) */
+    LMFAO_ERR_TOO_LARGE = -6,    /* more features/filters/cells than the engine supports */
+    LMFAO_ERR_WORKSPACE = -7,    /* bound buffer smaller than required */
+    LMFAO_ERR_STATE = -8,        /* call out of order */
+    LMFAO_ERR_HIP = -9,          /* a HIP runtime call failed */
+    LMFAO_ERR_UNSUPPORTED = -10  /* join shape outside the supported class (e.g. duplicate child key) */
+};
+
+/* ---- context ------------------------------------------------------------ */
+
+typedef struct lmfao_ctx lmfao_ctx;
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the
+ * context (NULL on failure). */
+lmfao_status lmfao_create(lmfao_ctx **out, int32_t hip_device);
+
+/* Release host-side state.  Device memory belongs to the caller. */
+void lmfao_destroy(lmfao_ctx *ctx);
+
+/* Human-readable description of the last error of this context ("" if none).
+ * The string is owned by the context and valid until the next call. */
+const char *lmfao_last_error(const lmfao_ctx *ctx);
+
+/* ---- relations (Section 2, query language: relations R_1..R_m) --------- */
+
+enum { LMFAO_I32 = 0, LMFAO_F32 = 1 };                 /* dtype */
+enum { LMFAO_KEY = 0, LMFAO_CONT = 1, LMFAO_CAT = 2 };  /* kind  */
+
+typedef struct {
+    const char *attr;   /* attribute name; equal names join (natural join) */
+    int32_t dtype;      /* LMFAO_I32 for KEY/CAT, LMFAO_F32 for CONT */
+    int32_t kind;       /* LMFAO_KEY, LMFAO_CONT or LMFAO_CAT */
+    int32_t domain;     /* KEY: values in [0, domain); CAT: codes in [0, domain); CONT: ignored */
+    const void *data;   /* device pointer to n_rows elements (borrowed) */
+} lmfao_col;
+
+/* Register relation `name` with `n_cols` columns of `n_rows` rows each.
+ * *rel_id receives its index (0, 1, ... in call order).  Column pointers are
+ * borrowed; names are copied. */
+lmfao_status lmfao_add_relation(lmfao_ctx *ctx, const char *name, int64_t n_rows, int32_t n_cols,
+                                const lmfao_col *cols, int32_t *rel_id);
+
+/* Join tree (Section 3.1): `edges` holds n_edges pairs {parent, child} of
+ * relation ids; n_edges must be (number of relations - 1) and the edges must
+ * form a tree.  Each edge joins on the single attribute the two relations
+ * share, which must be a KEY of the child.  Returns LMFAO_ERR_NOT_ACYCLIC if
+ * the edges do not form a tree or an attribute's holders are not connected
+ * in it (running intersection). */
+lmfao_status lmfao_set_join_tree(lmfao_ctx *ctx, int32_t n_edges, const int32_t *edges);
+
+/* ---- queries (Section 2, equation (1)) ---------------------------------- */
+
+enum { LMFAO_LE = 0, LMFAO_LT = 1, LMFAO_GE = 2, LMFAO_GT = 3, LMFAO_EQ = 4, LMFAO_NE = 5 };
+
+typedef struct {
+    const char *attr;          /* CAT attribute, or CONT attribute with thresholds */
+    int32_t n_thresholds;      /* 0 for CAT; else number of sorted fp32 thresholds */
+    const float *thresholds;   /* host pointer, strictly increasing; copied */
+} lmfao_groupby;
+
+typedef struct {
+    const char *attr;          /* factor 1[attr op value] */
+    int32_t op;                /* LMFAO_LE .. LMFAO_NE */
+    double value;              /* compared in fp32 for CONT, as an integer for KEY/CAT */
+} lmfao_pred;
+
+typedef struct {
+    double coeff;              /* c_j */
+    int32_t n_factors;         /* 0, 1 or 2 identity factors */
+    const char *factors[2];    /* CONT attribute names */
+} lmfao_term;
+
+typedef struct {
+    int32_t n_terms;           /* alpha = sum of terms */
+    const lmfao_term *terms;
+} lmfao_agg;
+
+typedef struct {
+    int32_t n_groupby;
+    const lmfao_groupby *groupby;
+    int32_t n_preds;           /* WHERE: conjunction of all predicates */
+    const lmfao_pred *preds;
+    int32_t n_aggs;
+    const lmfao_agg *aggs;
+} lmfao_query;
+
+/* Add one query; *qid receives its index.  All descriptor memory is copied.
+ * Errors: UNKNOWN_ATTR, TYPE (e.g. a factor that is not CONT), TOO_LARGE
+ * (more than 2^31 cells). */
+lmfao_status lmfao_add_query(lmfao_ctx *ctx, const lmfao_query *q, int32_t *qid);
+
+/* ---- planning ------------------------------------------------------------ */
+
+enum { LMFAO_FP32 = 0, LMFAO_BF16X3 = 1, LMFAO_BF16X4 = 2 };       /* covariance-block arithmetic */
+enum { LMFAO_PLAIN = 0, LMFAO_BATCHED = 1 };                        /* schedule */
+enum { LMFAO_HEURISTIC = 0, LMFAO_AUTOTUNE = 1, LMFAO_LEARNED = 2 }; /* tile/grouping choice */
+
+typedef struct {
+    int32_t precision;     /* FP32: fp32 FMAs; BF16X3: bf16 hi+lo split on MFMA (hi*hi+hi*lo+lo*hi),
+                              fp32 accumulate; BF16X4 adds lo*lo.  Cross-block merge is fp64 in all. */
+    int32_t schedule;      /* PLAIN: one launch per view; BATCHED: one fused launch per tree level,
+                              captured in a hipGraph and replayed */
+    int32_t planner;       /* HEURISTIC: fixed rules; AUTOTUNE: time every candidate tile config
+                              on the device during lmfao_plan_tune; LEARNED: cost-model prediction
+                              (falls back to HEURISTIC without a model) */
+    int32_t block_rows;    /* override: rows per tile (0 = planner's choice) */
+    int32_t grid_blocks;   /* override: workgroups of the fact scan (0 = planner's choice) */
+    int32_t gram_block;    /* override: FP32 register block edge 2/4/6/8 (0 = planner's choice) */
+    const char *cost_model;/* LEARNED: path of the weights file written by lmfao_train_cost_model */
+} lmfao_plan_opts;
+
+/* Build the evaluation plan for all queries added so far. */
+lmfao_status lmfao_plan(lmfao_ctx *ctx, const lmfao_plan_opts *opts);
+
+/* Plan statistics, the analogue of the paper's Table 2. */
+typedef struct {
+    int32_t app_aggregates;      /* A: aggregates the queries ask for (incl. one COUNT per query) */
+    int32_t inter_aggregates;    /* I: additional per-key aggregates carried by child views */
+    int32_t views;               /* V: views after merging */
+    int32_t groups;              /* G: view groups */
+    int32_t levels;              /* dependency levels of view groups */
+    int32_t features;            /* continuous features in the covariance block (incl. constant 1) */
+    int32_t filters;             /* distinct WHERE conjunctions */
+    int32_t tables;              /* grouped result tables */
+    int64_t table_cells;         /* cells over all grouped tables */
+    int32_t launches;            /* kernel launches per execution */
+    int32_t block_rows, grid_blocks, gram_block, lds_tables; /* chosen tile configuration */
+} lmfao_stats;
+
+lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);
+
+/* ---- memory -------------------------------------------------------------- */
+
+/* Device scratch the plan needs (views, partials, tables, descriptors). */
+lmfao_status lmfao_workspace_size(const lmfao_ctx *ctx, size_t *bytes);
+
+/* Size of the result arena and the layout of query `qid` inside it:
+ * counts at byte offset *counts_off (uint64[n_cells]); sums at byte offset
+ * *sums_off (double[n_cells * n_sums], sums[cell * n_sums + i] = alpha_i).
+ * Cells are dense over the product of the group-by domains, first group-by
+ * most significant. */
+lmfao_status lmfao_result_size(const lmfao_ctx *ctx, size_t *bytes);
+lmfao_status lmfao_result_layout(const lmfao_ctx *ctx, int32_t qid, int64_t *n_cells, int32_t *n_sums,
+                                 size_t *counts_off, size_t *sums_off);
+
+/* Bind caller-allocated device buffers (256-byte aligned) of at least the
+ * reported sizes.  Errors: WORKSPACE (too small or misaligned). */
+lmfao_status lmfao_bind(lmfao_ctx *ctx, void *workspace, size_t ws_bytes, void *results, size_t res_bytes);
+
+/* ---- execution ----------------------------------------------------------- */
+
+/* Enqueue one evaluation of the whole batch on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Asynchronous: results are valid after
+ * lmfao_sync().  With LMFAO_BATCHED the launches are captured in a hipGraph
+ * on the first call and replayed afterwards. */
+lmfao_status lmfao_execute(lmfao_ctx *ctx, void *hip_stream);
+
+/* Wait for the last execution and surface device-side errors: DOMAIN for a
+ * categorical code or key outside its domain, UNSUPPORTED for a duplicate
+ * child key, HIP for runtime failures. */
+lmfao_status lmfao_sync(lmfao_ctx *ctx);
+
+/* Time the fact-scan view group alone: runs it `reps` times after `warmup`
+ * runs on `hip_stream` and stores the mean milliseconds per run in *ms
+ * (hipEvents on that stream).  The views of lower levels must be current
+ * (call after one lmfao_execute). */
+lmfao_status lmfao_time_root_group(lmfao_ctx *ctx, void *hip_stream, int32_t warmup, int32_t reps, double *ms);
+
+/* ---- tile choice: exhaustive autotuner and learned cost model ------------ */
+
+/* Number of candidate tile configurations of the current plan, and the
+ * candidate `i` as {block_rows, grid_blocks, gram_block, lds_tables}. */
+lmfao_status lmfao_candidates(const lmfao_ctx *ctx, int32_t *n);
+lmfao_status lmfao_candidate(const lmfao_ctx *ctx, int32_t i, int32_t cfg[4]);
+
+/* Feature vector of the root view group under candidate `i` (input of the
+ * cost model): LMFAO_N_FEATURES floats. */
+#define LMFAO_N_FEATURES 16
+lmfao_status lmfao_candidate_features(const lmfao_ctx *ctx, int32_t i, float *features);
+
+/* Re-plan with candidate `i` as the tile configuration (must be bound again). */
+lmfao_status lmfao_select_candidate(lmfao_ctx *ctx, int32_t i);
+
+/* Exhaustive autotuner: time every candidate (needs bound buffers and one
+ * prior lmfao_execute), append one line per candidate to the timing file
+ * `timing_db` (features, configuration, milliseconds; may be NULL), and
+ * select the fastest.  *best receives its index. */
+lmfao_status lmfao_autotune(lmfao_ctx *ctx, void *hip_stream, const char *timing_db, int32_t reps, int32_t *best);
+
+/* Learned choice: score every candidate with the cost model in `weights`
+ * (inference runs on the device in the workspace), select the lowest
+ * predicted time, and store its index in *best.  Falls back to the
+ * heuristic configuration (and returns LMFAO_OK with *best = -1) if the
+ * model is missing or predicts a non-finite time. */
+lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t *best);
+
+/* ---- cost-model network (hand-written device kernels) -------------------- */
+
+/* A fully connected network  in(16) -> H -> H -> 1  with ReLU, predicting
+ * log(milliseconds).  Parameters live in one fp32 device array laid out as
+ * W1[H][16], b1[H], W2[H][H], b2[H], W3[1][H], b3[1]. */
+int32_t lmfao_mlp_param_count(int32_t hidden);
+
+/* y[n] = f(x[n][16]) for device arrays x, y, params. */
+lmfao_status lmfao_mlp_forward(int32_t hidden, const float *params, const float *x, int32_t n, float *y,
+                               void *hip_stream);
+
+/* Mean-squared-error loss over n samples and its gradient w.r.t. all
+ * parameters (device arrays; grad has lmfao_mlp_param_count() floats,
+ * loss is one float).  `scratch` needs lmfao_mlp_scratch_floats(hidden, n). */
+int64_t lmfao_mlp_scratch_floats(int32_t hidden, int32_t n);
+lmfao_status lmfao_mlp_loss_grad(int32_t hidden, const float *params, const float *x, const float *target,
+                                 int32_t n, float *loss, float *grad, float *scratch, void *hip_stream);
+
+/* One Adam step (Kingma & Ba 2015) on device arrays: m, v are the moment
+ * estimates, `step` the 1-based step count. */
+lmfao_status lmfao_adam_step(int32_t n_params, float *params, const float *grad, float *m, float *v,
+                             int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* Full-batch training loop on the device: `epochs` steps of
+ * lmfao_mlp_loss_grad followed by lmfao_adam_step (beta1 0.9, beta2 0.999,
+ * eps 1e-8), storing each step's loss in the device array losses[epochs].
+ * `grad` holds lmfao_mlp_param_count() floats, m and v start at zero. */
+lmfao_status lmfao_mlp_train(int32_t hidden, float *params, float *m, float *v, const float *x, const float *target,
+                             int32_t n, int32_t epochs, float lr, float *grad, float *scratch, float *losses,
+                             void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMFAO_H */

@@ -1,0 +1,218 @@
+// Device-side descriptors shared by the host planner and the HIP kernels.
+//
+// A plan is a list of scans.  Each scan reads one relation once (the
+// multi-output scan of a view group, paper Section 3.5) and either
+//   * builds the key-indexed view record of a non-root relation (leaf and
+//     snowflake views, Section 3.2), or
+//   * evaluates every outgoing view of the root relation: the covariance
+//     block of ungrouped sums, a total count, and grouped tables.
+//
+// View record layout (32-bit words, one record per key of the relation):
+//   [0]                 count of joining rows with this key (0 or 1)
+//   [1 .. 1+n_mask)     filter mask words: bit f = every conjunct of filter f
+//                       on an attribute of this subtree holds
+//   [comp_off ..)       group-by components of this subtree (int32 cells)
+//   [feat_off ..)       continuous features of this subtree (fp32)
+//   padded to a multiple of 4 words (one 16-byte load per 4 words).
+#pragma once
+#include <stdint.h>
+
+namespace lmfao {
+
+constexpr int kMaxFeat = 64;      // staged features per row, including the constant 1
+constexpr int kMaxComp = 32;      // staged group-by components per row
+constexpr int kMaxFilters = 64;   // distinct WHERE conjunctions
+constexpr int kMaxKeyComps = 4;   // components of one group-by key
+constexpr int kBlock = 256;       // threads per workgroup of every scan (one row per thread)
+
+// error flags accumulated on the device, reported by lmfao_sync
+constexpr uint32_t kErrDomain = 1u;     // categorical code outside [0, domain)
+constexpr uint32_t kErrDupKey = 2u;     // two rows of a child relation share a key
+constexpr uint32_t kErrKeyRange = 4u;   // a primary key outside [0, n_keys)
+
+enum Op : int32_t { OP_LE = 0, OP_LT = 1, OP_GE = 2, OP_GT = 3, OP_EQ = 4, OP_NE = 5 };
+
+struct FeatSrc {          // continuous attribute of the scanned relation -> staged feature slot
+    const float *col;
+    int32_t dst;
+    int32_t pad;
+};
+
+struct CompSrc {          // group-by component of the scanned relation -> staged component slot
+    const void *col;      // int32 codes, or fp32 values when nthr > 0
+    const float *thr;     // sorted thresholds (device) for a bucketed attribute
+    int32_t nthr;         // 0: categorical code
+    int32_t dom;          // domain of the cell index
+    int32_t dst;
+    int32_t pad;
+};
+
+struct PredSrc {          // one conjunct 1[X op t] of filter `filter`
+    const void *col;
+    int32_t is_float;
+    int32_t op;
+    float fval;
+    int32_t ival;
+    int32_t filter;
+    int32_t pad;
+};
+
+struct ChildSrc {         // a child view gathered through a foreign key of the scanned relation
+    const int32_t *fk;    // foreign-key column of the scanned relation
+    const uint32_t *rec;  // child view records, indexed by key
+    int32_t n_keys;
+    int32_t stride;       // words per record
+    int32_t n_mask;       // mask words carried by the child record
+    int32_t comp_off, n_comp, comp_dst;
+    int32_t feat_off, n_feat, feat_dst;
+    int32_t pad;
+};
+
+struct ScanDesc {
+    int64_t n_rows;
+    int32_t n_feat, n_comp, n_pred, n_child;
+    int32_t n_mask;               // mask words in use (0, 1 or 2)
+    int32_t pad0;
+    uint64_t filter_all;          // bits of every filter of the plan
+    const FeatSrc *feats;
+    const CompSrc *comps;
+    const PredSrc *preds;
+    const ChildSrc *children;
+    // view building only
+    const int32_t *key;           // primary-key column
+    int32_t n_keys;               // record count (key domain)
+    int32_t rec_stride;
+    int32_t rec_comp_off, rec_feat_off;
+    int32_t rec_n_comp, rec_n_feat;
+    uint32_t *rec_out;
+    uint32_t *seen;               // per key: rows seen (duplicate detection)
+    uint32_t *err;
+};
+
+// ---- root multi-output scan ------------------------------------------------
+
+struct KeyDesc {          // group-by key: cell = sum_i comp[c[i]] * s[i]
+    int32_t c[kMaxKeyComps];
+    int32_t s[kMaxKeyComps];
+    int32_t n_comp;
+    int32_t n_cells;
+};
+
+struct ValDesc {          // summed monomial x[a] * x[b]; feature 0 is the constant 1
+    int16_t a, b;
+};
+
+struct TabDesc {          // one table = (filter, key) of a family
+    int32_t part;         // table partition (blockIdx.y) that evaluates it
+    int32_t lds_cnt;      // word offset of uint32 counts in LDS, or -1 when global
+    int32_t lds_val;      // word offset of fp32 sums in LDS
+    int32_t pad;
+    int64_t glb_cnt;      // index of the first uint64 count in the global count array
+    int64_t glb_val;      // index of the first double sum in the global sum array
+};
+
+struct FlushDesc {        // an LDS-resident table of one partition, copied out at the end
+    int32_t lds_cnt, lds_val;
+    int32_t n_cells, n_vals;
+    int64_t glb_cnt, glb_val;
+};
+
+constexpr int kMaxParts = 16;
+
+struct FamilyDesc {       // tables sharing one list of summed monomials
+    int32_t n_filt;       // filters (1 when the family is unfiltered)
+    int32_t unfiltered;
+    int32_t filt_base;    // into filt_bits (filter bit of each family filter, ascending)
+    int32_t n_keys;
+    int32_t key_base;     // into keys
+    int32_t n_vals;
+    int32_t val_base;     // into vals
+    int32_t tab_base;     // table (f, k) = tab_base + f * n_keys + k
+    uint64_t filt_mask;   // union of the family's filter bits
+    uint64_t part_mask[kMaxParts];   // filter bits whose tables belong to each partition
+};
+
+struct RootDesc {
+    ScanDesc scan;
+    int32_t n_feat;       // staged features (feature 0 = constant 1)
+    int32_t n_gram;       // covariance block over features [0, n_gram); 0 = none
+    int32_t n_comp;       // staged components
+    int32_t n_tfeat;      // features [0, n_tfeat) are read by table values
+    int32_t n_fam;
+    int32_t do_count;     // accumulate the total count
+    int32_t n_parts;      // table partitions (grid.y)
+    int32_t gram_part;    // partition whose workgroups compute the covariance block and count
+    // dynamic LDS layout, 32-bit word offsets
+    int32_t lds_tables;   // table storage (size lds_table_words[part])
+    int32_t lds_xs;       // fp32 covariance tile [kBlock][ngp]
+    int32_t ngp;          // row pitch of the fp32 tile
+    int32_t lds_frag;     // bf16 fragments, per wave frag_wave_words
+    int32_t frag_sp;      // words between (k-step, hi/lo) fragment blocks
+    int32_t frag_wave_words;
+    int32_t lds_tfeat;    // fp32 table features [kBlock][n_tfeat]
+    int32_t lds_tcomp;    // int32 components [kBlock][n_comp]
+    int32_t lds_red;      // fp64 reduction scratch (aliases the staging area at the end)
+    int32_t pad0;
+    int32_t lds_table_words[kMaxParts];
+    int32_t flush_base[kMaxParts], n_flush[kMaxParts];
+    int64_t rows_per_block;    // contiguous rows per workgroup (multiple of kBlock)
+    const FamilyDesc *fams;
+    const KeyDesc *keys;
+    const ValDesc *vals;
+    const TabDesc *tabs;
+    const FlushDesc *flush;
+    const int32_t *filt_bits;
+    unsigned long long *g_cnt;
+    double *g_val;
+    double *gram_partial;              // [grid.x][n_gram * n_gram]
+    unsigned long long *count_partial; // [grid.x]
+    uint32_t *err;
+};
+
+// ---- final merge and result assembly -----------------------------------------
+
+struct MergeDesc {
+    int32_t grid;                      // partials to reduce
+    int32_t n_gram;
+    const double *gram_partial;
+    const unsigned long long *count_partial;
+    double *gram;                      // [n_gram * n_gram], symmetric
+    unsigned long long *count;         // total joined tuples
+};
+
+enum SrcKind : int32_t { SRC_GRAM = 0, SRC_TABLE = 1 };
+
+struct OutDesc {          // one query's result
+    int32_t kind;         // SRC_GRAM (ungrouped, unfiltered) or SRC_TABLE
+    int32_t n_aggs;
+    int64_t n_cells;
+    int64_t dst_cnt;      // index into the result arena (uint64 units)
+    int64_t dst_sum;      // index into the result arena (double units)
+    int64_t src_cnt;      // table: first global count
+    int64_t src_val;      // table: first global sum
+    int32_t src_nvals;    // table: values per cell
+    int32_t term_base;    // into terms
+    int32_t pad[2];
+};
+
+struct TermDesc {         // alpha_agg += coeff * source value
+    int32_t agg;
+    int32_t src;          // gram: i * n_gram + j; table: value index; -1: the count
+    double coeff;
+};
+
+struct AssembleDesc {
+    int32_t n_out;
+    int32_t n_gram;
+    const OutDesc *outs;
+    const TermDesc *terms;
+    const int32_t *term_count;     // terms per output
+    const double *gram;
+    const unsigned long long *count;
+    const unsigned long long *g_cnt;
+    const double *g_val;
+    unsigned long long *res_cnt;
+    double *res_sum;
+};
+
+}  // namespace lmfao

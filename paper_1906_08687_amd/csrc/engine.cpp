@@ -1,0 +1,1812 @@
+// Host side of the aggregate-batch engine: the C ABI of include/lmfao.h,
+// the planner and the executor.
+//
+// Planning follows the layers of the paper (Section 1.2, Figure 1):
+//   join tree      validated tree of single-key edges (Section 3.1); the
+//                  root is the relation that is no edge's child;
+//   pushdown       every query is decomposed into one view per edge towards
+//                  the root (Section 3.2): the view of a child subtree T_i
+//                  carries the join key and exactly the parts of the query
+//                  that live in T_i -- its continuous factors, its group-by
+//                  components and its conjuncts, evaluated once per key
+//                  (Appendix D, "evaluate each UDAF once");
+//   merge          views with the same direction and group-by attributes are
+//                  merged (Section 3.4, cases 1-3): per child relation the
+//                  plan keeps ONE view record holding the union of what all
+//                  queries need; at the root, queries with equal group-by
+//                  and filter share one table whose aggregate list is the
+//                  union of their monomials, and every ungrouped unfiltered
+//                  sum shares the covariance block;
+//   group          the views leaving one relation form a view group and are
+//                  computed by one scan of that relation (Section 3.4);
+//   levels         a relation's group depends on its children's groups; the
+//                  groups of one tree level are independent (Section 1.2,
+//                  parallelization) and run in one launch when batched.
+// Code specialisation (Section 3.5, Appendix D) is replaced by templated
+// kernels and runtime descriptors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <set>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "desc.h"
+#include "lmfao.h"
+
+namespace lmfao {
+struct FillDesc {
+    uint32_t *ptr;
+    int64_t n_words;
+};
+typedef void (*RootKernel)(const RootDesc *);
+RootKernel root_kernel(int mode, int p1, bool tables);
+hipError_t launch_fill(const void *fills, int n, hipStream_t st);
+hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hipStream_t st);
+hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st);
+hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
+hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
+hipError_t launch_assemble(const AssembleDesc *desc, int n_out, hipStream_t st);
+// cost-model network (mlp.hip)
+hipError_t mlp_forward_dev(int hidden, const float *params, const float *x, int n, float *y, hipStream_t st);
+}  // namespace lmfao
+
+using namespace lmfao;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kGridMax = 2048;
+
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+struct Col {
+    std::string attr;
+    int32_t dtype, kind, domain;
+    const void *data;
+};
+
+struct Rel {
+    std::string name;
+    int64_t n_rows = 0;
+    std::vector<Col> cols;
+    int find(const std::string &a) const {
+        for (size_t i = 0; i < cols.size(); ++i)
+            if (cols[i].attr == a) return (int)i;
+        return -1;
+    }
+};
+
+struct QGroupBy {
+    std::string attr;
+    std::vector<float> thr;
+};
+struct QPred {
+    std::string attr;
+    int32_t op;
+    double value;
+};
+struct QTerm {
+    double coeff;
+    std::vector<std::string> f;
+};
+struct QAgg {
+    std::vector<QTerm> terms;
+};
+struct Query {
+    std::vector<QGroupBy> gb;
+    std::vector<QPred> preds;
+    std::vector<QAgg> aggs;
+};
+
+struct ARef {
+    int rel = -1, col = -1;
+    bool operator<(const ARef &o) const { return rel != o.rel ? rel < o.rel : col < o.col; }
+    bool operator==(const ARef &o) const { return rel == o.rel && col == o.col; }
+};
+
+struct Comp {              // a group-by component (an attribute, or its buckets)
+    ARef src;
+    std::vector<float> thr;
+    int dom = 0;
+    int slot = -1;          // staged component index at the root
+};
+
+struct Conj {              // one conjunct of a filter
+    ARef src;
+    int op;
+    double value;
+};
+
+struct Table {
+    std::vector<int> comps;             // component ids (group-by order)
+    int filter = -1;                    // -1: none
+    std::vector<std::pair<int, int>> vals;   // monomials (feature a <= b), sorted
+    int64_t n_cells = 1;
+    // placement
+    int part = 0;
+    int lds_cnt = -1, lds_val = -1;
+    int64_t glb_cnt = 0, glb_val = 0;
+    // uint32 counts, then fp64 sums at an even word offset
+    int words() const { return (int)(round_up((int)n_cells, 2) + 2 * n_cells * (int64_t)vals.size()); }
+    int val_off() const { return round_up((int)n_cells, 2); }
+};
+
+struct Family {
+    std::vector<std::pair<int, int>> vals;
+    std::vector<std::vector<int>> keys;   // component lists
+    std::vector<int> filters;             // ascending filter ids; empty = unfiltered
+    std::vector<int> tables;              // index f * n_keys + k -> table id
+};
+
+struct OutTerm {
+    int agg;
+    int src;          // gram entry / table value index; -1 = count
+    double coeff;
+};
+
+struct Output {
+    bool gram = false;
+    int table = -1;
+    int64_t n_cells = 1;
+    int n_aggs = 0;
+    size_t cnt_off = 0, sum_off = 0;   // bytes in the result arena
+    std::vector<OutTerm> terms;
+};
+
+struct TileCfg {
+    int grid_x = 0;         // requested workgroups (0 = heuristic)
+    int gram_block = 0;     // fp32 register block edge
+    int lds_policy = -1;    // 0 global tables, 1 greedy LDS, 2 partitioned LDS (-1 = heuristic)
+};
+
+struct RootLaunch {         // one launch of the root scan (batched: one; plain: one per view)
+    int mode = 0, p1 = 1;
+    bool tables = false;
+    int grid_x = 1, parts = 1;
+    size_t lds_bytes = 0;
+    RootDesc desc;           // pointers filled at bind
+    std::vector<int> fam_ids;        // families evaluated (plain: one table view)
+    int single_table = -1;           // plain mode: the one table of this launch
+    bool with_gram = false;
+    size_t desc_off = 0;
+};
+
+struct Plan {
+    bool ok = false;
+    // tree
+    int root = -1;
+    std::vector<int> parent, depth, height;
+    std::vector<std::vector<int>> children;
+    std::vector<int> fk_col;     // per non-root relation: FK column in its parent
+    std::vector<int> pk_col;     // per non-root relation: key column in itself
+    std::vector<int> n_keys;     // per non-root relation: key domain
+    int levels = 0;
+    // staged features / components, in DFS order of relations
+    std::vector<ARef> feats;                 // [0] = constant 1
+    std::vector<std::vector<int>> own_feats; // per relation, feature ids
+    std::vector<int> sub_feat_lo, sub_feat_n;   // subtree feature range in staged order
+    std::vector<Comp> comps;
+    std::vector<std::vector<int>> own_comps;
+    std::vector<int> sub_comp_lo, sub_comp_n;
+    std::vector<std::vector<Conj>> filters;
+    std::vector<std::vector<std::pair<int, int>>> own_preds;   // per relation: (filter, conjunct index)
+    int n_mask = 0;
+    // record layouts of non-root relations
+    std::vector<int> rec_stride, rec_comp_off, rec_feat_off;
+    // root outputs
+    int n_feat = 1, n_gram = 0;
+    bool need_count = false;
+    std::vector<Table> tables;
+    std::vector<Family> fams;
+    std::vector<Output> outs;
+    int64_t table_cells = 0, table_vals = 0;
+    // schedule
+    int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
+    TileCfg cfg;                      // chosen tile configuration
+    int gram_block = 4, n_tiles16 = 1, mode = 0, lds_policy = 0, parts = 1;
+    int grid_x = 1;
+    int64_t rows_per_block = kBlock;
+    std::vector<RootLaunch> root_launches;
+    int app_aggs = 0, inter_aggs = 0, views = 0, groups = 0;
+    // sizes
+    size_t ws_bytes = 0, res_bytes = 0;
+};
+
+}  // namespace
+
+struct lmfao_ctx {
+    int device = 0;
+    bool has_device = false;
+    int n_cu = 256;
+    size_t lds_limit = 160 * 1024;
+    std::string err;
+    std::vector<Rel> rels;
+    std::vector<std::pair<int, int>> edges;
+    bool tree_set = false;
+    std::vector<Query> queries;
+    lmfao_plan_opts opts{};
+    Plan plan;
+    // binding
+    uint8_t *ws = nullptr;
+    size_t ws_len = 0;
+    uint8_t *res = nullptr;
+    size_t res_len = 0;
+    bool bound = false;
+    // device layout (offsets into ws)
+    size_t off_err = 0, off_gcnt = 0, off_gval = 0, off_gpart = 0, off_cpart = 0, off_gram = 0, off_count = 0;
+    size_t off_desc = 0, off_mlp = 0;
+    std::vector<size_t> off_rec, off_seen;
+    std::vector<uint8_t> blob;       // descriptor image copied to ws + off_desc
+    size_t fill_off = 0;
+    int n_fills = 0;
+    std::vector<std::vector<int>> level_rels;     // relations per level (non-root)
+    std::vector<size_t> view_desc_off;            // per relation: ScanDesc offset in blob
+    size_t merge_off = 0, assemble_off = 0;
+    // execution
+    hipStream_t last_stream = nullptr;
+    bool executed = false;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+static lmfao_status fail(lmfao_ctx *c, lmfao_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                                \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) return fail((ctx), LMFAO_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ============================================================================
+// context, relations, join tree, queries
+// ============================================================================
+
+extern "C" lmfao_status lmfao_create(lmfao_ctx **out, int32_t hip_device) {
+    if (!out) return LMFAO_ERR_INVALID_ARG;
+    *out = nullptr;
+    lmfao_ctx *c = new (std::nothrow) lmfao_ctx();
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    c->device = hip_device;
+    int n = 0;
+    if (hipGetDeviceCount(&n) == hipSuccess && n > hip_device && hip_device >= 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+            c->has_device = true;
+            c->n_cu = prop.multiProcessorCount;
+            c->lds_limit = prop.sharedMemPerBlock;
+        }
+    } else {
+        (void)hipGetLastError();
+    }
+    *out = c;
+    return LMFAO_OK;
+}
+
+extern "C" void lmfao_destroy(lmfao_ctx *c) {
+    if (!c) return;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_def) (void)hipGraphDestroy(c->graph_def);
+    delete c;
+}
+
+extern "C" const char *lmfao_last_error(const lmfao_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+static void invalidate(lmfao_ctx *c) {
+    c->plan.ok = false;
+    c->bound = false;
+    c->executed = false;
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    if (c->graph_def) { (void)hipGraphDestroy(c->graph_def); c->graph_def = nullptr; }
+}
+
+extern "C" lmfao_status lmfao_add_relation(lmfao_ctx *c, const char *name, int64_t n_rows, int32_t n_cols,
+                                           const lmfao_col *cols, int32_t *rel_id) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (c->tree_set) return fail(c, LMFAO_ERR_STATE, "relations must be added before the join tree");
+    if (!name || n_rows < 0 || n_cols <= 0 || !cols) return fail(c, LMFAO_ERR_INVALID_ARG, "bad relation arguments");
+    if (n_rows > ((int64_t)1 << 40)) return fail(c, LMFAO_ERR_TOO_LARGE, "relation too large");
+    Rel r;
+    r.name = name;
+    r.n_rows = n_rows;
+    for (int i = 0; i < n_cols; ++i) {
+        const lmfao_col &x = cols[i];
+        if (!x.attr || (!x.data && n_rows > 0)) return fail(c, LMFAO_ERR_INVALID_ARG, "column without name or data");
+        if (x.kind < LMFAO_KEY || x.kind > LMFAO_CAT || x.dtype < LMFAO_I32 || x.dtype > LMFAO_F32)
+            return fail(c, LMFAO_ERR_INVALID_ARG, std::string("bad kind/dtype for ") + x.attr);
+        if ((x.kind == LMFAO_CONT) != (x.dtype == LMFAO_F32))
+            return fail(c, LMFAO_ERR_TYPE, std::string("CONT columns are F32, KEY/CAT columns I32: ") + x.attr);
+        if (x.kind != LMFAO_CONT && x.domain <= 0)
+            return fail(c, LMFAO_ERR_INVALID_ARG, std::string("KEY/CAT column needs a positive domain: ") + x.attr);
+        if (r.find(x.attr) >= 0) return fail(c, LMFAO_ERR_INVALID_ARG, std::string("duplicate attribute ") + x.attr);
+        r.cols.push_back(Col{x.attr, x.dtype, x.kind, x.domain, x.data});
+    }
+    for (auto &o : c->rels)
+        if (o.name == r.name) return fail(c, LMFAO_ERR_INVALID_ARG, "duplicate relation name " + r.name);
+    c->rels.push_back(std::move(r));
+    if (rel_id) *rel_id = (int32_t)c->rels.size() - 1;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_set_join_tree(lmfao_ctx *c, int32_t n_edges, const int32_t *edges) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (c->tree_set) return fail(c, LMFAO_ERR_STATE, "join tree already set");
+    const int m = (int)c->rels.size();
+    if (m == 0) return fail(c, LMFAO_ERR_STATE, "no relations");
+    if (n_edges != m - 1 || (n_edges > 0 && !edges))
+        return fail(c, LMFAO_ERR_NOT_ACYCLIC, "a join tree over m relations has m-1 edges");
+    std::vector<int> parent(m, -1);
+    for (int e = 0; e < n_edges; ++e) {
+        const int p = edges[2 * e], ch = edges[2 * e + 1];
+        if (p < 0 || p >= m || ch < 0 || ch >= m || p == ch)
+            return fail(c, LMFAO_ERR_INVALID_ARG, "edge names an unknown relation");
+        if (parent[ch] != -1) return fail(c, LMFAO_ERR_NOT_ACYCLIC, "relation " + c->rels[ch].name + " has two parents");
+        parent[ch] = p;
+    }
+    int root = -1;
+    for (int r = 0; r < m; ++r)
+        if (parent[r] == -1) {
+            if (root != -1) return fail(c, LMFAO_ERR_NOT_ACYCLIC, "edges do not connect all relations");
+            root = r;
+        }
+    if (root == -1) return fail(c, LMFAO_ERR_NOT_ACYCLIC, "edges form a cycle");
+    for (int r = 0; r < m; ++r) {   // every relation reaches the root
+        int x = r, steps = 0;
+        while (x != root && steps <= m) { x = parent[x]; ++steps; }
+        if (x != root) return fail(c, LMFAO_ERR_NOT_ACYCLIC, "edges form a cycle");
+    }
+    // each edge joins on exactly one shared attribute, a KEY of the child
+    for (int ch = 0; ch < m; ++ch) {
+        if (ch == root) continue;
+        const Rel &P = c->rels[parent[ch]], &C = c->rels[ch];
+        int shared = 0;
+        std::string name;
+        for (auto &col : C.cols)
+            if (P.find(col.attr) >= 0) { ++shared; name = col.attr; }
+        if (shared != 1)
+            return fail(c, LMFAO_ERR_UNSUPPORTED, "edge " + P.name + "-" + C.name + " must share exactly one attribute");
+        const Col &pc = P.cols[P.find(name)], &cc = C.cols[C.find(name)];
+        if (pc.kind != LMFAO_KEY || cc.kind != LMFAO_KEY)
+            return fail(c, LMFAO_ERR_TYPE, "join attribute " + name + " must be KEY in both relations");
+    }
+    // running intersection: the holders of every attribute are connected in the tree
+    std::map<std::string, std::vector<int>> holders;
+    for (int r = 0; r < m; ++r)
+        for (auto &col : c->rels[r].cols) holders[col.attr].push_back(r);
+    for (auto &kv : holders) {
+        if (kv.second.size() < 2) continue;
+        std::set<int> hs(kv.second.begin(), kv.second.end());
+        int inner = 0;
+        for (int r : kv.second)
+            if (r != root && hs.count(parent[r])) ++inner;
+        if (inner != (int)hs.size() - 1)
+            return fail(c, LMFAO_ERR_NOT_ACYCLIC, "attribute " + kv.first + " violates the running intersection property");
+    }
+    c->edges.clear();
+    for (int e = 0; e < n_edges; ++e) c->edges.push_back({edges[2 * e], edges[2 * e + 1]});
+    c->tree_set = true;
+    return LMFAO_OK;
+}
+
+static bool find_attr(const lmfao_ctx *c, const std::string &a, ARef &out) {
+    // a non-key attribute has one holder; a join key is read where it is closest to the root
+    const Plan &P = c->plan;
+    int best = -1, bestcol = -1, bestdepth = 1 << 30;
+    for (int r = 0; r < (int)c->rels.size(); ++r) {
+        const int col = c->rels[r].find(a);
+        if (col < 0) continue;
+        int d = 0, x = r;
+        while (x >= 0 && x < (int)P.parent.size() && P.parent[x] >= 0) { x = P.parent[x]; ++d; }
+        if (d < bestdepth) { best = r; bestcol = col; bestdepth = d; }
+    }
+    out.rel = best;
+    out.col = bestcol;
+    return best >= 0;
+}
+
+extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int32_t *qid) {
+    if (!c || !q) return LMFAO_ERR_INVALID_ARG;
+    if (!c->tree_set) return fail(c, LMFAO_ERR_STATE, "set the join tree before adding queries");
+    if (q->n_groupby < 0 || q->n_preds < 0 || q->n_aggs < 0 || (q->n_groupby && !q->groupby) ||
+        (q->n_preds && !q->preds) || (q->n_aggs && !q->aggs))
+        return fail(c, LMFAO_ERR_INVALID_ARG, "bad query arrays");
+    auto holder = [&](const char *a) -> const Col * {
+        if (!a) return nullptr;
+        for (auto &r : c->rels) {
+            const int i = r.find(a);
+            if (i >= 0) return &r.cols[i];
+        }
+        return nullptr;
+    };
+    Query Q;
+    double cells = 1.0;
+    for (int g = 0; g < q->n_groupby; ++g) {
+        const lmfao_groupby &x = q->groupby[g];
+        const Col *col = holder(x.attr);
+        if (!col) return fail(c, LMFAO_ERR_UNKNOWN_ATTR, std::string("unknown group-by attribute ") + (x.attr ? x.attr : "(null)"));
+        QGroupBy G;
+        G.attr = x.attr;
+        if (x.n_thresholds < 0 || (x.n_thresholds > 0 && !x.thresholds))
+            return fail(c, LMFAO_ERR_INVALID_ARG, "bad thresholds");
+        if (col->kind == LMFAO_CONT) {
+            if (x.n_thresholds == 0) return fail(c, LMFAO_ERR_TYPE, "a continuous group-by needs thresholds: " + G.attr);
+            G.thr.assign(x.thresholds, x.thresholds + x.n_thresholds);
+            for (size_t k = 1; k < G.thr.size(); ++k)
+                if (!(G.thr[k - 1] < G.thr[k])) return fail(c, LMFAO_ERR_INVALID_ARG, "thresholds must increase strictly");
+            cells *= (double)(x.n_thresholds + 1);
+        } else {
+            if (x.n_thresholds != 0) return fail(c, LMFAO_ERR_TYPE, "thresholds apply to continuous attributes: " + G.attr);
+            cells *= (double)col->domain;
+        }
+        Q.gb.push_back(G);
+    }
+    if (cells > 2147483647.0) return fail(c, LMFAO_ERR_TOO_LARGE, "query has more than 2^31 cells");
+    for (int p = 0; p < q->n_preds; ++p) {
+        const lmfao_pred &x = q->preds[p];
+        if (!holder(x.attr)) return fail(c, LMFAO_ERR_UNKNOWN_ATTR, std::string("unknown predicate attribute ") + (x.attr ? x.attr : "(null)"));
+        if (x.op < LMFAO_LE || x.op > LMFAO_NE) return fail(c, LMFAO_ERR_INVALID_ARG, "bad predicate operator");
+        Q.preds.push_back(QPred{x.attr, x.op, x.value});
+    }
+    for (int a = 0; a < q->n_aggs; ++a) {
+        const lmfao_agg &x = q->aggs[a];
+        if (x.n_terms < 0 || (x.n_terms && !x.terms)) return fail(c, LMFAO_ERR_INVALID_ARG, "bad aggregate terms");
+        QAgg A;
+        for (int t = 0; t < x.n_terms; ++t) {
+            const lmfao_term &tm = x.terms[t];
+            if (tm.n_factors < 0 || tm.n_factors > 2)
+                return fail(c, LMFAO_ERR_TOO_LARGE, "terms are products of at most two attributes");
+            QTerm T;
+            T.coeff = tm.coeff;
+            for (int f = 0; f < tm.n_factors; ++f) {
+                const Col *col = holder(tm.factors[f]);
+                if (!col) return fail(c, LMFAO_ERR_UNKNOWN_ATTR, std::string("unknown factor ") + (tm.factors[f] ? tm.factors[f] : "(null)"));
+                if (col->kind != LMFAO_CONT) return fail(c, LMFAO_ERR_TYPE, std::string("factor must be continuous: ") + tm.factors[f]);
+                T.f.push_back(tm.factors[f]);
+            }
+            A.terms.push_back(T);
+        }
+        Q.aggs.push_back(A);
+    }
+    c->queries.push_back(std::move(Q));
+    invalidate(c);
+    if (qid) *qid = (int32_t)c->queries.size() - 1;
+    return LMFAO_OK;
+}
+
+// ============================================================================
+// planner
+// ============================================================================
+
+static int estimate_gram_block(int n_gram) {
+    if (n_gram <= 8) return 2;
+    if (n_gram <= 24) return 4;
+    if (n_gram <= 48) return 6;
+    return 8;
+}
+
+static bool gram_block_ok(int n_gram, int gb) {
+    if (gb != 2 && gb != 4 && gb != 6 && gb != 8) return false;
+    const int ngp = round_up(n_gram, gb);
+    const int nb = ngp / gb;
+    return nb * (nb + 1) / 2 <= kBlock;
+}
+
+// Decompose the batch into views and tables (pushdown + merge).
+static lmfao_status build_logical(lmfao_ctx *c) {
+    Plan &P = c->plan;
+    const int m = (int)c->rels.size();
+    P = Plan();
+    P.parent.assign(m, -1);
+    for (auto &e : c->edges) P.parent[e.second] = e.first;
+    P.children.assign(m, {});
+    for (auto &e : c->edges) P.children[e.first].push_back(e.second);
+    for (int r = 0; r < m; ++r)
+        if (P.parent[r] == -1) P.root = r;
+    P.fk_col.assign(m, -1);
+    P.pk_col.assign(m, -1);
+    P.n_keys.assign(m, 0);
+    for (int r = 0; r < m; ++r) {
+        if (r == P.root) continue;
+        const Rel &Pr = c->rels[P.parent[r]], &C = c->rels[r];
+        for (size_t i = 0; i < C.cols.size(); ++i) {
+            const int pi = Pr.find(C.cols[i].attr);
+            if (pi >= 0) {
+                P.fk_col[r] = pi;
+                P.pk_col[r] = (int)i;
+                P.n_keys[r] = C.cols[i].domain;
+            }
+        }
+    }
+    // heights (levels) and DFS order
+    P.height.assign(m, 0);
+    P.depth.assign(m, 0);
+    std::vector<int> order;
+    std::vector<int> stack{P.root};
+    while (!stack.empty()) {
+        const int r = stack.back();
+        stack.pop_back();
+        order.push_back(r);
+        for (int k = (int)P.children[r].size() - 1; k >= 0; --k) {
+            P.depth[P.children[r][k]] = P.depth[r] + 1;
+            stack.push_back(P.children[r][k]);
+        }
+    }
+    for (int i = (int)order.size() - 1; i >= 0; --i) {
+        const int r = order[i];
+        for (int ch : P.children[r]) P.height[r] = std::max(P.height[r], P.height[ch] + 1);
+    }
+    P.levels = P.height[P.root] + 1;
+
+    // ---- resolve queries: features, components, filters ------------------------------
+    std::set<ARef> feat_set;
+    std::map<std::string, int> comp_ids, filter_ids;
+    struct RQ {
+        std::vector<int> comps;
+        int filter = -1;
+        std::vector<std::vector<std::pair<double, std::vector<ARef>>>> aggs;
+    };
+    std::vector<RQ> rq(c->queries.size());
+    for (size_t qi = 0; qi < c->queries.size(); ++qi) {
+        const Query &Q = c->queries[qi];
+        RQ &R = rq[qi];
+        for (auto &g : Q.gb) {
+            ARef a;
+            find_attr(c, g.attr, a);
+            std::string sig = g.attr + "|";
+            for (float t : g.thr) { char b[32]; snprintf(b, sizeof b, "%a,", (double)t); sig += b; }
+            auto it = comp_ids.find(sig);
+            if (it == comp_ids.end()) {
+                Comp cp;
+                cp.src = a;
+                cp.thr = g.thr;
+                cp.dom = g.thr.empty() ? c->rels[a.rel].cols[a.col].domain : (int)g.thr.size() + 1;
+                it = comp_ids.emplace(sig, (int)P.comps.size()).first;
+                P.comps.push_back(cp);
+            }
+            R.comps.push_back(it->second);
+        }
+        if (!Q.preds.empty()) {
+            std::vector<std::string> parts;
+            std::vector<Conj> conj;
+            for (auto &p : Q.preds) {
+                ARef a;
+                find_attr(c, p.attr, a);
+                char b[96];
+                snprintf(b, sizeof b, "%s|%d|%a", p.attr.c_str(), p.op, p.value);
+                parts.push_back(b);
+                conj.push_back(Conj{a, p.op, p.value});
+            }
+            std::vector<size_t> idx(parts.size());
+            for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+            std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return parts[x] < parts[y]; });
+            std::string sig;
+            std::vector<Conj> sorted;
+            for (size_t i : idx) { sig += parts[i] + ";"; sorted.push_back(conj[i]); }
+            auto it = filter_ids.find(sig);
+            if (it == filter_ids.end()) {
+                if ((int)P.filters.size() >= kMaxFilters)
+                    return fail(c, LMFAO_ERR_TOO_LARGE, "more than 64 distinct WHERE conjunctions");
+                it = filter_ids.emplace(sig, (int)P.filters.size()).first;
+                P.filters.push_back(sorted);
+            }
+            R.filter = it->second;
+        }
+        for (auto &ag : Q.aggs) {
+            std::vector<std::pair<double, std::vector<ARef>>> terms;
+            for (auto &t : ag.terms) {
+                std::vector<ARef> fs;
+                for (auto &f : t.f) {
+                    ARef a;
+                    find_attr(c, f, a);
+                    fs.push_back(a);
+                    feat_set.insert(a);
+                }
+                terms.push_back({t.coeff, fs});
+            }
+            R.aggs.push_back(terms);
+        }
+    }
+    P.n_mask = P.filters.empty() ? 0 : (P.filters.size() <= 32 ? 1 : 2);
+
+    // ---- staged order: DFS over relations, own columns in column order --------------------
+    P.feats.assign(1, ARef{});
+    P.own_feats.assign(m, {});
+    P.own_comps.assign(m, {});
+    P.sub_feat_lo.assign(m, 0);
+    P.sub_feat_n.assign(m, 0);
+    P.sub_comp_lo.assign(m, 0);
+    P.sub_comp_n.assign(m, 0);
+    std::map<ARef, int> feat_id;
+    int comp_slot = 0;
+    // recursive DFS assigning contiguous subtree ranges
+    std::vector<std::pair<int, int>> st;   // (relation, state)
+    std::function<void(int)> visit = [&](int r) {
+        P.sub_feat_lo[r] = (int)P.feats.size();
+        P.sub_comp_lo[r] = comp_slot;
+        for (int col = 0; col < (int)c->rels[r].cols.size(); ++col) {
+            ARef a{r, col};
+            if (feat_set.count(a)) {
+                feat_id[a] = (int)P.feats.size();
+                P.own_feats[r].push_back((int)P.feats.size());
+                P.feats.push_back(a);
+            }
+        }
+        for (size_t ci = 0; ci < P.comps.size(); ++ci)
+            if (P.comps[ci].src.rel == r) {
+                P.comps[ci].slot = comp_slot++;
+                P.own_comps[r].push_back((int)ci);
+            }
+        for (int ch : P.children[r]) visit(ch);
+        P.sub_feat_n[r] = (int)P.feats.size() - P.sub_feat_lo[r];
+        P.sub_comp_n[r] = comp_slot - P.sub_comp_lo[r];
+    };
+    visit(P.root);
+    P.n_feat = (int)P.feats.size();
+    if (P.n_feat > kMaxFeat) return fail(c, LMFAO_ERR_TOO_LARGE, "more than 63 continuous features");
+    if (comp_slot > kMaxComp) return fail(c, LMFAO_ERR_TOO_LARGE, "more than 32 group-by components");
+    P.own_preds.assign(m, {});
+    for (size_t f = 0; f < P.filters.size(); ++f)
+        for (size_t k = 0; k < P.filters[f].size(); ++k) P.own_preds[P.filters[f][k].src.rel].push_back({(int)f, (int)k});
+
+    // ---- outputs: covariance block, tables (merge of same group-by + filter) --------
+    auto mono = [&](const std::vector<ARef> &fs) -> std::pair<int, int> {
+        int a = fs.size() > 0 ? feat_id[fs[0]] : 0;
+        int b = fs.size() > 1 ? feat_id[fs[1]] : 0;
+        if (fs.size() == 1) { b = a; a = 0; }
+        if (a > b) std::swap(a, b);
+        return {a, b};
+    };
+    std::map<std::pair<std::vector<int>, int>, int> table_ids;
+    bool gram_used = false;
+    P.outs.resize(c->queries.size());
+    for (size_t qi = 0; qi < c->queries.size(); ++qi) {
+        RQ &R = rq[qi];
+        Output &O = P.outs[qi];
+        O.n_aggs = (int)R.aggs.size();
+        if (R.comps.empty() && R.filter < 0) {
+            O.gram = true;
+            P.need_count = true;
+            for (int a = 0; a < O.n_aggs; ++a)
+                for (auto &t : R.aggs[a]) {
+                    if (t.second.empty()) O.terms.push_back({a, -1, t.first});
+                    else {
+                        auto mo = mono(t.second);
+                        gram_used = true;
+                        O.terms.push_back({a, mo.first * 1000 + mo.second, t.first});   // resolved below
+                    }
+                }
+        } else {
+            auto key = std::make_pair(R.comps, R.filter);
+            auto it = table_ids.find(key);
+            if (it == table_ids.end()) {
+                Table T;
+                T.comps = R.comps;
+                T.filter = R.filter;
+                for (int ci : R.comps) T.n_cells *= P.comps[ci].dom;
+                it = table_ids.emplace(key, (int)P.tables.size()).first;
+                P.tables.push_back(T);
+            }
+            O.table = it->second;
+            O.n_cells = P.tables[O.table].n_cells;
+            for (int a = 0; a < O.n_aggs; ++a)
+                for (auto &t : R.aggs[a]) {
+                    if (t.second.empty()) O.terms.push_back({a, -1, t.first});
+                    else {
+                        auto mo = mono(t.second);
+                        auto &v = P.tables[O.table].vals;
+                        if (std::find(v.begin(), v.end(), mo) == v.end()) v.push_back(mo);
+                        O.terms.push_back({a, mo.first * 1000 + mo.second, t.first});
+                    }
+                }
+        }
+    }
+    P.n_gram = gram_used ? P.n_feat : 0;
+    for (auto &T : P.tables) std::sort(T.vals.begin(), T.vals.end());
+    for (auto &O : P.outs)
+        for (auto &t : O.terms) {
+            if (t.src < 0) continue;
+            const int a = t.src / 1000, b = t.src % 1000;
+            if (O.gram) t.src = a * P.n_gram + b;
+            else {
+                auto &v = P.tables[O.table].vals;
+                t.src = (int)(std::find(v.begin(), v.end(), std::make_pair(a, b)) - v.begin());
+            }
+        }
+    // ---- families: tables with equal value lists and equal key lists across filters ----
+    std::map<std::pair<std::vector<std::pair<int, int>>, int>, std::vector<int>> by_vf;
+    for (size_t t = 0; t < P.tables.size(); ++t) by_vf[{P.tables[t].vals, P.tables[t].filter}].push_back((int)t);
+    std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, std::vector<int>> fam_of;
+    std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, bool> fam_unf;
+    for (auto &kv : by_vf) {
+        std::vector<std::vector<int>> keys;
+        for (int t : kv.second) keys.push_back(P.tables[t].comps);
+        auto fk = std::make_pair(kv.first.first, keys);
+        if (kv.first.second < 0) {
+            Family F;
+            F.vals = kv.first.first;
+            F.keys = keys;
+            F.tables = kv.second;
+            P.fams.push_back(F);
+        } else {
+            fam_of[fk].push_back(kv.first.second);
+        }
+    }
+    for (auto &kv : fam_of) {
+        Family F;
+        F.vals = kv.first.first;
+        F.keys = kv.first.second;
+        F.filters = kv.second;
+        std::sort(F.filters.begin(), F.filters.end());
+        for (int f : F.filters)
+            for (auto &k : F.keys) {
+                auto &lst = by_vf[{F.vals, f}];
+                int found = -1;
+                for (int t : lst)
+                    if (P.tables[t].comps == k) found = t;
+                F.tables.push_back(found);
+            }
+        P.fams.push_back(F);
+    }
+    P.table_cells = 0;
+    P.table_vals = 0;
+    for (auto &T : P.tables) {
+        T.glb_cnt = P.table_cells;
+        T.glb_val = P.table_vals;
+        P.table_cells += T.n_cells;
+        P.table_vals += T.n_cells * (int64_t)T.vals.size();
+    }
+    // ---- record layouts of non-root relations ------------------------------------------------
+    P.rec_stride.assign(m, 0);
+    P.rec_comp_off.assign(m, 0);
+    P.rec_feat_off.assign(m, 0);
+    for (int r = 0; r < m; ++r) {
+        if (r == P.root) continue;
+        P.rec_comp_off[r] = 1 + P.n_mask;
+        P.rec_feat_off[r] = P.rec_comp_off[r] + P.sub_comp_n[r];
+        P.rec_stride[r] = round_up(P.rec_feat_off[r] + P.sub_feat_n[r], 4);
+    }
+    // ---- statistics (Table 2 analogue) ---------------------------------------------------------
+    P.app_aggs = 0;
+    for (auto &Q : c->queries) P.app_aggs += 1 + (int)Q.aggs.size();
+    P.inter_aggs = 0;
+    for (int r = 0; r < m; ++r)
+        if (r != P.root) P.inter_aggs += 1 + (P.n_mask ? 1 : 0) + P.sub_comp_n[r] + P.sub_feat_n[r];
+    P.views = (m - 1) + (P.n_gram > 0 || P.need_count ? 1 : 0) + (int)P.tables.size();
+    P.groups = m;
+    return LMFAO_OK;
+}
+
+// LDS budget and placement of tables for a tile configuration.
+struct Layout {
+    int lds_xs = 0, ngp = 0, lds_frag = 0, frag_sp = 0, frag_wave_words = 0, lds_tfeat = 0, lds_tcomp = 0, lds_red = 0;
+    int stage_words = 0;
+};
+
+static Layout stage_layout(const Plan &P, int mode, int p1, bool tables, int table_words) {
+    Layout L;
+    int w = table_words;
+    w = round_up(w, 4);
+    int stage = w;
+    int red = 0;
+    if (mode == 1) {
+        L.ngp = round_up(P.n_gram, p1);
+        L.lds_xs = stage;
+        stage += kBlock * L.ngp;
+        red = 2 * L.ngp * L.ngp;
+    } else if (mode >= 2) {
+        const int nt = p1;
+        int sp = round_up(nt * 272, 64) + 16;
+        L.frag_sp = sp;
+        L.frag_wave_words = 4 * sp;
+        L.lds_frag = stage;
+        stage += 4 * L.frag_wave_words;
+        red = (mode == 3 ? 3 : 2) * (16 * nt) * (16 * nt) * 2;
+    }
+    if (tables) {
+        L.lds_tfeat = stage;
+        stage += kBlock * P.n_feat;
+        L.lds_tcomp = stage;
+        stage += kBlock * std::max(1, (int)P.comps.size());
+    }
+    L.lds_red = w;
+    L.stage_words = std::max(stage - w, red);
+    return L;
+}
+
+static int table_words_fit(const lmfao_ctx *c, const Plan &P, int mode, int p1, bool tables) {
+    const Layout L = stage_layout(P, mode, p1, tables, 0);
+    const int limit = (int)(c->lds_limit / 4) - 64;
+    return std::max(0, limit - L.stage_words - 16);
+}
+
+// place tables: policy 0 all global; 1 greedy (small first) into one partition's LDS;
+// 2 split filtered families' filters (or unfiltered tables) over partitions so all fit
+static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_words) {
+    for (auto &T : P.tables) { T.part = 0; T.lds_cnt = T.lds_val = -1; }
+    P.parts = 1;
+    if (P.tables.empty() || policy == 0 || budget_words <= 0) return;
+    if (policy == 1) {
+        std::vector<int> idx(P.tables.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return P.tables[a].words() < P.tables[b].words(); });
+        int used = 0;
+        for (int t : idx) {
+            const int w = P.tables[t].words();
+            if (used + w > budget_words) continue;
+            P.tables[t].lds_cnt = used;
+            P.tables[t].lds_val = used + P.tables[t].val_off();
+            used += w;
+        }
+        return;
+    }
+    // policy 2: units = (family, filter) groups of tables, or single unfiltered tables
+    std::vector<std::vector<int>> units;
+    for (auto &F : P.fams) {
+        const int nk = (int)F.keys.size();
+        if (F.filters.empty()) {
+            for (int t : F.tables) units.push_back({t});
+        } else {
+            for (size_t f = 0; f < F.filters.size(); ++f) {
+                std::vector<int> u;
+                for (int k = 0; k < nk; ++k) u.push_back(F.tables[f * nk + k]);
+                units.push_back(u);
+            }
+        }
+    }
+    std::vector<int> used(kMaxParts, 0);
+    int parts = 1;
+    for (auto &u : units) {
+        int w = 0;
+        for (int t : u) w += P.tables[t].words();
+        if (w > budget_words) {   // too big for any partition: global, evaluated by partition 0
+            continue;
+        }
+        int p = 0;
+        while (p < kMaxParts && used[p] + w > budget_words) ++p;
+        if (p == kMaxParts) continue;
+        for (int t : u) {
+            P.tables[t].part = p;
+            P.tables[t].lds_cnt = used[p];
+            P.tables[t].lds_val = used[p] + P.tables[t].val_off();
+            used[p] += P.tables[t].words();
+        }
+        parts = std::max(parts, p + 1);
+    }
+    P.parts = parts;
+    (void)c;
+}
+
+static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
+    Plan &P = c->plan;
+    const Rel &root = c->rels[P.root];
+    P.cfg = cfg;
+    P.mode = P.n_gram == 0 ? 0 : (P.precision == LMFAO_FP32 ? 1 : (P.precision == LMFAO_BF16X3 ? 2 : 3));
+    P.n_tiles16 = (P.n_gram + 15) / 16;
+    if (P.mode == 1) {
+        int gb = cfg.gram_block > 0 ? cfg.gram_block : estimate_gram_block(P.n_gram);
+        if (!gram_block_ok(P.n_gram, gb)) gb = estimate_gram_block(P.n_gram);
+        if (!gram_block_ok(P.n_gram, gb)) gb = 8;
+        P.gram_block = gb;
+    }
+    const int p1 = P.mode == 1 ? P.gram_block : (P.mode >= 2 ? P.n_tiles16 : 1);
+    const bool has_tables = !P.tables.empty();
+    // table placement
+    int policy = cfg.lds_policy;
+    if (policy < 0) policy = 2;
+    P.lds_policy = has_tables ? policy : 0;
+    const int budget = table_words_fit(c, P, P.mode, p1, has_tables);
+    place_tables(c, P, P.lds_policy, budget);
+    // root launches
+    P.root_launches.clear();
+    auto make_launch = [&](bool with_gram, const std::vector<int> &fams, int single_table) {
+        RootLaunch L;
+        L.with_gram = with_gram;
+        L.mode = with_gram ? P.mode : 0;
+        L.p1 = with_gram ? p1 : 1;
+        L.tables = !fams.empty();
+        L.fam_ids = fams;
+        L.single_table = single_table;
+        int max_words = 0;
+        int parts = 1;
+        if (single_table >= 0) {
+            const Table &T = P.tables[single_table];
+            max_words = T.lds_cnt >= 0 ? T.words() : 0;
+        } else if (L.tables) {
+            std::vector<int> w(kMaxParts, 0);
+            for (auto &T : P.tables)
+                if (T.lds_cnt >= 0) w[T.part] = std::max(w[T.part], T.lds_cnt + T.words());
+            for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, w[p]);
+            parts = P.parts;
+        }
+        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words);
+        L.lds_bytes = (size_t)(round_up(max_words, 4) + Ly.stage_words) * 4;
+        L.parts = parts;
+        // grid: enough workgroups to cover the chip several times, bounded by LDS occupancy
+        const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, kBlock));
+        int occ = (int)std::max<size_t>(1, std::min<size_t>(4, c->lds_limit / std::max<size_t>(L.lds_bytes, 1)));
+        int gx = cfg.grid_x > 0 ? cfg.grid_x : c->n_cu * occ;
+        gx = (int)std::min<int64_t>(gx, blocks_needed);
+        gx = std::max(1, std::min(gx, kGridMax));
+        const int64_t rpb = round_up((int)std::min<int64_t>(ceil_div(root.n_rows, gx), 1 << 30), kBlock);
+        L.grid_x = (int)std::max<int64_t>(1, ceil_div(root.n_rows, std::max<int64_t>(rpb, kBlock)));
+        L.desc.rows_per_block = std::max<int64_t>(rpb, kBlock);
+        return L;
+    };
+    std::vector<int> all_fams;
+    for (size_t f = 0; f < P.fams.size(); ++f) all_fams.push_back((int)f);
+    const bool need_gram_launch = P.n_gram > 0 || P.need_count;
+    if (P.schedule == LMFAO_BATCHED) {
+        P.root_launches.push_back(make_launch(need_gram_launch, all_fams, -1));
+    } else {
+        if (need_gram_launch) P.root_launches.push_back(make_launch(true, {}, -1));
+        for (size_t f = 0; f < P.fams.size(); ++f)
+            for (int t : P.fams[f].tables) P.root_launches.push_back(make_launch(false, {(int)f}, t));
+    }
+    if (P.root_launches.empty()) P.root_launches.push_back(make_launch(false, {}, -1));
+    P.grid_x = P.root_launches[0].grid_x;
+    P.rows_per_block = P.root_launches[0].desc.rows_per_block;
+    for (auto &L : P.root_launches) {
+        if (L.lds_bytes > c->lds_limit) return fail(c, LMFAO_ERR_TOO_LARGE, "root scan exceeds the LDS limit");
+        if (!root_kernel(L.mode, L.p1, L.tables)) return fail(c, LMFAO_ERR_TOO_LARGE, "no kernel variant for this covariance size");
+    }
+    return LMFAO_OK;
+}
+
+// ============================================================================
+// device images: workspace layout, descriptors
+// ============================================================================
+
+struct Blob {
+    std::vector<uint8_t> b;
+    size_t put(const void *p, size_t n) {
+        const size_t off = align_up(b.size(), 16);
+        b.resize(off + n);
+        if (n) memcpy(b.data() + off, p, n);
+        return off;
+    }
+    template <class T> size_t vec(const std::vector<T> &v) { return put(v.data(), v.size() * sizeof(T)); }
+    template <class T> T *at(size_t off) { return reinterpret_cast<T *>(b.data() + off); }
+};
+
+static size_t compute_ws(lmfao_ctx *c) {
+    Plan &P = c->plan;
+    const int m = (int)c->rels.size();
+    size_t o = 0;
+    c->off_err = o;
+    o += kAlign;
+    c->off_rec.assign(m, 0);
+    c->off_seen.assign(m, 0);
+    for (int r = 0; r < m; ++r) {
+        if (r == P.root) continue;
+        c->off_rec[r] = o;
+        o = align_up(o + (size_t)P.n_keys[r] * P.rec_stride[r] * 4);
+        c->off_seen[r] = o;
+        o = align_up(o + (size_t)P.n_keys[r] * 4);
+    }
+    c->off_gcnt = o;
+    o = align_up(o + (size_t)P.table_cells * 8);
+    c->off_gval = o;
+    o = align_up(o + (size_t)P.table_vals * 8);
+    c->off_gpart = o;
+    o = align_up(o + (size_t)kGridMax * P.n_gram * P.n_gram * 8);
+    c->off_cpart = o;
+    o = align_up(o + (size_t)kGridMax * 8);
+    c->off_gram = o;
+    o = align_up(o + (size_t)P.n_gram * P.n_gram * 8 + 8);
+    c->off_count = o;
+    o = align_up(o + 8);
+    c->off_mlp = o;
+    o = align_up(o + ((size_t)1 << 20));
+    c->off_desc = o;
+    return o;   // descriptor blob size added later
+}
+
+static lmfao_status build_blob(lmfao_ctx *c) {
+    Plan &P = c->plan;
+    const int m = (int)c->rels.size();
+    Blob B;
+    uint8_t *ws = c->ws;
+    const size_t dbase = c->off_desc;
+    auto dev = [&](size_t blob_off) -> uint64_t { return (uint64_t)(uintptr_t)(ws + dbase + blob_off); };
+    uint32_t *err = reinterpret_cast<uint32_t *>(ws + c->off_err);
+    // thresholds of components
+    std::vector<size_t> thr_off(P.comps.size(), 0);
+    for (size_t i = 0; i < P.comps.size(); ++i)
+        if (!P.comps[i].thr.empty()) thr_off[i] = B.vec(P.comps[i].thr);
+    auto comp_src = [&](int ci) {
+        const Comp &cp = P.comps[ci];
+        CompSrc s{};
+        s.col = c->rels[cp.src.rel].cols[cp.src.col].data;
+        s.thr = cp.thr.empty() ? nullptr : reinterpret_cast<const float *>(dev(thr_off[ci]));
+        s.nthr = (int)cp.thr.size();
+        s.dom = cp.dom;
+        return s;
+    };
+    auto preds_of = [&](int r) {
+        std::vector<PredSrc> v;
+        for (auto &fp : P.own_preds[r]) {
+            const Conj &cj = P.filters[fp.first][fp.second];
+            const Col &col = c->rels[cj.src.rel].cols[cj.src.col];
+            PredSrc p{};
+            p.col = col.data;
+            p.is_float = col.dtype == LMFAO_F32;
+            p.op = cj.op;
+            p.fval = (float)cj.value;
+            p.ival = (int32_t)cj.value;
+            p.filter = fp.first;
+            v.push_back(p);
+        }
+        return v;
+    };
+    uint64_t filter_all = 0;
+    for (size_t f = 0; f < P.filters.size(); ++f) filter_all |= 1ull << f;
+    auto child_srcs = [&](int r, int feat_base, int comp_base) {
+        std::vector<ChildSrc> v;
+        for (int ch : P.children[r]) {
+            ChildSrc s{};
+            s.fk = static_cast<const int32_t *>(c->rels[r].cols[P.fk_col[ch]].data);
+            s.rec = reinterpret_cast<const uint32_t *>(ws + c->off_rec[ch]);
+            s.n_keys = P.n_keys[ch];
+            s.stride = P.rec_stride[ch];
+            s.n_mask = P.n_mask;
+            s.comp_off = P.rec_comp_off[ch];
+            s.n_comp = P.sub_comp_n[ch];
+            s.comp_dst = P.sub_comp_lo[ch] - comp_base;
+            s.feat_off = P.rec_feat_off[ch];
+            s.n_feat = P.sub_feat_n[ch];
+            s.feat_dst = P.sub_feat_lo[ch] - feat_base;
+            v.push_back(s);
+        }
+        return v;
+    };
+    // ---- view scans of non-root relations, grouped by level ----------------------------
+    c->level_rels.assign(P.levels, {});
+    c->view_desc_off.assign(m, 0);
+    std::vector<ScanDesc> vdescs(m);
+    for (int r = 0; r < m; ++r) {
+        if (r == P.root) continue;
+        c->level_rels[P.height[r]].push_back(r);
+        ScanDesc d{};
+        d.n_rows = c->rels[r].n_rows;
+        std::vector<FeatSrc> fs;
+        for (int f : P.own_feats[r]) {
+            FeatSrc s{};
+            s.col = static_cast<const float *>(c->rels[r].cols[P.feats[f].col].data);
+            s.dst = f - P.sub_feat_lo[r];
+            fs.push_back(s);
+        }
+        std::vector<CompSrc> cs;
+        for (int ci : P.own_comps[r]) {
+            CompSrc s = comp_src(ci);
+            s.dst = P.comps[ci].slot - P.sub_comp_lo[r];
+            cs.push_back(s);
+        }
+        auto ps = preds_of(r);
+        auto chs = child_srcs(r, P.sub_feat_lo[r], P.sub_comp_lo[r]);
+        d.n_feat = (int)fs.size();
+        d.n_comp = (int)cs.size();
+        d.n_pred = (int)ps.size();
+        d.n_child = (int)chs.size();
+        d.n_mask = P.n_mask;
+        d.filter_all = filter_all;
+        d.feats = reinterpret_cast<const FeatSrc *>(dev(B.vec(fs)));
+        d.comps = reinterpret_cast<const CompSrc *>(dev(B.vec(cs)));
+        d.preds = reinterpret_cast<const PredSrc *>(dev(B.vec(ps)));
+        d.children = reinterpret_cast<const ChildSrc *>(dev(B.vec(chs)));
+        d.key = static_cast<const int32_t *>(c->rels[r].cols[P.pk_col[r]].data);
+        d.n_keys = P.n_keys[r];
+        d.rec_stride = P.rec_stride[r];
+        d.rec_comp_off = P.rec_comp_off[r];
+        d.rec_feat_off = P.rec_feat_off[r];
+        d.rec_n_comp = P.sub_comp_n[r];
+        d.rec_n_feat = P.sub_feat_n[r];
+        d.rec_out = reinterpret_cast<uint32_t *>(ws + c->off_rec[r]);
+        d.seen = reinterpret_cast<uint32_t *>(ws + c->off_seen[r]);
+        d.err = err;
+        vdescs[r] = d;
+    }
+    // per level: contiguous arrays of ScanDescs (batched); per relation offsets (plain)
+    std::vector<size_t> level_off(P.levels, 0);
+    for (int L = 0; L < P.levels; ++L) {
+        std::vector<ScanDesc> v;
+        for (int r : c->level_rels[L]) v.push_back(vdescs[r]);
+        level_off[L] = B.vec(v);
+        for (size_t i = 0; i < c->level_rels[L].size(); ++i)
+            c->view_desc_off[c->level_rels[L][i]] = level_off[L] + i * sizeof(ScanDesc);
+    }
+    // ---- root scan ------------------------------------------------------------------------------
+    const int r0 = P.root;
+    std::vector<FeatSrc> rfs;
+    for (int f : P.own_feats[r0]) {
+        FeatSrc s{};
+        s.col = static_cast<const float *>(c->rels[r0].cols[P.feats[f].col].data);
+        s.dst = f;
+        rfs.push_back(s);
+    }
+    std::vector<CompSrc> rcs;
+    for (int ci : P.own_comps[r0]) {
+        CompSrc s = comp_src(ci);
+        s.dst = P.comps[ci].slot;
+        rcs.push_back(s);
+    }
+    auto rps = preds_of(r0);
+    auto rch = child_srcs(r0, 0, 0);
+    if ((int)rch.size() > 8) return fail(c, LMFAO_ERR_TOO_LARGE, "the root relation has more than 8 children");
+    ScanDesc rs{};
+    rs.n_rows = c->rels[r0].n_rows;
+    rs.n_feat = (int)rfs.size();
+    rs.n_comp = (int)rcs.size();
+    rs.n_pred = (int)rps.size();
+    rs.n_child = (int)rch.size();
+    rs.n_mask = P.n_mask;
+    rs.filter_all = filter_all;
+    rs.feats = reinterpret_cast<const FeatSrc *>(dev(B.vec(rfs)));
+    rs.comps = reinterpret_cast<const CompSrc *>(dev(B.vec(rcs)));
+    rs.preds = reinterpret_cast<const PredSrc *>(dev(B.vec(rps)));
+    rs.children = reinterpret_cast<const ChildSrc *>(dev(B.vec(rch)));
+    rs.err = err;
+    // keys and values of all tables
+    std::vector<KeyDesc> keys;
+    std::vector<ValDesc> vals;
+    std::vector<int32_t> fbits;
+    auto add_key = [&](const std::vector<int> &comps) {
+        KeyDesc k{};
+        k.n_comp = (int)comps.size();
+        int64_t stride = 1;
+        for (int i = (int)comps.size() - 1; i >= 0; --i) {
+            k.c[i] = P.comps[comps[i]].slot;
+            k.s[i] = (int32_t)stride;
+            stride *= P.comps[comps[i]].dom;
+        }
+        k.n_cells = (int32_t)stride;
+        keys.push_back(k);
+    };
+    unsigned long long *gcnt = reinterpret_cast<unsigned long long *>(ws + c->off_gcnt);
+    double *gval = reinterpret_cast<double *>(ws + c->off_gval);
+    for (auto &L : P.root_launches) {
+        RootDesc D{};
+        D.scan = rs;
+        D.n_feat = P.n_feat;
+        D.n_gram = L.mode != 0 ? P.n_gram : 0;
+        D.n_comp = (int)P.comps.size();
+        D.n_tfeat = L.tables ? P.n_feat : 0;
+        D.do_count = L.with_gram && P.need_count;
+        D.gram_part = 0;
+        // families of this launch
+        std::vector<FamilyDesc> fdesc;
+        std::vector<TabDesc> tdesc;
+        std::vector<FlushDesc> flushes[kMaxParts];
+        int max_words = 0;
+        std::vector<int> pw(kMaxParts, 0);
+        for (int fi : L.fam_ids) {
+            const Family &F = P.fams[fi];
+            FamilyDesc fd{};
+            fd.unfiltered = F.filters.empty();
+            fd.n_filt = fd.unfiltered ? 1 : (int)F.filters.size();
+            fd.filt_base = (int)fbits.size();
+            for (int f : F.filters) { fbits.push_back(f); fd.filt_mask |= 1ull << f; }
+            fd.val_base = (int)vals.size();
+            for (auto &v : F.vals) vals.push_back(ValDesc{(int16_t)v.first, (int16_t)v.second});
+            fd.n_vals = (int)F.vals.size();
+            fd.tab_base = (int)tdesc.size();
+            fd.key_base = (int)keys.size();
+            if (L.single_table >= 0) {
+                // plain schedule: this launch computes one table, presented as a 1 x 1 family
+                const Table &T = P.tables[L.single_table];
+                add_key(T.comps);
+                fd.n_keys = 1;
+                fd.unfiltered = T.filter < 0;
+                fd.n_filt = 1;
+                fd.filt_mask = T.filter < 0 ? 0 : (1ull << T.filter);
+                fd.filt_base = (int)fbits.size();
+                if (T.filter >= 0) fbits.push_back(T.filter);
+                TabDesc td{};
+                td.part = 0;
+                td.lds_cnt = T.lds_cnt >= 0 ? 0 : -1;
+                td.lds_val = T.lds_cnt >= 0 ? T.val_off() : -1;
+                td.glb_cnt = T.glb_cnt;
+                td.glb_val = T.glb_val;
+                tdesc.push_back(td);
+                fd.part_mask[0] = fd.filt_mask;
+                if (td.lds_cnt >= 0) {
+                    flushes[0].push_back(FlushDesc{0, T.val_off(), (int)T.n_cells, (int)T.vals.size(), T.glb_cnt, T.glb_val});
+                    pw[0] = T.words();
+                }
+            } else {
+                for (auto &k : F.keys) add_key(k);
+                fd.n_keys = (int)F.keys.size();
+                for (size_t i = 0; i < F.tables.size(); ++i) {
+                    const Table &T = P.tables[F.tables[i]];
+                    TabDesc td{};
+                    td.part = T.part;
+                    td.lds_cnt = T.lds_cnt;
+                    td.lds_val = T.lds_val;
+                    td.glb_cnt = T.glb_cnt;
+                    td.glb_val = T.glb_val;
+                    tdesc.push_back(td);
+                    if (T.filter >= 0) fd.part_mask[T.part] |= 1ull << T.filter;
+                    if (T.lds_cnt >= 0) {
+                        flushes[T.part].push_back(FlushDesc{T.lds_cnt, T.lds_val, (int)T.n_cells, (int)T.vals.size(), T.glb_cnt, T.glb_val});
+                        pw[T.part] = std::max(pw[T.part], T.lds_cnt + T.words());
+                    }
+                }
+            }
+            fdesc.push_back(fd);
+        }
+        for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, pw[p]);
+        std::vector<FlushDesc> fl;
+        for (int p = 0; p < kMaxParts; ++p) {
+            D.flush_base[p] = (int)fl.size();
+            D.n_flush[p] = (int)flushes[p].size();
+            D.lds_table_words[p] = pw[p];
+            fl.insert(fl.end(), flushes[p].begin(), flushes[p].end());
+        }
+        D.n_fam = (int)fdesc.size();
+        D.n_parts = L.parts;
+        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words);
+        D.lds_tables = 0;
+        D.lds_xs = Ly.lds_xs;
+        D.ngp = Ly.ngp;
+        D.lds_frag = Ly.lds_frag;
+        D.frag_sp = Ly.frag_sp;
+        D.frag_wave_words = Ly.frag_wave_words;
+        D.lds_tfeat = Ly.lds_tfeat;
+        D.lds_tcomp = Ly.lds_tcomp;
+        D.lds_red = Ly.lds_red;
+        D.rows_per_block = L.desc.rows_per_block;
+        D.fams = reinterpret_cast<const FamilyDesc *>(dev(B.vec(fdesc)));
+        D.tabs = reinterpret_cast<const TabDesc *>(dev(B.vec(tdesc)));
+        D.flush = reinterpret_cast<const FlushDesc *>(dev(B.vec(fl)));
+        D.g_cnt = gcnt;
+        D.g_val = gval;
+        D.gram_partial = reinterpret_cast<double *>(ws + c->off_gpart);
+        D.count_partial = reinterpret_cast<unsigned long long *>(ws + c->off_cpart);
+        D.err = err;
+        L.desc = D;
+    }
+    // keys/vals/filter bits are shared by all root launches: patch pointers after all were appended
+    const size_t keys_off = B.vec(keys), vals_off = B.vec(vals), fb_off = B.vec(fbits);
+    for (auto &L : P.root_launches) {
+        L.desc.keys = reinterpret_cast<const KeyDesc *>(dev(keys_off));
+        L.desc.vals = reinterpret_cast<const ValDesc *>(dev(vals_off));
+        L.desc.filt_bits = reinterpret_cast<const int32_t *>(dev(fb_off));
+        L.desc_off = B.put(&L.desc, sizeof(RootDesc));
+    }
+    // ---- merge and assembly ---------------------------------------------------------------------
+    MergeDesc md{};
+    md.grid = P.root_launches[0].grid_x;
+    for (auto &L : P.root_launches)
+        if (L.with_gram) md.grid = L.grid_x;
+    md.n_gram = P.n_gram;
+    md.gram_partial = reinterpret_cast<const double *>(ws + c->off_gpart);
+    md.count_partial = P.need_count ? reinterpret_cast<const unsigned long long *>(ws + c->off_cpart) : nullptr;
+    md.gram = reinterpret_cast<double *>(ws + c->off_gram);
+    md.count = reinterpret_cast<unsigned long long *>(ws + c->off_count);
+    c->merge_off = B.put(&md, sizeof md);
+    std::vector<OutDesc> outs;
+    std::vector<TermDesc> terms;
+    std::vector<int32_t> tcount;
+    for (auto &O : P.outs) {
+        OutDesc od{};
+        od.kind = O.gram ? SRC_GRAM : SRC_TABLE;
+        od.n_aggs = O.n_aggs;
+        od.n_cells = O.n_cells;
+        od.dst_cnt = (int64_t)(O.cnt_off / 8);
+        od.dst_sum = (int64_t)(O.sum_off / 8);
+        if (!O.gram) {
+            const Table &T = P.tables[O.table];
+            od.src_cnt = T.glb_cnt;
+            od.src_val = T.glb_val;
+            od.src_nvals = (int)T.vals.size();
+        }
+        od.term_base = (int)terms.size();
+        for (auto &t : O.terms) terms.push_back(TermDesc{t.agg, t.src, t.coeff});
+        tcount.push_back((int)O.terms.size());
+        outs.push_back(od);
+    }
+    AssembleDesc ad{};
+    ad.n_out = (int)outs.size();
+    ad.n_gram = P.n_gram;
+    ad.outs = reinterpret_cast<const OutDesc *>(dev(B.vec(outs)));
+    ad.terms = reinterpret_cast<const TermDesc *>(dev(B.vec(terms)));
+    ad.term_count = reinterpret_cast<const int32_t *>(dev(B.vec(tcount)));
+    ad.gram = reinterpret_cast<const double *>(ws + c->off_gram);
+    ad.count = reinterpret_cast<const unsigned long long *>(ws + c->off_count);
+    ad.g_cnt = gcnt;
+    ad.g_val = gval;
+    ad.res_cnt = reinterpret_cast<unsigned long long *>(c->res);
+    ad.res_sum = reinterpret_cast<double *>(c->res);
+    c->assemble_off = B.put(&ad, sizeof ad);
+    // ---- fills: error word, records, seen counters, global tables -----------------------------
+    std::vector<FillDesc> fills;
+    fills.push_back(FillDesc{err, 1});
+    for (int r = 0; r < m; ++r) {
+        if (r == P.root) continue;
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_rec[r]), (int64_t)P.n_keys[r] * P.rec_stride[r]});
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_seen[r]), (int64_t)P.n_keys[r]});
+    }
+    if (P.table_cells) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gcnt), P.table_cells * 2});
+    if (P.table_vals) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gval), P.table_vals * 2});
+    c->n_fills = (int)fills.size();
+    c->fill_off = B.vec(fills);
+    c->blob = std::move(B.b);
+    return LMFAO_OK;
+}
+
+static void layout_results(Plan &P) {
+    size_t o = 0;
+    for (auto &O : P.outs) {
+        O.cnt_off = o;
+        o = align_up(o + (size_t)O.n_cells * 8, 8);
+        O.sum_off = o;
+        o = align_up(o + (size_t)O.n_cells * O.n_aggs * 8, 8);
+    }
+    P.res_bytes = align_up(std::max<size_t>(o, 8));
+}
+
+static lmfao_status do_plan(lmfao_ctx *c, const TileCfg &cfg) {
+    const int precision = c->plan.precision, schedule = c->plan.schedule, planner = c->plan.planner;
+    lmfao_status s = build_logical(c);
+    if (s != LMFAO_OK) return s;
+    c->plan.precision = precision;
+    c->plan.schedule = schedule;
+    c->plan.planner = planner;
+    s = build_physical(c, cfg);
+    if (s != LMFAO_OK) return s;
+    layout_results(c->plan);
+    // workspace: fixed part + an upper bound of the descriptor image
+    const size_t fixed = compute_ws(c);
+    // bound the blob by building it against a null base once
+    uint8_t *save_ws = c->ws, *save_res = c->res;
+    c->ws = nullptr;
+    c->res = nullptr;
+    s = build_blob(c);
+    c->ws = save_ws;
+    c->res = save_res;
+    if (s != LMFAO_OK) return s;
+    c->plan.ws_bytes = align_up(fixed + c->blob.size() + 4096);
+    c->plan.ok = true;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->tree_set) return fail(c, LMFAO_ERR_STATE, "set the join tree first");
+    if (c->queries.empty()) return fail(c, LMFAO_ERR_STATE, "no queries");
+    lmfao_plan_opts o{};
+    o.precision = LMFAO_FP32;
+    o.schedule = LMFAO_BATCHED;
+    o.planner = LMFAO_HEURISTIC;
+    if (opts) o = *opts;
+    if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X4 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
+        o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED)
+        return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
+    invalidate(c);
+    c->opts = o;
+    c->plan.precision = o.precision;
+    c->plan.schedule = o.schedule;
+    c->plan.planner = o.planner;
+    TileCfg cfg;
+    cfg.grid_x = o.grid_blocks;
+    cfg.gram_block = o.gram_block;
+    cfg.lds_policy = -1;
+    return do_plan(c, cfg);
+}
+
+extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
+    if (!c || !s) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    const Plan &P = c->plan;
+    memset(s, 0, sizeof *s);
+    s->app_aggregates = P.app_aggs;
+    s->inter_aggregates = P.inter_aggs;
+    s->views = P.views;
+    s->groups = P.groups;
+    s->levels = P.levels;
+    s->features = P.n_gram;
+    s->filters = (int)P.filters.size();
+    s->tables = (int)P.tables.size();
+    s->table_cells = P.table_cells;
+    int launches = 1;   // fill
+    for (int L = 0; L < P.levels - 1; ++L) {
+        int nrel = 0;
+        for (int r = 0; r < (int)c->rels.size(); ++r)
+            if (r != P.root && P.height[r] == L) ++nrel;
+        launches += P.schedule == LMFAO_BATCHED ? (nrel > 0) : nrel;
+    }
+    launches += (int)P.root_launches.size();
+    if (P.n_gram > 0 || P.need_count) launches += 1;
+    launches += 1;   // assemble
+    s->launches = launches;
+    s->block_rows = kBlock;
+    s->grid_blocks = P.grid_x;
+    s->gram_block = P.mode == 1 ? P.gram_block : (P.mode >= 2 ? 16 * P.n_tiles16 : 0);
+    s->lds_tables = P.lds_policy;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_workspace_size(const lmfao_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    *bytes = c->plan.ws_bytes;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_result_size(const lmfao_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    *bytes = c->plan.res_bytes;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_result_layout(const lmfao_ctx *c, int32_t qid, int64_t *n_cells, int32_t *n_sums,
+                                            size_t *counts_off, size_t *sums_off) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (qid < 0 || qid >= (int)c->plan.outs.size()) return fail(const_cast<lmfao_ctx *>(c), LMFAO_ERR_INVALID_ARG, "bad query id");
+    const Output &O = c->plan.outs[qid];
+    if (n_cells) *n_cells = O.n_cells;
+    if (n_sums) *n_sums = O.n_aggs;
+    if (counts_off) *counts_off = O.cnt_off;
+    if (sums_off) *sums_off = O.sum_off;
+    return LMFAO_OK;
+}
+
+static lmfao_status upload(lmfao_ctx *c) {
+    lmfao_status s = build_blob(c);
+    if (s != LMFAO_OK) return s;
+    if (c->off_desc + c->blob.size() > c->ws_len) return fail(c, LMFAO_ERR_WORKSPACE, "workspace too small for descriptors");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_desc, c->blob.data(), c->blob.size(), hipMemcpyHostToDevice));
+    for (auto &L : c->plan.root_launches) {
+        RootKernel k = root_kernel(L.mode, L.p1, L.tables);
+        if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_root_lds_limit(k, L.lds_bytes));
+    }
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_bind(lmfao_ctx *c, void *workspace, size_t ws_bytes, void *results, size_t res_bytes) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "plan before binding");
+    if (!c->has_device) return fail(c, LMFAO_ERR_HIP, "no HIP device");
+    if (!workspace || !results) return fail(c, LMFAO_ERR_WORKSPACE, "null buffer");
+    if (((uintptr_t)workspace % kAlign) || ((uintptr_t)results % 8))
+        return fail(c, LMFAO_ERR_WORKSPACE, "workspace must be 256-byte aligned, results 8-byte aligned");
+    if (ws_bytes < c->plan.ws_bytes || res_bytes < c->plan.res_bytes)
+        return fail(c, LMFAO_ERR_WORKSPACE, "bound buffers are smaller than required");
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    if (c->graph_def) { (void)hipGraphDestroy(c->graph_def); c->graph_def = nullptr; }
+    c->ws = static_cast<uint8_t *>(workspace);
+    c->ws_len = ws_bytes;
+    c->res = static_cast<uint8_t *>(results);
+    c->res_len = res_bytes;
+    compute_ws(c);
+    lmfao_status s = upload(c);
+    if (s != LMFAO_OK) return s;
+    c->bound = true;
+    c->executed = false;
+    return LMFAO_OK;
+}
+
+// ============================================================================
+// execution
+// ============================================================================
+
+static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
+    for (auto &L : c->plan.root_launches) {
+        RootKernel k = root_kernel(L.mode, L.p1, L.tables);
+        HIP_TRY(c, launch_root(k, reinterpret_cast<const RootDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x, L.parts,
+                               L.lds_bytes, st));
+    }
+    return LMFAO_OK;
+}
+
+static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
+    Plan &P = c->plan;
+    uint8_t *db = c->ws + c->off_desc;
+    HIP_TRY(c, launch_fill(db + c->fill_off, c->n_fills, st));
+    for (int L = 0; L + 1 < P.levels; ++L) {
+        const auto &rels = c->level_rels[L];
+        if (rels.empty()) continue;
+        if (P.schedule == LMFAO_BATCHED) {
+            int64_t mx = 0;
+            for (int r : rels) mx = std::max(mx, c->rels[r].n_rows);
+            HIP_TRY(c, launch_views(reinterpret_cast<const ScanDesc *>(db + c->view_desc_off[rels[0]]), (int)rels.size(), mx, st));
+        } else {
+            for (int r : rels)
+                HIP_TRY(c, launch_views(reinterpret_cast<const ScanDesc *>(db + c->view_desc_off[r]), 1, c->rels[r].n_rows, st));
+        }
+    }
+    lmfao_status s = enqueue_root(c, st);
+    if (s != LMFAO_OK) return s;
+    if (P.n_gram > 0 || P.need_count)
+        HIP_TRY(c, launch_merge(reinterpret_cast<const MergeDesc *>(db + c->merge_off), P.n_gram, st));
+    HIP_TRY(c, launch_assemble(reinterpret_cast<const AssembleDesc *>(db + c->assemble_off), (int)P.outs.size(), st));
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_execute(lmfao_ctx *c, void *hip_stream) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before executing");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    c->last_stream = st;
+    c->executed = true;
+    if (c->plan.schedule == LMFAO_BATCHED && st != nullptr) {
+        if (c->graph && c->graph_stream != st) {
+            (void)hipGraphExecDestroy(c->graph);
+            c->graph = nullptr;
+            (void)hipGraphDestroy(c->graph_def);
+            c->graph_def = nullptr;
+        }
+        if (!c->graph) {
+            HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            lmfao_status s = enqueue_all(c, st);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &g);
+            if (s != LMFAO_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+            if (e != hipSuccess) return fail(c, LMFAO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            c->graph_def = g;
+            HIP_TRY(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+            c->graph_stream = st;
+        }
+        HIP_TRY(c, hipGraphLaunch(c->graph, st));
+        return LMFAO_OK;
+    }
+    return enqueue_all(c, st);
+}
+
+extern "C" lmfao_status lmfao_sync(lmfao_ctx *c) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->executed) return fail(c, LMFAO_ERR_STATE, "nothing executed");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->last_stream) HIP_TRY(c, hipStreamSynchronize(c->last_stream));
+    else HIP_TRY(c, hipDeviceSynchronize());
+    uint32_t flags = 0;
+    HIP_TRY(c, hipMemcpy(&flags, c->ws + c->off_err, 4, hipMemcpyDeviceToHost));
+    if (flags & kErrDomain) return fail(c, LMFAO_ERR_DOMAIN, "a categorical code lies outside its domain");
+    if (flags & kErrKeyRange) return fail(c, LMFAO_ERR_DOMAIN, "a child key lies outside [0, domain)");
+    if (flags & kErrDupKey) return fail(c, LMFAO_ERR_UNSUPPORTED, "a child relation has a duplicate join key");
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_time_root_group(lmfao_ctx *c, void *hip_stream, int32_t warmup, int32_t reps, double *ms) {
+    if (!c || !ms || reps <= 0 || warmup < 0) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound || !c->executed) return fail(c, LMFAO_ERR_STATE, "execute once before timing");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (int i = 0; i < warmup; ++i) {
+        lmfao_status s = enqueue_root(c, st);
+        if (s != LMFAO_OK) return s;
+    }
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    HIP_TRY(c, hipEventCreate(&b));
+    HIP_TRY(c, hipEventRecord(a, st));
+    for (int i = 0; i < reps; ++i) {
+        lmfao_status s = enqueue_root(c, st);
+        if (s != LMFAO_OK) return s;
+    }
+    HIP_TRY(c, hipEventRecord(b, st));
+    HIP_TRY(c, hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = (double)t / reps;
+    c->last_stream = st;
+    return LMFAO_OK;
+}
+
+// ============================================================================
+// candidates, autotuner, learned choice
+// ============================================================================
+
+static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
+    const Plan &P = c->plan;
+    std::vector<TileCfg> out;
+    std::vector<int> grids;
+    for (int g : {256, 512, 1024, 2048}) grids.push_back(g * c->n_cu / 256);
+    std::vector<int> gbs{0};
+    if (P.mode == 1) {
+        gbs.clear();
+        for (int gb : {2, 4, 6, 8})
+            if (gram_block_ok(P.n_gram, gb)) gbs.push_back(gb);
+    }
+    std::vector<int> pols{0};
+    if (!P.tables.empty()) pols = {0, 1, 2};
+    for (int g : grids)
+        for (int gb : gbs)
+            for (int pl : pols) {
+                TileCfg t;
+                t.grid_x = g;
+                t.gram_block = gb;
+                t.lds_policy = pl;
+                out.push_back(t);
+            }
+    return out;
+}
+
+extern "C" lmfao_status lmfao_candidates(const lmfao_ctx *c, int32_t *n) {
+    if (!c || !n) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    *n = (int32_t)enumerate_candidates(c).size();
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t cfg[4]) {
+    if (!c || !cfg) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    auto v = enumerate_candidates(c);
+    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    cfg[0] = kBlock;
+    cfg[1] = v[i].grid_x;
+    cfg[2] = v[i].gram_block;
+    cfg[3] = v[i].lds_policy;
+    return LMFAO_OK;
+}
+
+static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
+    const Plan &P = c->plan;
+    const double rows = (double)c->rels[P.root].n_rows;
+    int64_t child_keys = 0;
+    for (int r = 0; r < (int)c->rels.size(); ++r)
+        if (r != P.root) child_keys += P.n_keys[r];
+    double upd = 0.0;   // table updates per row (filtered tables counted at half)
+    for (auto &T : P.tables) upd += (T.filter < 0 ? 1.0 : 0.5) * (1.0 + (double)T.vals.size());
+    const int mode = P.n_gram == 0 ? 0 : (P.precision == LMFAO_FP32 ? 1 : (P.precision == LMFAO_BF16X3 ? 2 : 3));
+    f[0] = (float)std::log2(rows + 1.0);
+    f[1] = (float)P.n_gram;
+    f[2] = (float)(P.n_gram * P.n_gram) / 64.f;
+    f[3] = (float)P.children[P.root].size();
+    f[4] = (float)P.comps.size();
+    f[5] = (float)std::log2((double)P.tables.size() + 1.0);
+    f[6] = (float)std::log2((double)P.table_cells + 1.0);
+    f[7] = (float)std::log2(upd + 1.0);
+    f[8] = (float)P.filters.size();
+    f[9] = (float)t.lds_policy;
+    f[10] = (float)std::log2((double)std::max(1, t.grid_x));
+    f[11] = (float)(mode == 1 ? t.gram_block : 0);
+    f[12] = (float)mode;
+    f[13] = (float)std::log2((double)child_keys + 1.0);
+    f[14] = (float)std::log2(rows * (double)std::max(1, P.n_feat) * 4.0 + 1.0);
+    f[15] = (float)P.n_feat;
+}
+
+extern "C" lmfao_status lmfao_candidate_features(const lmfao_ctx *c, int32_t i, float *features) {
+    if (!c || !features) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    auto v = enumerate_candidates(c);
+    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    features_of(c, v[i], features);
+    return LMFAO_OK;
+}
+
+static lmfao_status select_cfg(lmfao_ctx *c, const TileCfg &t) {
+    const bool was_bound = c->bound;
+    uint8_t *ws = c->ws, *res = c->res;
+    const size_t wl = c->ws_len, rl = c->res_len;
+    invalidate(c);
+    lmfao_status s = do_plan(c, t);
+    if (s != LMFAO_OK) return s;
+    if (was_bound && ws && c->plan.ws_bytes <= wl && c->plan.res_bytes <= rl) {
+        s = lmfao_bind(c, ws, wl, res, rl);
+        if (s != LMFAO_OK) return s;
+    }
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_select_candidate(lmfao_ctx *c, int32_t i) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    auto v = enumerate_candidates(c);
+    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    return select_cfg(c, v[i]);
+}
+
+extern "C" lmfao_status lmfao_autotune(lmfao_ctx *c, void *hip_stream, const char *timing_db, int32_t reps, int32_t *best) {
+    if (!c || reps <= 0) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before autotuning");
+    auto cands = enumerate_candidates(c);
+    std::FILE *db = timing_db ? std::fopen(timing_db, "a") : nullptr;
+    double best_ms = 1e300;
+    int best_i = -1;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        lmfao_status s = select_cfg(c, cands[i]);
+        if (s != LMFAO_OK || !c->bound) continue;   // a candidate that does not fit is skipped
+        s = lmfao_execute(c, hip_stream);
+        if (s == LMFAO_OK) s = lmfao_sync(c);
+        double ms = 0.0;
+        if (s == LMFAO_OK) s = lmfao_time_root_group(c, hip_stream, 1, reps, &ms);
+        if (s != LMFAO_OK) continue;
+        if (db) {
+            float f[LMFAO_N_FEATURES];
+            features_of(c, cands[i], f);
+            for (int k = 0; k < LMFAO_N_FEATURES; ++k) std::fprintf(db, "%.6g,", f[k]);
+            std::fprintf(db, "%d,%d,%d,%.6f\n", cands[i].grid_x, cands[i].gram_block, cands[i].lds_policy, ms);
+        }
+        if (ms < best_ms) { best_ms = ms; best_i = (int)i; }
+    }
+    if (db) std::fclose(db);
+    if (best_i < 0) return fail(c, LMFAO_ERR_HIP, "no candidate ran");
+    lmfao_status s = select_cfg(c, cands[best_i]);
+    if (s != LMFAO_OK) return s;
+    if (best) *best = best_i;
+    return LMFAO_OK;
+}
+
+// weights file: "LMFAOMLP" | int32 hidden | float mean[16] | float std[16] | float y_mean | float y_std | params
+static bool load_weights(const char *path, int &hidden, std::vector<float> &norm, std::vector<float> &params) {
+    std::ifstream in(path, std::ios::binary);
+    if (!in) return false;
+    char magic[8];
+    in.read(magic, 8);
+    if (!in || memcmp(magic, "LMFAOMLP", 8) != 0) return false;
+    int32_t h = 0;
+    in.read(reinterpret_cast<char *>(&h), 4);
+    if (!in || h <= 0 || h > 1024) return false;
+    norm.resize(2 * LMFAO_N_FEATURES + 2);
+    in.read(reinterpret_cast<char *>(norm.data()), norm.size() * 4);
+    const int np = lmfao_mlp_param_count(h);
+    params.resize(np);
+    in.read(reinterpret_cast<char *>(params.data()), (size_t)np * 4);
+    if (!in) return false;
+    hidden = h;
+    return true;
+}
+
+extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, void *hip_stream, int32_t *best) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (best) *best = -1;
+    int hidden = 0;
+    std::vector<float> norm, params;
+    if (!weights || !load_weights(weights, hidden, norm, params)) return LMFAO_OK;   // heuristic stays
+    auto cands = enumerate_candidates(c);
+    const int n = (int)cands.size();
+    std::vector<float> x((size_t)n * LMFAO_N_FEATURES);
+    for (int i = 0; i < n; ++i) {
+        features_of(c, cands[i], &x[(size_t)i * LMFAO_N_FEATURES]);
+        for (int k = 0; k < LMFAO_N_FEATURES; ++k) {
+            float &v = x[(size_t)i * LMFAO_N_FEATURES + k];
+            v = (v - norm[k]) / (norm[LMFAO_N_FEATURES + k] > 0.f ? norm[LMFAO_N_FEATURES + k] : 1.f);
+        }
+    }
+    const size_t need = (params.size() + x.size() + n) * 4;
+    if (need > ((size_t)1 << 20)) return fail(c, LMFAO_ERR_TOO_LARGE, "cost model too large for its scratch");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    float *dp = reinterpret_cast<float *>(c->ws + c->off_mlp);
+    float *dx = dp + params.size();
+    float *dy = dx + x.size();
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(dp, params.data(), params.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, mlp_forward_dev(hidden, dp, dx, n, dy, st));
+    std::vector<float> y(n);
+    HIP_TRY(c, hipMemcpyAsync(y.data(), dy, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    int bi = -1;
+    float bv = 0.f;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(y[i])) return LMFAO_OK;   // fall back to the heuristic
+        if (bi < 0 || y[i] < bv) { bi = i; bv = y[i]; }
+    }
+    if (bi < 0) return LMFAO_OK;
+    lmfao_status s = select_cfg(c, cands[bi]);
+    if (s != LMFAO_OK) return s;
+    if (best) *best = bi;
+    return LMFAO_OK;
+}

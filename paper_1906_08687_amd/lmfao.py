@@ -1,0 +1,381 @@
+"""Thin Python binding of ``liblmfao.so`` (ctypes): argument marshalling only.
+
+Every step of the evaluation runs in the library's HIP kernels; PyTorch is
+used to hold device memory (columns, workspace, results) and streams.  The
+binding refuses to run without the compiled library: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblmfao.so")
+
+OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "NOT_ACYCLIC", -3: "UNKNOWN_ATTR", -4: "TYPE", -5: "DOMAIN", -6: "TOO_LARGE",
+          -7: "WORKSPACE", -8: "STATE", -9: "HIP", -10: "UNSUPPORTED"}
+I32, F32 = 0, 1
+KEY, CONT, CAT = 0, 1, 2
+OPS = {"le": 0, "lt": 1, "ge": 2, "gt": 3, "eq": 4, "ne": 5}
+PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x4": 2}
+SCHEDULE = {"plain": 0, "batched": 1}
+PLANNER = {"heuristic": 0, "autotune": 1, "learned": 2}
+N_FEATURES = 16
+
+
+class LmfaoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (ERRORS.get(status, str(status)), msg))
+        self.status = status
+        self.code = ERRORS.get(status, str(status))
+
+
+class _Col(ctypes.Structure):
+    _fields_ = [("attr", ctypes.c_char_p), ("dtype", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("domain", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
+class _GroupBy(ctypes.Structure):
+    _fields_ = [("attr", ctypes.c_char_p), ("n_thresholds", ctypes.c_int32), ("thresholds", ctypes.c_void_p)]
+
+
+class _Pred(ctypes.Structure):
+    _fields_ = [("attr", ctypes.c_char_p), ("op", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class _Term(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("n_factors", ctypes.c_int32), ("factors", ctypes.c_char_p * 2)]
+
+
+class _Agg(ctypes.Structure):
+    _fields_ = [("n_terms", ctypes.c_int32), ("terms", ctypes.POINTER(_Term))]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("n_groupby", ctypes.c_int32), ("groupby", ctypes.POINTER(_GroupBy)),
+                ("n_preds", ctypes.c_int32), ("preds", ctypes.POINTER(_Pred)),
+                ("n_aggs", ctypes.c_int32), ("aggs", ctypes.POINTER(_Agg))]
+
+
+class _PlanOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("planner", ctypes.c_int32),
+                ("block_rows", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32),
+                ("cost_model", ctypes.c_char_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("app_aggregates", ctypes.c_int32), ("inter_aggregates", ctypes.c_int32),
+                ("views", ctypes.c_int32), ("groups", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("features", ctypes.c_int32), ("filters", ctypes.c_int32), ("tables", ctypes.c_int32),
+                ("table_cells", ctypes.c_int64), ("launches", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32)]
+
+
+# every symbol the header declares
+SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relation", "lmfao_set_join_tree",
+           "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_workspace_size", "lmfao_result_size",
+           "lmfao_result_layout", "lmfao_bind", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
+           "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
+           "lmfao_autotune", "lmfao_choose_learned", "lmfao_mlp_param_count", "lmfao_mlp_forward",
+           "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the compiled engine; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("liblmfao.so is not built (run __graft_entry__.build()); "
+                          "the engine has no fallback path")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    st = ctypes.c_int32
+    sig = {
+        "lmfao_create": (st, [ctypes.POINTER(P), i32]),
+        "lmfao_destroy": (None, [P]),
+        "lmfao_last_error": (ctypes.c_char_p, [P]),
+        "lmfao_add_relation": (st, [P, ctypes.c_char_p, i64, i32, P, ctypes.POINTER(i32)]),
+        "lmfao_set_join_tree": (st, [P, i32, P]),
+        "lmfao_add_query": (st, [P, ctypes.POINTER(_Query), ctypes.POINTER(i32)]),
+        "lmfao_plan": (st, [P, ctypes.POINTER(_PlanOpts)]),
+        "lmfao_plan_stats": (st, [P, ctypes.POINTER(_Stats)]),
+        "lmfao_workspace_size": (st, [P, ctypes.POINTER(sz)]),
+        "lmfao_result_size": (st, [P, ctypes.POINTER(sz)]),
+        "lmfao_result_layout": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz),
+                                     ctypes.POINTER(sz)]),
+        "lmfao_bind": (st, [P, P, sz, P, sz]),
+        "lmfao_execute": (st, [P, P]),
+        "lmfao_sync": (st, [P]),
+        "lmfao_time_root_group": (st, [P, P, i32, i32, ctypes.POINTER(ctypes.c_double)]),
+        "lmfao_candidates": (st, [P, ctypes.POINTER(i32)]),
+        "lmfao_candidate": (st, [P, i32, P]),
+        "lmfao_candidate_features": (st, [P, i32, P]),
+        "lmfao_select_candidate": (st, [P, i32]),
+        "lmfao_autotune": (st, [P, P, ctypes.c_char_p, i32, ctypes.POINTER(i32)]),
+        "lmfao_choose_learned": (st, [P, ctypes.c_char_p, P, ctypes.POINTER(i32)]),
+        "lmfao_mlp_param_count": (i32, [i32]),
+        "lmfao_mlp_scratch_floats": (i64, [i32, i32]),
+        "lmfao_mlp_forward": (st, [i32, P, P, i32, P, P]),
+        "lmfao_mlp_loss_grad": (st, [i32, P, P, P, i32, P, P, P, P]),
+        "lmfao_adam_step": (st, [i32, P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, P]),
+        "lmfao_mlp_train": (st, [i32, P, P, P, P, P, i32, i32, ctypes.c_float, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return int(stream.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+@dataclass
+class QueryResult:
+    counts: np.ndarray          # uint64 [n_cells]
+    sums: np.ndarray            # float64 [n_cells, n_aggs]
+
+
+class Context:
+    """One engine context over a database whose columns live on the device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.ptr = ctypes.c_void_p()
+        self._check(self.lib.lmfao_create(ctypes.byref(self.ptr), device))
+        self.device = device
+        self._keep: list = []
+        self.n_queries = 0
+
+    def close(self):
+        if self.ptr:
+            self.lib.lmfao_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, status: int):
+        if status != OK:
+            msg = self.lib.lmfao_last_error(self.ptr) if self.ptr else b""
+            raise LmfaoError(status, (msg or b"").decode())
+
+    # ---- relations, tree, queries --------------------------------------------------
+    def add_relation(self, name: str, n_rows: int, cols: Sequence[tuple]) -> int:
+        """cols: (attr, dtype, kind, domain, device pointer)."""
+        arr = (_Col * len(cols))()
+        for i, (attr, dtype, kind, domain, ptr) in enumerate(cols):
+            b = attr.encode()
+            self._keep.append(b)
+            arr[i] = _Col(b, dtype, kind, domain, ptr)
+        rid = ctypes.c_int32()
+        self._check(self.lib.lmfao_add_relation(self.ptr, name.encode(), n_rows, len(cols), arr, ctypes.byref(rid)))
+        return rid.value
+
+    def set_join_tree(self, edges: Sequence[tuple]):
+        flat = (ctypes.c_int32 * max(1, 2 * len(edges)))(*[v for e in edges for v in e])
+        self._check(self.lib.lmfao_set_join_tree(self.ptr, len(edges), flat))
+
+    def add_query(self, q) -> int:
+        keep = self._keep
+        gbs = (_GroupBy * max(1, len(q.groupby)))()
+        for i, g in enumerate(q.groupby):
+            b = g.attr.encode()
+            keep.append(b)
+            if g.thresholds is not None:
+                th = np.ascontiguousarray(g.thresholds, np.float32)
+                keep.append(th)
+                gbs[i] = _GroupBy(b, len(th), th.ctypes.data)
+            else:
+                gbs[i] = _GroupBy(b, 0, None)
+        preds = (_Pred * max(1, len(q.where)))()
+        for i, p in enumerate(q.where):
+            b = p.attr.encode()
+            keep.append(b)
+            preds[i] = _Pred(b, OPS[p.op], float(p.value))
+        aggs = (_Agg * max(1, len(q.aggs)))()
+        for i, a in enumerate(q.aggs):
+            terms = (_Term * max(1, len(a.terms)))()
+            for j, (coeff, facs) in enumerate(a.terms):
+                names = (ctypes.c_char_p * 2)()
+                for k, f in enumerate(facs):
+                    b = f.encode()
+                    keep.append(b)
+                    names[k] = b
+                terms[j] = _Term(float(coeff), len(facs), names)
+            keep.append(terms)
+            aggs[i] = _Agg(len(a.terms), terms)
+        keep.extend([gbs, preds, aggs])
+        Q = _Query(len(q.groupby), gbs, len(q.where), preds, len(q.aggs), aggs)
+        qid = ctypes.c_int32()
+        self._check(self.lib.lmfao_add_query(self.ptr, ctypes.byref(Q), ctypes.byref(qid)))
+        self.n_queries += 1
+        return qid.value
+
+    # ---- planning --------------------------------------------------------------------
+    def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0):
+        o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None)
+        self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        self._check(self.lib.lmfao_plan_stats(self.ptr, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+    def workspace_size(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(self.lib.lmfao_workspace_size(self.ptr, ctypes.byref(v)))
+        return v.value
+
+    def result_size(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(self.lib.lmfao_result_size(self.ptr, ctypes.byref(v)))
+        return v.value
+
+    def result_layout(self, qid: int):
+        n, a, co, so = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.lmfao_result_layout(self.ptr, qid, ctypes.byref(n), ctypes.byref(a), ctypes.byref(co),
+                                                 ctypes.byref(so)))
+        return n.value, a.value, co.value, so.value
+
+    def bind(self, ws_ptr: int, ws_bytes: int, res_ptr: int, res_bytes: int):
+        self._check(self.lib.lmfao_bind(self.ptr, ws_ptr, ws_bytes, res_ptr, res_bytes))
+
+    def execute(self, stream=None):
+        self._check(self.lib.lmfao_execute(self.ptr, _stream_handle(stream)))
+
+    def sync(self):
+        self._check(self.lib.lmfao_sync(self.ptr))
+
+    def time_root_group(self, stream=None, warmup=2, reps=10) -> float:
+        ms = ctypes.c_double()
+        self._check(self.lib.lmfao_time_root_group(self.ptr, _stream_handle(stream), warmup, reps, ctypes.byref(ms)))
+        return ms.value
+
+    def candidates(self) -> List[List[int]]:
+        n = ctypes.c_int32()
+        self._check(self.lib.lmfao_candidates(self.ptr, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            cfg = (ctypes.c_int32 * 4)()
+            self._check(self.lib.lmfao_candidate(self.ptr, i, cfg))
+            out.append(list(cfg))
+        return out
+
+    def candidate_features(self, i: int) -> np.ndarray:
+        f = np.zeros(N_FEATURES, np.float32)
+        self._check(self.lib.lmfao_candidate_features(self.ptr, i, f.ctypes.data))
+        return f
+
+    def select_candidate(self, i: int):
+        self._check(self.lib.lmfao_select_candidate(self.ptr, i))
+
+    def autotune(self, stream=None, timing_db: Optional[str] = None, reps: int = 3) -> int:
+        best = ctypes.c_int32()
+        self._check(self.lib.lmfao_autotune(self.ptr, _stream_handle(stream), timing_db.encode() if timing_db else None,
+                                            reps, ctypes.byref(best)))
+        return best.value
+
+    def choose_learned(self, weights: str, stream=None) -> int:
+        best = ctypes.c_int32()
+        self._check(self.lib.lmfao_choose_learned(self.ptr, weights.encode(), _stream_handle(stream),
+                                                  ctypes.byref(best)))
+        return best.value
+
+
+class Engine:
+    """Evaluate a query batch over a ``datagen.Database`` on one GPU.
+
+    Columns are copied to the device once (load time is outside every
+    measurement, as in the paper's protocol); the workspace and result arena
+    are torch tensors bound to the context.
+    """
+
+    def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
+                 grid_blocks=0, gram_block=0, columns=None):
+        import torch
+        self.torch = torch
+        self.db = db
+        self.queries = list(queries)
+        self.dev = torch.device("cuda", device)
+        self.ctx = Context(device)
+        self.cols = columns if columns is not None else upload_columns(db, self.dev)
+        for r in db.relations:
+            spec = []
+            for c in r.columns:
+                t = self.cols[(r.name, c.attr)]
+                dtype = F32 if c.kind == "cont" else I32
+                kind = {"key": KEY, "cont": CONT, "cat": CAT}[c.kind]
+                spec.append((c.attr, dtype, kind, int(c.domain), _ptr(t)))
+            self.ctx.add_relation(r.name, r.n_rows, spec)
+        self.ctx.set_join_tree(db.edges)
+        for q in self.queries:
+            self.ctx.add_query(q)
+        self.precision, self.schedule = precision, schedule
+        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block)
+        self._bind()
+
+    def _bind(self):
+        torch = self.torch
+        self.ws_bytes = self.ctx.workspace_size()
+        self.res_bytes = self.ctx.result_size()
+        if not hasattr(self, "ws") or self.ws.numel() < self.ws_bytes + 256:
+            # slack so that other tile candidates (autotuner, cost model) bind in place
+            self.ws = torch.empty(self.ws_bytes + (4 << 20), dtype=torch.uint8, device=self.dev)
+        if not hasattr(self, "res") or self.res.numel() < self.res_bytes:
+            self.res = torch.empty(self.res_bytes, dtype=torch.uint8, device=self.dev)
+        base = _ptr(self.ws)
+        self.ws_base = (base + 255) // 256 * 256
+        self.ctx.bind(self.ws_base, self.ws.numel() - (self.ws_base - base), _ptr(self.res), self.res.numel())
+
+    def replan(self, precision=None, schedule=None, planner="heuristic", grid_blocks=0, gram_block=0):
+        self.precision = precision or self.precision
+        self.schedule = schedule or self.schedule
+        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block)
+        self._bind()
+
+    def run(self, stream=None):
+        self.ctx.execute(stream)
+        self.ctx.sync()
+
+    def results(self) -> List[QueryResult]:
+        host = self.res.cpu().numpy()
+        out = []
+        for qid in range(len(self.queries)):
+            n, a, co, so = self.ctx.result_layout(qid)
+            counts = host[co:co + 8 * n].view(np.uint64).copy()
+            sums = host[so:so + 8 * n * a].view(np.float64).reshape(n, a).copy()
+            out.append(QueryResult(counts, sums))
+        return out
+
+    def stats(self) -> dict:
+        return self.ctx.stats()
+
+
+def upload_columns(db, dev):
+    import torch
+    out = {}
+    for r in db.relations:
+        for c in r.columns:
+            out[(r.name, c.attr)] = torch.from_numpy(np.ascontiguousarray(c.data)).to(dev)
+    return out

@@ -1,0 +1,155 @@
+"""Parity of the HIP engine (through the C ABI) with the CPU oracle.
+
+Counts are compared bit for bit.  Sums use the tolerance rule of
+tests/helpers.check_sums: 1e-6 for the fp32 covariance form (fp64 merge),
+1e-5 for the bf16 hi+lo split forms.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from datagen import Agg, Column, Database, GroupBy, Pred, Query, Relation, make_batch, make_database
+from tests.helpers import check_sums
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"fp32": 1e-6, "bf16x3": 1e-5, "bf16x4": 1e-5}
+
+
+def _engine(db, qs, **kw):
+    from paper_1906_08687_amd.lmfao import Engine
+    return Engine(db, qs, **kw)
+
+
+def compare(got, ref, queries, rtol, what):
+    worst = (0.0, 0.0)
+    for i, (g, r, q) in enumerate(zip(got, ref, queries)):
+        assert g.counts.shape == r.counts.shape, (what, i)
+        if not np.array_equal(g.counts, r.counts):
+            bad = np.argwhere(g.counts != r.counts).ravel()[:5]
+            raise AssertionError("%s query %d: counts differ at cells %s: got %s ref %s" %
+                                 (what, i, bad, g.counts[bad], r.counts[bad]))
+        if q.aggs:
+            s, n = check_sums(g.sums, r.sums, r.abs_sums, rtol, "%s query %d" % (what, i))
+            worst = (max(worst[0], s), max(worst[1], n))
+    return worst
+
+
+_cache = {}
+
+
+def _workload(k):
+    if k not in _cache:
+        db = make_database(k)
+        qs = make_batch(k, db)
+        _cache[k] = (db, qs, oracle.evaluate(db, qs))
+    return _cache[k]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_parity_batched(k, precision):
+    if k in (3, 5) and precision != "fp32":
+        pytest.skip("no covariance block in this workload")
+    db, qs, ref = _workload(k)
+    print("case: workload %d %s batched" % (k, precision), flush=True)
+    eng = _engine(db, qs, precision=precision, schedule="batched")
+    eng.run()
+    compare(eng.results(), ref, qs, RTOL[precision], "workload %d %s" % (k, precision))
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_parity_plain_schedule(k):
+    db, qs, ref = _workload(k)
+    print("case: workload %d fp32 plain" % k, flush=True)
+    eng = _engine(db, qs, precision="fp32", schedule="plain")
+    eng.run()
+    compare(eng.results(), ref, qs, RTOL["fp32"], "workload %d plain" % k)
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_parity_bf16x4(k):
+    db, qs, ref = _workload(k)
+    print("case: workload %d bf16x4" % k, flush=True)
+    eng = _engine(db, qs, precision="bf16x4")
+    eng.run()
+    compare(eng.results(), ref, qs, RTOL["bf16x4"], "workload %d bf16x4" % k)
+
+
+def test_repeat_runs_bitwise_counts_and_graph_replay():
+    import torch
+    db, qs, ref = _workload(2)
+    eng = _engine(db, qs, precision="bf16x3", schedule="batched")
+    s = torch.cuda.Stream()
+    first = None
+    for rep in range(3):
+        eng.ctx.execute(s)   # captured into a hipGraph on the first call, replayed afterwards
+        eng.ctx.sync()
+        res = eng.results()
+        compare(res, ref, qs, RTOL["bf16x3"], "replay %d" % rep)
+        if first is None:
+            first = res
+        else:
+            for a, b in zip(first, res):
+                assert np.array_equal(a.counts, b.counts)
+        torch.cuda.synchronize()
+
+
+def test_tile_candidates_all_agree():
+    db, qs, ref = _workload(1)
+    eng = _engine(db, qs, precision="fp32")
+    for i, cfg in enumerate(eng.ctx.candidates()):
+        eng.ctx.select_candidate(i)
+        eng.run()
+        compare(eng.results(), ref, qs, RTOL["fp32"], "candidate %s" % cfg)
+
+
+def _tiny_star(dup=False, bad_code=False):
+    F = Relation("F", [Column("k", "key", np.array([0, 1, 2, 1, 5, 3], np.int32), 4),
+                       Column("x", "cont", np.array([1, 2, 3, 4, 5, 6], np.float32))])
+    keys = np.array([0, 1, 2, 2] if dup else [0, 1, 2, 3], np.int32)
+    codes = np.array([0, 1, 7 if bad_code else 1, 0], np.int32)
+    D = Relation("D", [Column("k", "key", keys, 4), Column("c", "cat", codes, 2),
+                       Column("y", "cont", np.array([0.5, 1.5, 2.5, 3.5], np.float32))])
+    return Database([F, D], [(0, 1)])
+
+
+def test_dangling_keys_drop_rows():
+    """Fact keys with no dimension row (5 is outside the key domain) do not
+    join: natural-join semantics."""
+    db = _tiny_star()
+    qs = [Query(), Query(aggs=[Agg.monomial("x", "y")]), Query([GroupBy("c")], [], [Agg.monomial("x")]),
+          Query([], [Pred("y", "gt", 1.0)], [Agg.monomial("x")])]
+    ref = oracle.evaluate(db, qs)
+    eng = _engine(db, qs)
+    eng.run()
+    compare(eng.results(), ref, qs, 1e-6, "dangling")
+    assert int(eng.results()[0].counts[0]) == 5
+
+
+def test_device_errors_surface_at_sync():
+    from paper_1906_08687_amd.lmfao import LmfaoError
+    qs = [Query([GroupBy("c")], [], [])]
+    eng = _engine(_tiny_star(dup=True), qs)
+    eng.ctx.execute()
+    with pytest.raises(LmfaoError) as e:
+        eng.ctx.sync()
+    assert e.value.code == "UNSUPPORTED"
+    eng = _engine(_tiny_star(bad_code=True), qs)
+    eng.ctx.execute()
+    with pytest.raises(LmfaoError) as e:
+        eng.ctx.sync()
+    assert e.value.code == "DOMAIN"
+
+
+def test_empty_fact_and_empty_result_cells():
+    db = make_database(1, n_fact=0)
+    qs = make_batch(1, db)
+    ref = oracle.evaluate(db, qs)
+    eng = _engine(db, qs)
+    eng.run()
+    compare(eng.results(), ref, qs, 1e-6, "empty fact")
+    assert int(eng.results()[0].counts[0]) == 0

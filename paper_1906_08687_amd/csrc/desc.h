@@ -44,6 +44,8 @@ struct CompSrc {          // group-by component of the scanned relation -> stage
     int32_t nthr;         // 0: categorical code
     int32_t dom;          // domain of the cell index
     int32_t dst;
+    int32_t aux;          // root scan: LDS column holding this attribute; thresholds at thr_lds
+    int32_t thr_lds;      // root scan: word offset of the thresholds in the block's LDS copy
     int32_t pad;
 };
 
@@ -54,7 +56,7 @@ struct PredSrc {          // one conjunct 1[X op t] of filter `filter`
     float fval;
     int32_t ival;
     int32_t filter;
-    int32_t pad;
+    int32_t aux;          // root scan: LDS column holding this attribute
 };
 
 struct ChildSrc {         // a child view gathered through a foreign key of the scanned relation
@@ -65,7 +67,7 @@ struct ChildSrc {         // a child view gathered through a foreign key of the 
     int32_t n_mask;       // mask words carried by the child record
     int32_t comp_off, n_comp, comp_dst;
     int32_t feat_off, n_feat, feat_dst;
-    int32_t pad;
+    int32_t quad_base;    // root scan: first 16-byte quad of this child in the record buffer
 };
 
 struct ScanDesc {
@@ -132,30 +134,47 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
     uint64_t part_mask[kMaxParts];   // filter bits whose tables belong to each partition
 };
 
+constexpr int kColPitch = 68;     // words per 64-row LDS column (64 rows + 4 words of bank padding)
+constexpr int kMaxWaves = 4;      // waves per workgroup of the root scan
+
 struct RootDesc {
     ScanDesc scan;
     int32_t n_feat;       // staged features (feature 0 = constant 1)
     int32_t n_gram;       // covariance block over features [0, n_gram); 0 = none
     int32_t n_comp;       // staged components
-    int32_t n_tfeat;      // features [0, n_tfeat) are read by table values
     int32_t n_fam;
     int32_t do_count;     // accumulate the total count
     int32_t n_parts;      // table partitions (grid.y)
     int32_t gram_part;    // partition whose workgroups compute the covariance block and count
-    // dynamic LDS layout, 32-bit word offsets
-    int32_t lds_tables;   // table storage (size lds_table_words[part])
-    int32_t lds_xs;       // fp32 covariance tile [kBlock][ngp]
-    int32_t ngp;          // row pitch of the fp32 tile
-    int32_t lds_frag;     // bf16 fragments, per wave frag_wave_words
-    int32_t frag_sp;      // words between (k-step, hi/lo) fragment blocks
-    int32_t frag_wave_words;
-    int32_t lds_tfeat;    // fp32 table features [kBlock][n_tfeat]
-    int32_t lds_tcomp;    // int32 components [kBlock][n_comp]
-    int32_t lds_red;      // fp64 reduction scratch (aliases the staging area at the end)
+    int32_t ngp;          // fp32 covariance: features padded to the register block
+    // staged feature order: 0 = constant, [1, 1 + n_fact) fact columns, then child subtrees
+    int32_t n_fact;       // fact features (copied straight into LDS columns)
+    int32_t n_aux;        // fact columns read by components and predicates
+    int32_t n_quads;      // 16-byte record quads over all children
+    int32_t nbuf;         // 1 or 2 staging buffers per wave (2: the next tile loads during this one)
+    // dynamic LDS layout (32-bit words)
+    int32_t lds_tables;   // table storage (lds_table_words[part] words)
+    int32_t lds_consts;   // a column of ones and a column of zeros (64 words each)
+    int32_t lds_thr;      // thresholds of fact components
+    int32_t lds_wave;     // first wave region; wave w at lds_wave + w * wave_words
+    int32_t wave_words;
+    int32_t w_fact;       // wave-relative: nbuf x n_fact columns
+    int32_t w_aux;        // wave-relative: nbuf x n_aux columns
+    int32_t w_rec;        // wave-relative: nbuf x n_quads x 64 quads (row-major records)
+    int32_t w_comp;       // wave-relative: component columns (tables only)
+    int32_t lds_red;      // fp64 reduction scratch at the end (aliases the wave regions)
+    int32_t n_thr_words;  // thresholds copied to LDS
     int32_t pad0;
     int32_t lds_table_words[kMaxParts];
     int32_t flush_base[kMaxParts], n_flush[kMaxParts];
-    int64_t rows_per_block;    // contiguous rows per workgroup (multiple of kBlock)
+    int64_t rows_per_block;    // contiguous rows per workgroup (multiple of 64 * waves)
+    const float *const *fact_cols;    // [n_fact] fact feature columns, staged order
+    const float *const *aux_cols;     // [n_aux] fact columns (as 32-bit words)
+    const int32_t *feat_src;          // [n_feat] child feature f: word offset in one record
+                                      // buffer (rows 4 words apart); fact feature: -1 - column
+    const int32_t *comp_src;          // [n_comp] child component: record word offset; fact: -1
+    const float *thr_all;             // [n_thr_words] thresholds of fact components
+    const uint32_t *zero_rec;         // a record of zeros (count 0) for keys without a row
     const FamilyDesc *fams;
     const KeyDesc *keys;
     const ValDesc *vals;

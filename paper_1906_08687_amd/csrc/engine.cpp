@@ -50,7 +50,8 @@ typedef void (*RootKernel)(const RootDesc *);
 RootKernel root_kernel(int mode, int p1, bool tables);
 hipError_t launch_fill(const void *fills, int n, hipStream_t st);
 hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hipStream_t st);
-hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st);
+hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, int waves, size_t lds_bytes,
+                       hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
 hipError_t launch_assemble(const AssembleDesc *desc, int n_out, hipStream_t st);
@@ -63,6 +64,7 @@ using namespace lmfao;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxRecWords = 128;   // largest view record (the zero record stands in for missing keys)
 constexpr int kGridMax = 2048;
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -164,6 +166,7 @@ struct Output {
 };
 
 struct TileCfg {
+    int waves = 0;          // waves per workgroup of the root scan (0 = heuristic)
     int grid_x = 0;         // requested workgroups (0 = heuristic)
     int gram_block = 0;     // fp32 register block edge
     int lds_policy = -1;    // 0 global tables, 1 greedy LDS, 2 partitioned LDS (-1 = heuristic)
@@ -172,7 +175,7 @@ struct TileCfg {
 struct RootLaunch {         // one launch of the root scan (batched: one; plain: one per view)
     int mode = 0, p1 = 1;
     bool tables = false;
-    int grid_x = 1, parts = 1;
+    int grid_x = 1, parts = 1, waves = 2;
     size_t lds_bytes = 0;
     RootDesc desc;           // pointers filled at bind
     std::vector<int> fam_ids;        // families evaluated (plain: one table view)
@@ -213,7 +216,7 @@ struct Plan {
     // schedule
     int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
     TileCfg cfg;                      // chosen tile configuration
-    int gram_block = 4, n_tiles16 = 1, mode = 0, lds_policy = 0, parts = 1;
+    int gram_block = 4, n_tiles16 = 1, mode = 0, lds_policy = 0, parts = 1, nbuf = 2, waves = 2;
     int grid_x = 1;
     int64_t rows_per_block = kBlock;
     std::vector<RootLaunch> root_launches;
@@ -244,7 +247,7 @@ struct lmfao_ctx {
     bool bound = false;
     // device layout (offsets into ws)
     size_t off_err = 0, off_gcnt = 0, off_gval = 0, off_gpart = 0, off_cpart = 0, off_gram = 0, off_count = 0;
-    size_t off_desc = 0, off_mlp = 0;
+    size_t off_desc = 0, off_mlp = 0, off_zero = 0;
     std::vector<size_t> off_rec, off_seen;
     std::vector<uint8_t> blob;       // descriptor image copied to ws + off_desc
     size_t fill_off = 0;
@@ -493,7 +496,7 @@ extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int3
 static int estimate_gram_block(int n_gram) {
     if (n_gram <= 8) return 2;
     if (n_gram <= 24) return 4;
-    if (n_gram <= 48) return 6;
+    if (n_gram <= 36) return 6;
     return 8;
 }
 
@@ -501,7 +504,7 @@ static bool gram_block_ok(int n_gram, int gb) {
     if (gb != 2 && gb != 4 && gb != 6 && gb != 8) return false;
     const int ngp = round_up(n_gram, gb);
     const int nb = ngp / gb;
-    return nb * (nb + 1) / 2 <= kBlock;
+    return nb * (nb + 1) / 2 <= 64;   // block pairs are spread over the 64 lanes of a wave
 }
 
 // Decompose the batch into views and tables (pushdown + merge).
@@ -777,6 +780,7 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         P.rec_comp_off[r] = 1 + P.n_mask;
         P.rec_feat_off[r] = P.rec_comp_off[r] + P.sub_comp_n[r];
         P.rec_stride[r] = round_up(P.rec_feat_off[r] + P.sub_feat_n[r], 4);
+        if (P.rec_stride[r] > kMaxRecWords) return fail(c, LMFAO_ERR_TOO_LARGE, "view record of " + c->rels[r].name + " too wide");
     }
     // ---- statistics (Table 2 analogue) ---------------------------------------------------------
     P.app_aggs = 0;
@@ -789,47 +793,63 @@ static lmfao_status build_logical(lmfao_ctx *c) {
     return LMFAO_OK;
 }
 
-// LDS budget and placement of tables for a tile configuration.
+// LDS layout of the root scan for a tile configuration (32-bit words).
 struct Layout {
-    int lds_xs = 0, ngp = 0, lds_frag = 0, frag_sp = 0, frag_wave_words = 0, lds_tfeat = 0, lds_tcomp = 0, lds_red = 0;
-    int stage_words = 0;
+    int n_fact = 0, n_aux = 0, n_quads = 0, nbuf = 2, waves = 2;
+    int w_fact = 0, w_aux = 0, w_rec = 0, w_comp = 0, wave_words = 0;
+    int lds_consts = 0, lds_thr = 0, lds_wave = 0, lds_red = 0, thr_words = 0, ngp = 0;
+    int total = 0;
 };
 
-static Layout stage_layout(const Plan &P, int mode, int p1, bool tables, int table_words) {
+static int root_aux_count(const Plan &P) {
+    std::set<int> cols;
+    for (int ci : P.own_comps[P.root]) cols.insert(P.comps[ci].src.col);
+    for (auto &fp : P.own_preds[P.root]) cols.insert(P.filters[fp.first][fp.second].src.col);
+    return (int)cols.size();
+}
+
+static Layout stage_layout(const Plan &P, int mode, int p1, bool tables, int table_words, int nbuf, int waves) {
     Layout L;
-    int w = table_words;
+    L.nbuf = nbuf;
+    L.waves = waves;
+    L.n_fact = (int)P.own_feats[P.root].size();
+    L.n_aux = root_aux_count(P);
+    for (int ch : P.children[P.root]) L.n_quads += P.rec_stride[ch] / 4;
+    int w = 0;
+    L.w_fact = w;
+    w += nbuf * L.n_fact * kColPitch;
+    L.w_aux = w;
+    w += nbuf * L.n_aux * kColPitch;
     w = round_up(w, 4);
-    int stage = w;
+    L.w_rec = w;
+    w += nbuf * L.n_quads * 256;
+    L.w_comp = w;
+    if (tables) w += (int)P.comps.size() * 64;
+    L.wave_words = round_up(w, 4);
+    for (int ci : P.own_comps[P.root]) L.thr_words += (int)P.comps[ci].thr.size();
+    int o = round_up(table_words, 4);
+    L.lds_consts = o;
+    o += 128;
+    L.lds_thr = o;
+    o += round_up(L.thr_words, 4);
+    L.lds_wave = o;
+    o += waves * L.wave_words;
+    L.lds_red = L.lds_wave;
     int red = 0;
     if (mode == 1) {
         L.ngp = round_up(P.n_gram, p1);
-        L.lds_xs = stage;
-        stage += kBlock * L.ngp;
         red = 2 * L.ngp * L.ngp;
     } else if (mode >= 2) {
-        const int nt = p1;
-        int sp = round_up(nt * 272, 64) + 16;
-        L.frag_sp = sp;
-        L.frag_wave_words = 4 * sp;
-        L.lds_frag = stage;
-        stage += 4 * L.frag_wave_words;
-        red = (mode == 3 ? 3 : 2) * (16 * nt) * (16 * nt) * 2;
+        red = (mode == 3 ? 3 : 2) * (16 * p1) * (16 * p1) * 2;
     }
-    if (tables) {
-        L.lds_tfeat = stage;
-        stage += kBlock * P.n_feat;
-        L.lds_tcomp = stage;
-        stage += kBlock * std::max(1, (int)P.comps.size());
-    }
-    L.lds_red = w;
-    L.stage_words = std::max(stage - w, red);
+    L.total = std::max(o, L.lds_red + red);
     return L;
 }
 
-static int table_words_fit(const lmfao_ctx *c, const Plan &P, int mode, int p1, bool tables) {
-    const Layout L = stage_layout(P, mode, p1, tables, 0);
+static int table_words_fit(const lmfao_ctx *c, const Plan &P, int mode, int p1, bool tables, int nbuf, int waves) {
+    const Layout L = stage_layout(P, mode, p1, tables, 0, nbuf, waves);
     const int limit = (int)(c->lds_limit / 4) - 64;
-    return std::max(0, limit - L.stage_words - 16);
+    return std::max(0, limit - L.total - 16);
 }
 
 // place tables: policy 0 all global; 1 greedy (small first) into one partition's LDS;
@@ -907,7 +927,24 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     int policy = cfg.lds_policy;
     if (policy < 0) policy = 2;
     P.lds_policy = has_tables ? policy : 0;
-    const int budget = table_words_fit(c, P, P.mode, p1, has_tables);
+    // waves per workgroup and staging buffers: the most resident waves per CU
+    // (LDS-limited), two buffers when they fit next to the tables
+    {
+        const size_t lds_cu = 160 * 1024;
+        int best = -1;
+        for (int nb : {2, 1})
+            for (int wv : {4, 2, 1}) {
+                if (cfg.waves > 0 && wv != cfg.waves) continue;
+                const Layout Ly = stage_layout(P, P.mode, p1, has_tables, 0, nb, wv);
+                const size_t bytes = (size_t)Ly.total * 4 + 1024;
+                if (bytes > c->lds_limit) continue;
+                const int per_cu = (int)std::min<size_t>(8 / wv, lds_cu / bytes) * wv;
+                const int score = per_cu * 4 + (nb == 2 ? 2 : 0) + (wv >= 2 ? 1 : 0);
+                if (score > best) { best = score; P.nbuf = nb; P.waves = wv; }
+            }
+        if (best < 0) { P.nbuf = 1; P.waves = 1; }
+    }
+    const int budget = table_words_fit(c, P, P.mode, p1, has_tables, P.nbuf, P.waves);
     place_tables(c, P, P.lds_policy, budget);
     // root launches
     P.root_launches.clear();
@@ -931,18 +968,20 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, w[p]);
             parts = P.parts;
         }
-        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words);
-        L.lds_bytes = (size_t)(round_up(max_words, 4) + Ly.stage_words) * 4;
+        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
+        L.lds_bytes = (size_t)Ly.total * 4;
         L.parts = parts;
-        // grid: enough workgroups to cover the chip several times, bounded by LDS occupancy
-        const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, kBlock));
-        int occ = (int)std::max<size_t>(1, std::min<size_t>(4, c->lds_limit / std::max<size_t>(L.lds_bytes, 1)));
-        int gx = cfg.grid_x > 0 ? cfg.grid_x : c->n_cu * occ;
+        L.waves = P.waves;
+        // grid: enough workgroups to cover the chip twice at its LDS-limited residency
+        const int tile = 64 * P.waves;
+        const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, tile));
+        const int occ = (int)std::max<size_t>(1, std::min<size_t>(8 / P.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
+        int gx = cfg.grid_x > 0 ? cfg.grid_x : 2 * c->n_cu * occ;
         gx = (int)std::min<int64_t>(gx, blocks_needed);
         gx = std::max(1, std::min(gx, kGridMax));
-        const int64_t rpb = round_up((int)std::min<int64_t>(ceil_div(root.n_rows, gx), 1 << 30), kBlock);
-        L.grid_x = (int)std::max<int64_t>(1, ceil_div(root.n_rows, std::max<int64_t>(rpb, kBlock)));
-        L.desc.rows_per_block = std::max<int64_t>(rpb, kBlock);
+        const int64_t rpb = round_up((int)std::min<int64_t>(ceil_div(root.n_rows, gx), 1 << 30), tile);
+        L.grid_x = (int)std::max<int64_t>(1, ceil_div(root.n_rows, std::max<int64_t>(rpb, tile)));
+        L.desc.rows_per_block = std::max<int64_t>(rpb, tile);
         return L;
     };
     std::vector<int> all_fams;
@@ -1008,6 +1047,8 @@ static size_t compute_ws(lmfao_ctx *c) {
     o = align_up(o + (size_t)P.n_gram * P.n_gram * 8 + 8);
     c->off_count = o;
     o = align_up(o + 8);
+    c->off_zero = o;
+    o = align_up(o + 4 * kMaxRecWords);
     c->off_mlp = o;
     o = align_up(o + ((size_t)1 << 20));
     c->off_desc = o;
@@ -1136,15 +1177,60 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         s.dst = f;
         rfs.push_back(s);
     }
+    // fact columns read by components and predicates are copied into LDS columns ("aux")
+    std::vector<int> aux_cols;
+    auto aux_of = [&](int col) {
+        for (size_t i = 0; i < aux_cols.size(); ++i)
+            if (aux_cols[i] == col) return (int)i;
+        aux_cols.push_back(col);
+        return (int)aux_cols.size() - 1;
+    };
+    std::vector<float> thr_all;
     std::vector<CompSrc> rcs;
     for (int ci : P.own_comps[r0]) {
         CompSrc s = comp_src(ci);
         s.dst = P.comps[ci].slot;
+        s.aux = aux_of(P.comps[ci].src.col);
+        s.thr_lds = (int)thr_all.size();
+        thr_all.insert(thr_all.end(), P.comps[ci].thr.begin(), P.comps[ci].thr.end());
         rcs.push_back(s);
     }
     auto rps = preds_of(r0);
+    {
+        size_t k = 0;
+        for (auto &fp : P.own_preds[r0]) rps[k++].aux = aux_of(P.filters[fp.first][fp.second].src.col);
+    }
     auto rch = child_srcs(r0, 0, 0);
     if ((int)rch.size() > 8) return fail(c, LMFAO_ERR_TOO_LARGE, "the root relation has more than 8 children");
+    {
+        int qb = 0;
+        for (auto &ch : rch) { ch.quad_base = qb; qb += ch.stride / 4; }
+    }
+    // where each staged feature / component of a tile lives: fact column j (-1 - j) or a
+    // word of the row-major record buffer ((quad_base + w / 4) * 256 + w % 4)
+    std::vector<int32_t> feat_src(std::max(1, P.n_feat), 0), comp_map(std::max<size_t>(1, P.comps.size()), -1);
+    for (size_t j = 0; j < P.own_feats[r0].size(); ++j) feat_src[P.own_feats[r0][j]] = -1 - (int)j;
+    for (size_t k = 0; k < P.children[r0].size(); ++k) {
+        const int ch = P.children[r0][k];
+        for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
+            const int w = P.rec_feat_off[ch] + i;
+            feat_src[P.sub_feat_lo[ch] + i] = (rch[k].quad_base + w / 4) * 256 + w % 4;
+        }
+        for (int i = 0; i < P.sub_comp_n[ch]; ++i) {
+            const int w = P.rec_comp_off[ch] + i;
+            comp_map[P.sub_comp_lo[ch] + i] = (rch[k].quad_base + w / 4) * 256 + w % 4;
+        }
+    }
+    const size_t feat_src_off = B.vec(feat_src), comp_src_off = B.vec(comp_map);
+    std::vector<uint64_t> fact_ptrs;
+    for (int f : P.own_feats[r0]) fact_ptrs.push_back((uint64_t)(uintptr_t)c->rels[r0].cols[P.feats[f].col].data);
+    if (fact_ptrs.empty()) fact_ptrs.push_back(0);
+    const size_t fact_cols_off = B.vec(fact_ptrs);
+    std::vector<uint64_t> aux_ptrs;
+    for (int col : aux_cols) aux_ptrs.push_back((uint64_t)(uintptr_t)c->rels[r0].cols[col].data);
+    const size_t aux_off = B.vec(aux_ptrs);
+    if (thr_all.empty()) thr_all.push_back(0.f);
+    const size_t thr_all_off = B.vec(thr_all);
     ScanDesc rs{};
     rs.n_rows = c->rels[r0].n_rows;
     rs.n_feat = (int)rfs.size();
@@ -1182,7 +1268,6 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         D.n_feat = P.n_feat;
         D.n_gram = L.mode != 0 ? P.n_gram : 0;
         D.n_comp = (int)P.comps.size();
-        D.n_tfeat = L.tables ? P.n_feat : 0;
         D.do_count = L.with_gram && P.need_count;
         D.gram_part = 0;
         // families of this launch
@@ -1256,16 +1341,29 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         }
         D.n_fam = (int)fdesc.size();
         D.n_parts = L.parts;
-        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words);
-        D.lds_tables = 0;
-        D.lds_xs = Ly.lds_xs;
+        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
         D.ngp = Ly.ngp;
-        D.lds_frag = Ly.lds_frag;
-        D.frag_sp = Ly.frag_sp;
-        D.frag_wave_words = Ly.frag_wave_words;
-        D.lds_tfeat = Ly.lds_tfeat;
-        D.lds_tcomp = Ly.lds_tcomp;
+        D.n_fact = Ly.n_fact;
+        D.n_aux = Ly.n_aux;
+        D.n_quads = Ly.n_quads;
+        D.nbuf = Ly.nbuf;
+        D.lds_tables = 0;
+        D.lds_consts = Ly.lds_consts;
+        D.lds_thr = Ly.lds_thr;
+        D.lds_wave = Ly.lds_wave;
+        D.wave_words = Ly.wave_words;
+        D.w_fact = Ly.w_fact;
+        D.w_aux = Ly.w_aux;
+        D.w_rec = Ly.w_rec;
+        D.w_comp = Ly.w_comp;
         D.lds_red = Ly.lds_red;
+        D.n_thr_words = Ly.thr_words;
+        D.fact_cols = reinterpret_cast<const float *const *>(dev(fact_cols_off));
+        D.feat_src = reinterpret_cast<const int32_t *>(dev(feat_src_off));
+        D.comp_src = reinterpret_cast<const int32_t *>(dev(comp_src_off));
+        D.aux_cols = reinterpret_cast<const float *const *>(dev(aux_off));
+        D.thr_all = reinterpret_cast<const float *>(dev(thr_all_off));
+        D.zero_rec = reinterpret_cast<const uint32_t *>(ws + c->off_zero);
         D.rows_per_block = L.desc.rows_per_block;
         D.fams = reinterpret_cast<const FamilyDesc *>(dev(B.vec(fdesc)));
         D.tabs = reinterpret_cast<const TabDesc *>(dev(B.vec(tdesc)));
@@ -1333,6 +1431,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     // ---- fills: error word, records, seen counters, global tables -----------------------------
     std::vector<FillDesc> fills;
     fills.push_back(FillDesc{err, 1});
+    fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_zero), kMaxRecWords});
     for (int r = 0; r < m; ++r) {
         if (r == P.root) continue;
         fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_rec[r]), (int64_t)P.n_keys[r] * P.rec_stride[r]});
@@ -1509,7 +1608,7 @@ static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
     for (auto &L : c->plan.root_launches) {
         RootKernel k = root_kernel(L.mode, L.p1, L.tables);
         HIP_TRY(c, launch_root(k, reinterpret_cast<const RootDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x, L.parts,
-                               L.lds_bytes, st));
+                               L.waves, L.lds_bytes, st));
     }
     return LMFAO_OK;
 }

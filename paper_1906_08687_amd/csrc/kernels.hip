@@ -39,6 +39,26 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxChild = 8;
 
+// Address-space views.  Descriptor arrays are read through the constant
+// space (scalar loads that wait on lgkmcnt only); per-lane data and atomics
+// go through the global space.  Generic (flat) accesses would count against
+// both wait counters and serialise the asynchronous LDS copies.
+#define AS_GLOBAL __attribute__((address_space(1)))
+#define AS_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const AS_CONST T *cst(const T *p) { return (const AS_CONST T *)p; }
+template <class T>
+__device__ __forceinline__ const AS_GLOBAL T *gld(const T *p) { return (const AS_GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ AS_GLOBAL T *gst(T *p) { return (AS_GLOBAL T *)p; }
+template <class T>
+__device__ __forceinline__ void gadd(T *p, T v) {
+    __hip_atomic_fetch_add(gst(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gor(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_or(gst(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // fills (used instead of memset nodes so the sequence can live in a graph)
 // ---------------------------------------------------------------------------
@@ -164,32 +184,87 @@ __device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
     s = t;
 }
 
-__device__ __forceinline__ void two_sum_acc4(f32x4 &s, f32x4 &e, f32x4 x) {
-    const f32x4 t = s + x;
-    const f32x4 bp = t - s;
-    e += (s - (t - bp)) + (x - bp);
-    s = t;
-}
-
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// bf16 fragment layout of one wave (64 rows = two 32-row k-steps):
-// dword((kstep*2 + part) * frag_sp + tile*272 + group*68 + feat*4 + slot/2)
-// holds rows 8*group + slot, slot+1 of feature 16*tile + feat; part 0 = hi, 1 = lo.
-constexpr int kTileWords = 272;
-constexpr int kGroupWords = 68;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void;
 
+// Asynchronous global -> LDS copies (no registers): every lane's 4 or 16
+// bytes land at lds_base + lane * size.  lds_base must be wave-uniform.
+__device__ __forceinline__ void lds_dma4(const void *g, uint32_t *lds_base) {
+    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds_base, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_dma16(const void *g, uint32_t *lds_base) {
+    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds_base, 16, 0, 0);
+}
+
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), both round-to-nearest-even
+__device__ __forceinline__ void split_bf16x8(const float *x, bf16x8 &hi, bf16x8 &lo) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f32x2 v = {x[2 * i], x[2 * i + 1]};
+        const bf16x2 hb = __builtin_convertvector(v, bf16x2);
+        const f32x2 hf = __builtin_convertvector(hb, f32x2);
+        const bf16x2 lb = __builtin_convertvector(v - hf, bf16x2);
+        h[i] = __builtin_bit_cast(uint32_t, hb);
+        l[i] = __builtin_bit_cast(uint32_t, lb);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+constexpr int kFlushTiles = 16;   // mfma accumulators fold into fp32 sums every 16 tiles (1024 rows per wave)
+
+// Where a staged feature of a tile lives in LDS: word(row) = base + buf * step + row * stride.
+struct FeatLoc {
+    int base, step, stride;
+};
+
+// f: staged feature; src: its feat_src entry; wave: the wave region's first word
+__device__ __forceinline__ FeatLoc feat_loc(const RootDesc &d, int f, int src, int wave) {
+    if (f == 0) return {d.lds_consts, 0, 1};                 // constant 1
+    if (f >= d.n_feat) return {d.lds_consts + 64, 0, 1};     // padding feature 0
+    if (src >= 0) return {wave + d.w_rec + src, d.n_quads * 256, 4};   // child record word
+    return {wave + d.w_fact + (-1 - src) * kColPitch, d.n_fact * kColPitch, 1};
+}
+
+// Root multi-output scan.  Every wave owns a contiguous share of its
+// workgroup's rows and walks it in 64-row tiles, one row per lane:
+//   * the tile's fact columns and the child view records of its keys are
+//     copied straight into LDS (global_load_lds): fact columns
+//     feature-major, records row-major; with nbuf = 2 the next tile's copies
+//     are in flight while this tile is processed;
+//   * covariance: each MFMA lane reads 8 consecutive rows of one feature
+//     (from a fact column, or strided out of the records), zeroes rows that
+//     do not join, splits into bf16 hi/lo in registers; or fp32 register
+//     blocks accumulate per (row phase, block pair);
+//   * grouped tables: each lane updates the tables of its own row.
 template <int MODE, int P1, bool TABLES>
-__global__ __launch_bounds__(kBlock) void root_scan_kernel(const RootDesc *__restrict__ dp) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void root_scan_kernel(
+    const RootDesc *__restrict__ dp) {
     extern __shared__ __align__(16) uint32_t smem[];
     const RootDesc &d = *dp;
     const ScanDesc &s = d.scan;
+    const AS_CONST CompSrc *comps = cst(s.comps);
+    const AS_CONST PredSrc *preds = cst(s.preds);
+    const AS_CONST ChildSrc *children = cst(s.children);
+    const AS_CONST FamilyDesc *fams = cst(d.fams);
+    const AS_CONST KeyDesc *keys = cst(d.keys);
+    const AS_CONST ValDesc *vals = cst(d.vals);
+    const AS_CONST FlushDesc *flushes = cst(d.flush);
+    const AS_CONST int32_t *feat_src = cst(d.feat_src);
+    const AS_CONST int32_t *comp_src = cst(d.comp_src);
+    const auto fact_cols = cst(d.fact_cols);
+    const auto aux_cols = cst(d.aux_cols);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    const int nwaves = blockDim.x >> 6;
     const int part = blockIdx.y;
     const bool do_gram = MODE != 0 && part == d.gram_part && d.n_gram > 0;
     const bool do_count = d.do_count && part == d.gram_part;
@@ -198,24 +273,37 @@ __global__ __launch_bounds__(kBlock) void root_scan_kernel(const RootDesc *__res
     constexpr int NT = MODE >= 2 ? P1 : 1;
     constexpr int NHH = NT * (NT + 1) / 2;
     constexpr int NHL = NT * NT;
-    constexpr int NLL = MODE == 3 ? NHH : 0;
+    constexpr int NLL = MODE == 3 ? NHH : 1;
 
-    // ---- LDS set-up --------------------------------------------------------
+    // ---- block set-up: tables zeroed, constant columns, thresholds ------------------
     if (TABLES) {
         const int words = d.lds_table_words[part];
-        for (int i = tid; i < words; i += kBlock) smem[d.lds_tables + i] = 0u;
+        for (int i = tid; i < words; i += blockDim.x) smem[d.lds_tables + i] = 0u;
     }
-    if (MODE >= 2 && do_gram) {   // padding features stay zero for the whole scan
-        for (int i = tid; i < 4 * d.frag_wave_words; i += kBlock) smem[d.lds_frag + i] = 0u;
+    if (tid < 64) {
+        smem[d.lds_consts + tid] = __float_as_uint(1.f);
+        smem[d.lds_consts + 64 + tid] = 0u;
     }
-    if (MODE == 1 && do_gram) {
-        for (int i = tid; i < kBlock * d.ngp; i += kBlock) smem[d.lds_xs + i] = 0u;
-    }
+    for (int i = tid; i < d.n_thr_words; i += blockDim.x) smem[d.lds_thr + i] = __float_as_uint(gld(d.thr_all)[i]);
+    __syncthreads();
 
-    // ---- fp32 covariance: thread -> (row phase, GB x GB block pair) ------------
-    int gI = 0, gJ = 0, gph = 0, nph = 1;
-    bool gact = false;
+    const int wbase = d.lds_wave + wave * d.wave_words;
+    uint32_t *W = smem + wbase;
+    const float *fsm = reinterpret_cast<const float *>(smem);
+    const float *thr_lds = reinterpret_cast<const float *>(smem + d.lds_thr);
+    const int64_t blk_begin = (int64_t)blockIdx.x * d.rows_per_block;
+    const int64_t blk_end = min(blk_begin + d.rows_per_block, s.n_rows);
+    const int64_t per_wave = d.rows_per_block / nwaves;
+    const int64_t w_begin = blk_begin + wave * per_wave;
+    const int64_t w_end = min(w_begin + per_wave, blk_end);
+    const int64_t n_tiles = w_end > w_begin ? (w_end - w_begin + 63) / 64 : 0;
+    const int64_t last_row = s.n_rows - 1;
+
+    // ---- accumulators and per-lane feature sources ---------------------------------------
     float acc[GB][GB], shi[GB][GB], slo[GB][GB];
+    FeatLoc la[GB], lb[GB];
+    int gph = 0, nph = 1;
+    bool gact = false;
     if (MODE == 1) {
 #pragma unroll
         for (int i = 0; i < GB; ++i)
@@ -223,121 +311,223 @@ __global__ __launch_bounds__(kBlock) void root_scan_kernel(const RootDesc *__res
             for (int j = 0; j < GB; ++j) acc[i][j] = shi[i][j] = slo[i][j] = 0.f;
         const int nb = d.ngp / GB;
         const int np = nb * (nb + 1) / 2;
-        nph = kBlock / np;
-        if (tid < np * nph) {
+        nph = 64 / np;
+        int gI = 0, gJ = 0;
+        if (lane < np * nph) {
             gact = true;
-            int p = tid % np;
-            gph = tid / np;
-            int I = 0;
-            while (p >= nb - I) { p -= nb - I; ++I; }
-            gI = I;
-            gJ = I + p;
+            int p = lane % np;
+            gph = lane / np;
+            while (p >= nb - gI) { p -= nb - gI; ++gI; }
+            gJ = gI + p;
+        }
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+            const int fa = gI * GB + q, fb = gJ * GB + q;
+            la[q] = feat_loc(d, fa, fa < d.n_feat ? gld(d.feat_src)[fa] : 0, wbase);
+            lb[q] = feat_loc(d, fb, fb < d.n_feat ? gld(d.feat_src)[fb] : 0, wbase);
         }
     }
-    // ---- bf16 covariance accumulators ---------------------------------------------
-    f32x4 chh[NHH], chl[NHL], cll[NLL > 0 ? NLL : 1];
-    f32x4 shh[NHH], ehh[NHH], shl[NHL], ehl[NHL], sll[NLL > 0 ? NLL : 1], ell[NLL > 0 ? NLL : 1];
+    // hi*hi partials fold into a second fp32 level every kFlushTiles tiles; hi*lo and
+    // lo*lo partials are ~2^-8 and ~2^-16 of them, their fp32 chains need no second level
+    f32x4 chh[NHH], chl[NHL], cll[NLL], shh[NHH];
+    FeatLoc lt[NT];
     if (MODE >= 2) {
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < NHH; ++i) chh[i] = shh[i] = ehh[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NHH; ++i) chh[i] = shh[i] = z;
 #pragma unroll
-        for (int i = 0; i < NHL; ++i) chl[i] = shl[i] = ehl[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NHL; ++i) chl[i] = z;
 #pragma unroll
-        for (int i = 0; i < (NLL > 0 ? NLL : 1); ++i) cll[i] = sll[i] = ell[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NLL; ++i) cll[i] = z;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int f = 16 * t + (lane & 15);
+            lt[t] = feat_loc(d, f, f < d.n_feat ? gld(d.feat_src)[f] : 0, wbase);
+        }
     }
-    int rows_since_flush = 0;
-
+    int tiles_since_flush = 0;
     unsigned long long my_count = 0;
-    const int64_t row_begin = (int64_t)blockIdx.x * d.rows_per_block;
-    const int64_t row_end = min(row_begin + d.rows_per_block, s.n_rows);
-    float *xs = reinterpret_cast<float *>(smem + d.lds_xs);
-    float *tfeat = reinterpret_cast<float *>(smem + d.lds_tfeat);
-    int32_t *tcomp = reinterpret_cast<int32_t *>(smem + d.lds_tcomp);
-    uint32_t *frag = smem + d.lds_frag + wave * d.frag_wave_words;
-    // this lane's slot in the fragment layout (row = lane of the wave)
-    const int f_ks = lane >> 5, f_grp = (lane >> 3) & 3, f_half = (lane & 7) >> 1, f_part = lane & 1;
-    const int f_wbase = (f_ks * 2 + f_part) * d.frag_sp + f_grp * kGroupWords + f_half;
-    __syncthreads();
 
-    for (int64_t base = row_begin; base < row_end; base += kBlock) {
-        const int64_t row = base + tid;
-        const bool in = row < row_end;
-        bool valid = in;
-        uint64_t mask = s.filter_all;
-
-        // child views: validity, filter masks (one record per key, Section 3.2)
-        const uint32_t *rp[kMaxChild];
+    // ---- tile copies ------------------------------------------------------------------------
+    int32_t fk[kMaxChild];
+    auto load_keys = [&](int64_t tile) {
+        const int64_t row = min(w_begin + tile * 64 + lane, last_row);
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c)
+            if (c < s.n_child) fk[c] = gld(children[c].fk)[row];
+    };
+    auto issue = [&](int64_t tile, int buf) {
+        const int64_t row = min(w_begin + tile * 64 + lane, last_row);
+        uint32_t *fb = W + d.w_fact + buf * d.n_fact * kColPitch;
+        for (int f0 = 0; f0 < d.n_fact; f0 += 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (f0 + i < d.n_fact) lds_dma4(fact_cols[f0 + i] + row, fb + (f0 + i) * kColPitch);
+        }
+        uint32_t *ab = W + d.w_aux + buf * d.n_aux * kColPitch;
+        for (int a0 = 0; a0 < d.n_aux; a0 += 8) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (a0 + i < d.n_aux) lds_dma4(aux_cols[a0 + i] + row, ab + (a0 + i) * kColPitch);
+        }
+        uint32_t *rb = W + d.w_rec + buf * d.n_quads * 256;
 #pragma unroll
         for (int c = 0; c < kMaxChild; ++c) {
-            rp[c] = nullptr;
             if (c < s.n_child) {
-                const ChildSrc &ch = s.children[c];
-                if (in) {
-                    const int32_t k = ch.fk[row];
-                    if (k >= 0 && k < ch.n_keys) {
-                        const uint32_t *r = ch.rec + (int64_t)k * ch.stride;
-                        if (r[0] != 0u) {
-                            rp[c] = r;
-                            if (ch.n_mask > 0) {
-                                uint64_t m = r[1];
-                                if (ch.n_mask > 1) m |= (uint64_t)r[2] << 32;
-                                mask &= m;
-                            }
-                        } else valid = false;
-                    } else valid = false;
-                }
+                const AS_CONST ChildSrc &ch = children[c];
+                const int32_t k = fk[c];
+                const uint32_t *rec = (k >= 0 && k < ch.n_keys) ? ch.rec + (int64_t)k * ch.stride : d.zero_rec;
+                const int nq = ch.stride >> 2;
+                uint32_t *dst = rb + ch.quad_base * 256;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < nq) lds_dma16(rec + 4 * q, dst + q * 256);
+                for (int q = 4; q < nq; ++q) lds_dma16(rec + 4 * q, dst + q * 256);
             }
         }
-        if (in)
-            for (int p = 0; p < s.n_pred; ++p)
-                if (!pred_holds(s.preds[p], row)) mask &= ~(1ull << s.preds[p].filter);
+    };
+
+    if (n_tiles > 0) {
+        load_keys(0);
+        if (d.nbuf == 2) {
+            __builtin_amdgcn_s_waitcnt(0);
+            issue(0, 0);
+            if (n_tiles > 1) load_keys(1);
+        }
+    }
+
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        const int buf = d.nbuf == 2 ? (int)(t & 1) : 0;
+        if (d.nbuf == 1) {
+            __builtin_amdgcn_s_waitcnt(0);
+            wave_sync();       // the previous tile's reads of the single buffer are done
+            issue(t, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // this tile's copies and the next tile's keys have landed
+        wave_sync();
+        if (d.nbuf == 2 && t + 1 < n_tiles) {
+            issue(t + 1, buf ^ 1);
+            if (t + 2 < n_tiles) load_keys(t + 2);
+        } else if (d.nbuf == 1 && t + 1 < n_tiles) {
+            load_keys(t + 1);
+        }
+
+        // ---- per-row validity, filters, components --------------------------------------------
+        const int64_t row = w_begin + t * 64 + lane;
+        bool valid = row < w_end;
+        uint64_t mask = s.filter_all;
+        const uint32_t *rb = W + d.w_rec + buf * d.n_quads * 256;
+        const uint32_t *ab = W + d.w_aux + buf * d.n_aux * kColPitch;
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c) {
+            if (c < s.n_child) {
+                const uint4 q0 = *reinterpret_cast<const uint4 *>(rb + (children[c].quad_base * 64 + lane) * 4);
+                if (q0.x == 0u) valid = false;
+                if (s.n_mask > 0) mask &= (uint64_t)q0.y | (s.n_mask > 1 ? (uint64_t)q0.z << 32 : 0ull);
+            }
+        }
+        for (int p = 0; p < s.n_pred; ++p) {
+            const AS_CONST PredSrc &ps = preds[p];
+            const uint32_t raw = ab[ps.aux * kColPitch + lane];
+            const bool ok = ps.is_float ? compare(__uint_as_float(raw), ps.op, ps.fval) : compare((int32_t)raw, ps.op, ps.ival);
+            if (!ok) mask &= ~(1ull << ps.filter);
+        }
+        if (TABLES) {
+            for (int c = 0; c < d.n_comp; ++c) {
+                const int src = comp_src[c];
+                if (src >= 0) W[d.w_comp + c * 64 + lane] = rb[src + lane * 4];
+            }
+            for (int c = 0; c < s.n_comp; ++c) {
+                const AS_CONST CompSrc &cs = comps[c];
+                const uint32_t raw = ab[cs.aux * kColPitch + lane];
+                int32_t v;
+                if (cs.nthr == 0) {
+                    v = (int32_t)raw;
+                    if (valid && (v < 0 || v >= cs.dom)) gor(d.err, kErrDomain);
+                    if (v < 0 || v >= cs.dom) v = 0;
+                } else {
+                    const float x = __uint_as_float(raw);
+                    v = 0;
+                    for (int k = 0; k < cs.nthr; ++k) v += thr_lds[cs.thr_lds + k] < x ? 1 : 0;
+                }
+                W[d.w_comp + cs.dst * 64 + lane] = (uint32_t)v;
+            }
+        }
+        const uint64_t vm = __ballot(valid);
         if (do_count) my_count += valid ? 1ull : 0ull;
 
-        if (MODE >= 2 && do_gram) wave_sync();   // previous fragments consumed
-
-        // ---- stage features: x[0] = 1, own columns, child record features -------
-        auto put = [&](int dst, float v) {
-            if (MODE == 1 && do_gram && dst < d.n_gram) xs[tid * d.ngp + dst] = v;
-            if (MODE >= 2 && do_gram && dst < d.n_gram) {
-                const uint32_t hi = bf16_rne(v);
-                const uint32_t lo = bf16_rne(v - __uint_as_float(hi << 16));
-                const uint32_t send = (lane & 1) ? hi : lo;
-                const uint32_t recv = (uint32_t)__shfl_xor((int)send, 1);
-                const uint32_t word = (lane & 1) ? (recv | (lo << 16)) : (hi | (recv << 16));
-                frag[f_wbase + (dst >> 4) * kTileWords + (dst & 15) * 4] = word;
-            }
-            if (TABLES && dst < d.n_tfeat) tfeat[tid * d.n_tfeat + dst] = v;
-        };
-        put(0, valid ? 1.f : 0.f);
-        for (int f = 0; f < s.n_feat; ++f) {
-            const FeatSrc &fs = s.feats[f];
-            float v = 0.f;
-            if (valid) v = fs.col[row];
-            put(fs.dst, v);
-        }
+        // ---- covariance block ---------------------------------------------------------------
+        if (MODE == 1 && do_gram && gact) {
+            int pa[GB], pb[GB];
 #pragma unroll
-        for (int c = 0; c < kMaxChild; ++c) {
-            if (c < s.n_child) {
-                const ChildSrc &ch = s.children[c];
-                const uint32_t *r = rp[c];
-                for (int i = 0; i < ch.n_feat; ++i) {
-                    float v = 0.f;
-                    if (valid) v = __uint_as_float(r[ch.feat_off + i]);
-                    put(ch.feat_dst + i, v);
-                }
-                if (TABLES && valid)
-                    for (int i = 0; i < ch.n_comp; ++i) tcomp[tid * d.n_comp + ch.comp_dst + i] = (int32_t)r[ch.comp_off + i];
+            for (int q = 0; q < GB; ++q) {
+                pa[q] = la[q].base + buf * la[q].step;
+                pb[q] = lb[q].base + buf * lb[q].step;
+            }
+            for (int r = gph; r < 64; r += nph) {
+                if (!((vm >> r) & 1ull)) continue;
+                float a[GB], b[GB];
+#pragma unroll
+                for (int q = 0; q < GB; ++q) { a[q] = fsm[pa[q] + r * la[q].stride]; b[q] = fsm[pb[q] + r * lb[q].stride]; }
+#pragma unroll
+                for (int i = 0; i < GB; ++i)
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+            }
+            if (++tiles_since_flush == 4) {
+#pragma unroll
+                for (int i = 0; i < GB; ++i)
+#pragma unroll
+                    for (int j = 0; j < GB; ++j) { two_sum_acc(shi[i][j], slo[i][j], acc[i][j]); acc[i][j] = 0.f; }
+                tiles_since_flush = 0;
             }
         }
-        if (TABLES && valid)
-            for (int c = 0; c < s.n_comp; ++c) tcomp[tid * d.n_comp + s.comps[c].dst] = comp_value(s.comps[c], row, d.err);
+        if (MODE >= 2 && do_gram) {
+#pragma unroll 1
+            for (int ks = 0; ks < 2; ++ks) {
+                const int row0 = 32 * ks + 8 * (lane >> 4);
+                const uint32_t vbits = (uint32_t)(vm >> row0) & 0xFFu;
+                bf16x8 fh[NT], fl[NT];
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2) {
+                    const int w0 = lt[t2].base + buf * lt[t2].step + row0 * lt[t2].stride;
+                    const int st = lt[t2].stride;
+                    float x[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) x[i] = ((vbits >> i) & 1u) ? fsm[w0 + i * st] : 0.f;
+                    split_bf16x8(x, fh[t2], fl[t2]);
+                }
+                int ih = 0;
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2)
+#pragma unroll
+                    for (int u = t2; u < NT; ++u, ++ih) {
+                        chh[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t2], fh[u], chh[ih], 0, 0, 0);
+                        if (MODE == 3) cll[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[t2], fl[u], cll[ih], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2)
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+                        chl[t2 * NT + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t2], fl[u], chl[t2 * NT + u], 0, 0, 0);
+            }
+            if (++tiles_since_flush == kFlushTiles) {
+                const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < NHH; ++i) { shh[i] += chh[i]; chh[i] = z; }
+                tiles_since_flush = 0;
+            }
+        }
 
-        // ---- grouped tables (this thread's own row) ------------------------------------
+        // ---- grouped tables (this lane's own row) ---------------------------------------------
         if (TABLES && valid) {
-            const float *xr = tfeat + tid * d.n_tfeat;
-            const int32_t *cr = tcomp + tid * d.n_comp;
+            const uint32_t *cr = W + d.w_comp + lane;
+            auto fval = [&](int f) -> double {
+                const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
+                return (double)fsm[L.base + buf * L.step + lane * L.stride];
+            };
             for (int fi = 0; fi < d.n_fam; ++fi) {
-                const FamilyDesc &F = d.fams[fi];
+                const AS_CONST FamilyDesc &F = fams[fi];
                 uint64_t bits = F.unfiltered ? 1ull : (mask & F.part_mask[part]);
                 while (bits) {
                     int f;
@@ -350,110 +540,47 @@ __global__ __launch_bounds__(kBlock) void root_scan_kernel(const RootDesc *__res
                         f = __popcll(F.filt_mask & ((1ull << b) - 1ull));
                     }
                     for (int k = 0; k < F.n_keys; ++k) {
-                        const TabDesc &T = d.tabs[F.tab_base + f * F.n_keys + k];
+                        const AS_GLOBAL TabDesc &T = gld(d.tabs)[F.tab_base + f * F.n_keys + k];
                         if (T.part != part) continue;
-                        const KeyDesc &K = d.keys[F.key_base + k];
+                        const AS_CONST KeyDesc &K = keys[F.key_base + k];
                         int32_t cell = 0;
-                        for (int c = 0; c < K.n_comp; ++c) cell += cr[K.c[c]] * K.s[c];
-                        // a product of two fp32 values is exact in fp64; the cell sums
-                        // accumulate in fp64 (runs of one dimension key repeat a value
-                        // thousands of times in a row, beyond what fp32 sums exactly)
+                        for (int c = 0; c < K.n_comp; ++c) cell += (int32_t)cr[K.c[c] * 64] * K.s[c];
+                        // a product of two fp32 values is exact in fp64; cell sums accumulate
+                        // in fp64 (runs of one dimension key repeat a value thousands of
+                        // times in a row, beyond what fp32 sums exactly)
                         if (T.lds_cnt >= 0) {
                             atomicAdd(&smem[d.lds_tables + T.lds_cnt + cell], 1u);
                             double *vs = reinterpret_cast<double *>(smem + d.lds_tables + T.lds_val) + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
-                                const ValDesc vd = d.vals[F.val_base + v];
-                                atomicAdd(vs + v, (double)xr[vd.a] * (double)xr[vd.b]);
+                                const AS_CONST ValDesc &vd = vals[F.val_base + v];
+                                atomicAdd(vs + v, fval(vd.a) * fval(vd.b));
                             }
                         } else {
-                            atomicAdd(&d.g_cnt[T.glb_cnt + cell], 1ull);
+                            gadd(d.g_cnt + T.glb_cnt + cell, 1ull);
                             double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
-                                const ValDesc vd = d.vals[F.val_base + v];
-                                atomicAdd(vs + v, (double)xr[vd.a] * (double)xr[vd.b]);
+                                const AS_CONST ValDesc &vd = vals[F.val_base + v];
+                                gadd(vs + v, fval(vd.a) * fval(vd.b));
                             }
                         }
                     }
                 }
             }
         }
-
-        // ---- covariance block --------------------------------------------------------
-        if (MODE == 1) {
-            __syncthreads();
-            if (do_gram && gact) {
-                for (int r = gph; r < kBlock; r += nph) {
-                    const float *xr = xs + r * d.ngp;
-                    float a[GB], b[GB];
-#pragma unroll
-                    for (int q = 0; q < GB; ++q) { a[q] = xr[gI * GB + q]; b[q] = xr[gJ * GB + q]; }
-#pragma unroll
-                    for (int i = 0; i < GB; ++i)
-#pragma unroll
-                        for (int j = 0; j < GB; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
-                }
-                rows_since_flush += kBlock / nph;
-                if (rows_since_flush >= 128) {
-#pragma unroll
-                    for (int i = 0; i < GB; ++i)
-#pragma unroll
-                        for (int j = 0; j < GB; ++j) { two_sum_acc(shi[i][j], slo[i][j], acc[i][j]); acc[i][j] = 0.f; }
-                    rows_since_flush = 0;
-                }
-            }
-            __syncthreads();
-        }
-        if (MODE >= 2 && do_gram) {
-            wave_sync();
-            const uint32_t *fr = smem + d.lds_frag + wave * d.frag_wave_words + (lane >> 4) * kGroupWords + (lane & 15) * 4;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x8 fh[NT], fl[NT];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const uint4 h = *reinterpret_cast<const uint4 *>(fr + (ks * 2 + 0) * d.frag_sp + t * kTileWords);
-                    const uint4 l = *reinterpret_cast<const uint4 *>(fr + (ks * 2 + 1) * d.frag_sp + t * kTileWords);
-                    fh[t] = __builtin_bit_cast(bf16x8, h);
-                    fl[t] = __builtin_bit_cast(bf16x8, l);
-                }
-                int ih = 0;
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int u = t; u < NT; ++u, ++ih) {
-                        chh[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t], fh[u], chh[ih], 0, 0, 0);
-                        if (MODE == 3) cll[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[t], fl[u], cll[ih], 0, 0, 0);
-                    }
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int u = 0; u < NT; ++u)
-                        chl[t * NT + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t], fl[u], chl[t * NT + u], 0, 0, 0);
-            }
-            rows_since_flush += 64;
-            if (rows_since_flush >= 512) {
-const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int i = 0; i < NHH; ++i) { two_sum_acc4(shh[i], ehh[i], chh[i]); chh[i] = zero4; }
-#pragma unroll
-                for (int i = 0; i < NHL; ++i) { two_sum_acc4(shl[i], ehl[i], chl[i]); chl[i] = zero4; }
-                if (MODE == 3) {
-#pragma unroll
-                    for (int i = 0; i < NHH; ++i) { two_sum_acc4(sll[i], ell[i], cll[i]); cll[i] = zero4; }
-                }
-                rows_since_flush = 0;
-            }
-        }
     }
 
-    // ---- end of scan: workgroup reduction in fp64, partials out --------------------
-    __syncthreads();
+    // ---- end of scan: workgroup reduction in fp64, partials out ------------------------
+    __syncthreads();   // every wave is done with its region; the reduction scratch aliases them
     double *red = reinterpret_cast<double *>(smem + d.lds_red);
     if (MODE == 1 && do_gram) {
         const int ngp = d.ngp;
-        for (int i = tid; i < ngp * ngp; i += kBlock) red[i] = 0.0;
+        for (int i = tid; i < ngp * ngp; i += blockDim.x) red[i] = 0.0;
         __syncthreads();
         if (gact) {
+            const int nb = d.ngp / GB;
+            int p = lane % (nb * (nb + 1) / 2), gI = 0;
+            while (p >= nb - gI) { p -= nb - gI; ++gI; }
+            const int gJ = gI + p;
 #pragma unroll
             for (int i = 0; i < GB; ++i)
 #pragma unroll
@@ -465,25 +592,18 @@ const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
         }
         __syncthreads();
         double *out = d.gram_partial + (int64_t)blockIdx.x * d.n_gram * d.n_gram;
-        for (int e = tid; e < d.n_gram * d.n_gram; e += kBlock) {
+        for (int e = tid; e < d.n_gram * d.n_gram; e += blockDim.x) {
             const int i = e / d.n_gram, j = e % d.n_gram;
-            if (i <= j) out[e] = red[i * ngp + j];
+            if (i <= j) gst(out)[e] = red[i * ngp + j];
         }
     }
     if (MODE >= 2 && do_gram) {
         const int n16 = NT * 16;
         double *rhh = red, *rhl = red + n16 * n16, *rll = red + 2 * n16 * n16;
         const int nred = (MODE == 3 ? 3 : 2) * n16 * n16;
-        for (int i = tid; i < nred; i += kBlock) red[i] = 0.0;
+        for (int i = tid; i < nred; i += blockDim.x) red[i] = 0.0;
         __syncthreads();
         const int ci = 4 * (lane >> 4), cj = lane & 15;
-#pragma unroll
-        for (int i = 0; i < NHH; ++i) {
-            two_sum_acc4(shh[i], ehh[i], chh[i]);
-            if (MODE == 3) two_sum_acc4(sll[i], ell[i], cll[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < NHL; ++i) two_sum_acc4(shl[i], ehl[i], chl[i]);
         int ih = 0;
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -491,56 +611,51 @@ const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
             for (int u = t; u < NT; ++u, ++ih)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    atomicAdd(&rhh[(16 * t + ci + e) * n16 + 16 * u + cj], (double)shh[ih][e] + (double)ehh[ih][e]);
-                    if (MODE == 3) {
-                        atomicAdd(&rll[(16 * t + ci + e) * n16 + 16 * u + cj], (double)sll[ih][e] + (double)ell[ih][e]);
-                    }
+                    atomicAdd(&rhh[(16 * t + ci + e) * n16 + 16 * u + cj], (double)shh[ih][e] + (double)chh[ih][e]);
+                    if (MODE == 3) atomicAdd(&rll[(16 * t + ci + e) * n16 + 16 * u + cj], (double)cll[ih][e]);
                 }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int u = 0; u < NT; ++u)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    atomicAdd(&rhl[(16 * t + ci + e) * n16 + 16 * u + cj],
-                              (double)shl[t * NT + u][e] + (double)ehl[t * NT + u][e]);
-                }
+                for (int e = 0; e < 4; ++e)
+                    atomicAdd(&rhl[(16 * t + ci + e) * n16 + 16 * u + cj], (double)chl[t * NT + u][e]);
         __syncthreads();
         double *out = d.gram_partial + (int64_t)blockIdx.x * d.n_gram * d.n_gram;
-        for (int e = tid; e < d.n_gram * d.n_gram; e += kBlock) {
+        for (int e = tid; e < d.n_gram * d.n_gram; e += blockDim.x) {
             const int i = e / d.n_gram, j = e % d.n_gram;
             if (i <= j) {
                 double v = rhh[i * n16 + j] + rhl[i * n16 + j] + rhl[j * n16 + i];
                 if (MODE == 3) v += rll[i * n16 + j];
-                out[e] = v;
+                gst(out)[e] = v;
             }
         }
     }
     if (do_count) {
-        __shared__ unsigned long long wcount[kBlock / 64];
+        __shared__ unsigned long long wcount[kMaxWaves];
         const unsigned long long w = wave_sum_u64(my_count);
         if (lane == 0) wcount[wave] = w;
         __syncthreads();
         if (tid == 0) {
             unsigned long long t = 0;
-            for (int i = 0; i < kBlock / 64; ++i) t += wcount[i];
-            d.count_partial[blockIdx.x] = t;
+            for (int i = 0; i < nwaves; ++i) t += wcount[i];
+            gst(d.count_partial)[blockIdx.x] = t;
         }
     }
     if (TABLES) {
         const int nf = d.n_flush[part];
-        const FlushDesc *fl = d.flush + d.flush_base[part];
         for (int t = 0; t < nf; ++t) {
-            const FlushDesc F = fl[t];
+            const AS_CONST FlushDesc &F = flushes[d.flush_base[part] + t];
             const uint32_t *cnt = smem + d.lds_tables + F.lds_cnt;
             const double *val = reinterpret_cast<const double *>(smem + d.lds_tables + F.lds_val);
-            for (int cell = tid; cell < F.n_cells; cell += kBlock) {
+            for (int cell = tid; cell < F.n_cells; cell += blockDim.x) {
                 const uint32_t c = cnt[cell];
                 if (c == 0u) continue;
-                atomicAdd(&d.g_cnt[F.glb_cnt + cell], (unsigned long long)c);
+                gadd(d.g_cnt + F.glb_cnt + cell, (unsigned long long)c);
                 for (int v = 0; v < F.n_vals; ++v) {
                     const double x = val[(int64_t)cell * F.n_vals + v];
-                    if (x != 0.0) atomicAdd(&d.g_val[F.glb_val + (int64_t)cell * F.n_vals + v], x);
+                    if (x != 0.0) gadd(d.g_val + F.glb_val + (int64_t)cell * F.n_vals + v, x);
                 }
             }
         }
@@ -655,8 +770,9 @@ hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hi
     return hipGetLastError();
 }
 
-hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k, dim3(grid_x, parts), dim3(kBlock), lds_bytes, st, desc);
+hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, int waves, size_t lds_bytes,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k, dim3(grid_x, parts), dim3(64 * waves), lds_bytes, st, desc);
     return hipGetLastError();
 }
 

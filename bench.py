@@ -62,6 +62,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"])
+    ap.add_argument("--forms", default="both", choices=["both", "full"],
+                    help="full: skip the plain form (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device-to-device copy of 2 GiB (a plain copy kernel of known size, "
+                         "used to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the engine shards by fact rows "
@@ -83,14 +88,25 @@ def main():
     stream = torch.cuda.Stream()
     n_join = db.relations[0].n_rows
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: %d bytes read, %d bytes written" % (src.numel(), dst.numel()),
+              file=sys.stderr, flush=True)
+        del src, dst
+
     # plain form: fp32 covariance, one launch per view, heuristic tiles
-    plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols)
-    t_plain = time_steps(plain, stream, args.steps, args.warmup)
-    res_plain = plain.results()
-    plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)
-    plain_stats = plain.stats()
-    print("[bench] plain fp32: %.3f ms/step" % (t_plain * 1e3), file=sys.stderr, flush=True)
-    del plain
+    t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
+    if args.forms == "both":
+        plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols)
+        t_plain = time_steps(plain, stream, args.steps, args.warmup)
+        res_plain = plain.results()
+        plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)
+        plain_stats = plain.stats()
+        print("[bench] plain fp32: %.3f ms/step" % (t_plain * 1e3), file=sys.stderr, flush=True)
+        del plain
 
     # full form: bf16x3 on MFMA, batched in a hipGraph, learned (or autotuned) tiles
     full = Engine(db, qs, precision="bf16x3", schedule="batched", columns=cols)
@@ -121,6 +137,8 @@ def main():
         ref = oracle.evaluate(db, [qs[i] for i in sample])
         errors = {}
         for name, res in (("plain_fp32", res_plain), ("full", res_full)):
+            if res is None:
+                continue
             worst = 0.0
             for i, r in zip(sample, ref):
                 if not np.array_equal(res[i].counts, r.counts):
@@ -163,10 +181,12 @@ def main():
         "config": {"workload": "covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with "
                                "4 dims (1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates",
                    "fact_rows": n_join, "aggregates": len(qs), "plan": chosen,
-                   "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"]},
-        "speedup_vs_plain_fp32": t_plain / t_full,
-        "plain_fp32": {"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
-                       "launches": plain_stats["launches"]},
+                   "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
+                   "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
+                   "lds_bytes": stats["lds_bytes"]},
+        "speedup_vs_plain_fp32": (t_plain / t_full) if t_plain else None,
+        "plain_fp32": ({"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
+                        "launches": plain_stats["launches"]} if t_plain else None),
         "errors_vs_oracle": errors,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

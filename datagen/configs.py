@@ -404,3 +404,71 @@ def make_batch(k: int, db: Database) -> List[Query]:
     if k == 5:
         return batch5(db)
     raise ValueError(k)
+
+
+# ---------------------------------------------------------------------------
+# random star/snowflake workloads (training and held-out data of the cost model)
+# ---------------------------------------------------------------------------
+
+def random_workload(j: int, max_rows: int = 20_000_000, min_rows: int = 1_000):
+    """Random schema and batch number j (seed 6000 + j): 2-6 relations, each
+    dimension attached to the fact or to an earlier dimension; sizes
+    log-uniform in [min_rows, max_rows] with the fact largest; 1-10 continuous
+    and 0-5 categorical attributes per relation; 10-500 aggregates mixing
+    covariance entries, grouped sums, pairwise counts and filtered sums."""
+    seed = 6000 + j
+    g = native()
+    u = g.unit(g.key(seed, "shape"), 4096)
+    pos = [0]
+
+    def nxt():
+        pos[0] += 1
+        return float(u[pos[0] - 1])
+
+    def loguni(lo, hi):
+        return int(round(math.exp(math.log(lo) + nxt() * (math.log(hi) - math.log(lo)))))
+
+    m = 2 + min(int(nxt() * 5), 4)
+    sizes = sorted([loguni(min_rows, max_rows) for _ in range(m)], reverse=True)
+    specs = []
+    for r in range(m):
+        n_cont = 1 + min(int(nxt() * 10), 9)
+        n_cat = min(int(nxt() * 6), 5)
+        name = "F" if r == 0 else "R%d" % r
+        attrs = [AttrSpec("%s_x%d" % (name, i), "cont") for i in range(n_cont)]
+        attrs += [AttrSpec("%s_c%d" % (name, i), "cat", domain=2 + min(int(nxt() * 60), 59)) for i in range(n_cat)]
+        specs.append(RelSpec(name, sizes[r], attrs, key=None if r == 0 else "k%d" % r))
+    for r in range(1, m):
+        parent = 0 if r == 1 or nxt() < 0.6 else 1 + min(int(nxt() * (r - 1)), r - 2)
+        specs[parent].children.append((specs[r], "k%d" % r))
+        if parent == 0 and nxt() < 0.5:
+            specs[0].zipf_s["k%d" % r] = 1.1
+    db = build_database(seed, specs[0])
+    conts = cont_attrs(db)
+    cats = cat_attrs(db)
+    qs: List[Query] = []
+    budget = 10 + min(int(nxt() * 491), 490)
+    # covariance block over a random subset of continuous attributes
+    k = max(1, min(len(conts), int(math.sqrt(2 * budget * nxt())) or 1))
+    sub = [conts[i] for i in sorted(set(min(int(nxt() * len(conts)), len(conts) - 1) for _ in range(k)))]
+    for q in covariance_queries(sub):
+        if len(qs) < budget:
+            qs.append(q)
+    # grouped sums and pairwise counts
+    for c in cats:
+        if len(qs) >= budget:
+            break
+        if nxt() < 0.6:
+            x = conts[min(int(nxt() * len(conts)), len(conts) - 1)]
+            qs.append(Query(groupby=[GroupBy(c)], aggs=[Agg.monomial(x)]))
+    for i in range(len(cats)):
+        for jj in range(i + 1, len(cats)):
+            if len(qs) < budget and nxt() < 0.3:
+                qs.append(Query(groupby=[GroupBy(cats[i]), GroupBy(cats[jj])]))
+    # a few filtered sums
+    for _ in range(min(int(nxt() * 6), 5)):
+        x = conts[min(int(nxt() * len(conts)), len(conts) - 1)]
+        y = conts[min(int(nxt() * len(conts)), len(conts) - 1)]
+        qs.append(Query(where=[Pred(x, "le" if nxt() < 0.5 else "gt", float(np.float32(2 * nxt() - 1)))],
+                        aggs=[Agg.monomial(y)]))
+    return db, qs

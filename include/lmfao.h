@@ -186,6 +186,9 @@ typedef struct {
     int64_t table_cells;         /* cells over all grouped tables */
     int32_t launches;            /* kernel launches per execution */
     int32_t block_rows, grid_blocks, gram_block, lds_tables; /* chosen tile configuration */
+    int32_t waves;               /* waves per workgroup of the root scan */
+    int32_t nbuf;                /* staging buffers per wave (2: next tile copied during this one) */
+    int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);
@@ -230,9 +233,10 @@ lmfao_status lmfao_time_root_group(lmfao_ctx *ctx, void *hip_stream, int32_t war
 /* ---- tile choice: exhaustive autotuner and learned cost model ------------ */
 
 /* Number of candidate tile configurations of the current plan, and the
- * candidate `i` as {block_rows, grid_blocks, gram_block, lds_tables}. */
+ * candidate `i` as {waves per workgroup, staging buffers per wave, workgroups,
+ * fp32 register block edge (0 for bf16), table placement policy}. */
 lmfao_status lmfao_candidates(const lmfao_ctx *ctx, int32_t *n);
-lmfao_status lmfao_candidate(const lmfao_ctx *ctx, int32_t i, int32_t cfg[4]);
+lmfao_status lmfao_candidate(const lmfao_ctx *ctx, int32_t i, int32_t cfg[5]);
 
 /* Feature vector of the root view group under candidate `i` (input of the
  * cost model): LMFAO_N_FEATURES floats. */
@@ -242,17 +246,18 @@ lmfao_status lmfao_candidate_features(const lmfao_ctx *ctx, int32_t i, float *fe
 /* Re-plan with candidate `i` as the tile configuration (must be bound again). */
 lmfao_status lmfao_select_candidate(lmfao_ctx *ctx, int32_t i);
 
-/* Exhaustive autotuner: time every candidate (needs bound buffers and one
- * prior lmfao_execute), append one line per candidate to the timing file
- * `timing_db` (features, configuration, milliseconds; may be NULL), and
- * select the fastest.  *best receives its index. */
+/* Exhaustive autotuner: time every candidate (needs bound buffers), append
+ * one line per candidate to the timing file `timing_db` (16 features, the 5
+ * configuration values of lmfao_candidate, milliseconds; may be NULL),
+ * select the fastest and execute it once on `hip_stream` (so that
+ * lmfao_time_root_group can follow).  *best receives its index. */
 lmfao_status lmfao_autotune(lmfao_ctx *ctx, void *hip_stream, const char *timing_db, int32_t reps, int32_t *best);
 
 /* Learned choice: score every candidate with the cost model in `weights`
  * (inference runs on the device in the workspace), select the lowest
- * predicted time, and store its index in *best.  Falls back to the
- * heuristic configuration (and returns LMFAO_OK with *best = -1) if the
- * model is missing or predicts a non-finite time. */
+ * predicted time, execute it once on `hip_stream`, and store its index in
+ * *best.  Keeps the heuristic configuration (and returns LMFAO_OK with
+ * *best = -1) if the model is missing or predicts a non-finite time. */
 lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t *best);
 
 /* ---- cost-model network (hand-written device kernels) -------------------- */

@@ -1,0 +1,100 @@
+"""Learned cost model of the root view-group scan.
+
+A small network (16 plan features -> log milliseconds) ranks the candidate
+tile configurations of a plan (waves per workgroup, staging buffers,
+workgroups, fp32 register block, table placement).  Timings come from the
+engine itself: the exhaustive autotuner appends one line per timed candidate
+to a timing file; training runs on the device with the library's own
+forward/backward/Adam kernels; the planner queries the network through
+lmfao_choose_learned and keeps the heuristic configuration whenever the
+model is absent or predicts a non-finite time.
+
+Weights file: b"LMFAOMLP", int32 hidden, float32 feature mean[16] and
+std[16], float32 target mean and std, float32 parameters.
+"""
+from __future__ import annotations
+
+import os
+import struct
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .. import lmfao
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "weights.bin")
+N_FEATURES = lmfao.N_FEATURES
+
+
+def collect(workloads, timing_db: str, precision: str = "bf16x3", reps: int = 3, device: int = 0,
+            log=None) -> List[Tuple[int, float]]:
+    """Time every tile candidate of every workload (db, queries) and append
+    the timings to ``timing_db``.  Returns (best candidate, best ms) per
+    workload."""
+    import torch
+    out = []
+    stream = torch.cuda.Stream(device=device)
+    for i, (db, qs) in enumerate(workloads):
+        eng = lmfao.Engine(db, qs, precision=precision, schedule="batched", device=device)
+        eng.run(stream)
+        best = eng.ctx.autotune(stream, timing_db, reps)
+        ms = eng.ctx.time_root_group(stream, 1, reps)
+        out.append((best, ms))
+        if log:
+            log("workload %d: %d fact rows, %d queries, best candidate %d at %.3f ms" %
+                (i, db.relations[0].n_rows, len(qs), best, ms))
+        del eng
+        torch.cuda.empty_cache()
+    return out
+
+
+def load_db(path: str):
+    """Features (n x 16), candidate configuration columns and milliseconds."""
+    rows = [l.strip().split(",") for l in open(path) if l.strip()]
+    a = np.array([[float(v) for v in r] for r in rows], dtype=np.float64)
+    return a[:, :N_FEATURES], a[:, N_FEATURES:-1], a[:, -1]
+
+
+def init_params(hidden: int, seed: int = 1) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, np.sqrt(2.0 / N_FEATURES), hidden * N_FEATURES), np.zeros(hidden),
+             rng.normal(0, np.sqrt(2.0 / hidden), hidden * hidden), np.zeros(hidden),
+             rng.normal(0, np.sqrt(1.0 / hidden), hidden), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X: np.ndarray, ms: np.ndarray, hidden: int = 32, epochs: int = 3000, lr: float = 3e-3,
+          device: int = 0, seed: int = 1):
+    """Fit log(ms) on the device; returns (norm vector, params, losses)."""
+    import torch
+    X = np.asarray(X, np.float64)
+    y = np.log(np.asarray(ms, np.float64))
+    mean, std = X.mean(axis=0), X.std(axis=0)
+    std[std == 0] = 1.0
+    ym, ys = y.mean(), y.std() or 1.0
+    dev = torch.device("cuda", device)
+    xt = torch.from_numpy(((X - mean) / std).astype(np.float32)).to(dev).contiguous()
+    yt = torch.from_numpy(((y - ym) / ys).astype(np.float32)).to(dev).contiguous()
+    p = torch.from_numpy(init_params(hidden, seed)).to(dev)
+    losses = lmfao.mlp_train(hidden, p, xt, yt, epochs, lr)
+    torch.cuda.synchronize()
+    norm = np.concatenate([mean, std, [ym, ys]]).astype(np.float32)
+    return norm, p.cpu().numpy(), losses.cpu().numpy()
+
+
+def save(path: str, hidden: int, norm: np.ndarray, params: np.ndarray):
+    with open(path, "wb") as f:
+        f.write(b"LMFAOMLP")
+        f.write(struct.pack("<i", hidden))
+        f.write(np.asarray(norm, np.float32).tobytes())
+        f.write(np.asarray(params, np.float32).tobytes())
+
+
+def load(path: str = WEIGHTS):
+    with open(path, "rb") as f:
+        assert f.read(8) == b"LMFAOMLP"
+        hidden = struct.unpack("<i", f.read(4))[0]
+        norm = np.frombuffer(f.read(4 * (2 * N_FEATURES + 2)), np.float32)
+        params = np.frombuffer(f.read(), np.float32)
+    return hidden, norm, params

@@ -167,6 +167,7 @@ struct Output {
 
 struct TileCfg {
     int waves = 0;          // waves per workgroup of the root scan (0 = heuristic)
+    int nbuf = 0;           // staging buffers per wave (0 = heuristic)
     int grid_x = 0;         // requested workgroups (0 = heuristic)
     int gram_block = 0;     // fp32 register block edge
     int lds_policy = -1;    // 0 global tables, 1 greedy LDS, 2 partitioned LDS (-1 = heuristic)
@@ -935,6 +936,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         for (int nb : {2, 1})
             for (int wv : {4, 2, 1}) {
                 if (cfg.waves > 0 && wv != cfg.waves) continue;
+                if (cfg.nbuf > 0 && nb != cfg.nbuf) continue;
                 const Layout Ly = stage_layout(P, P.mode, p1, has_tables, 0, nb, wv);
                 const size_t bytes = (size_t)Ly.total * 4 + 1024;
                 if (bytes > c->lds_limit) continue;
@@ -995,6 +997,11 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             for (int t : P.fams[f].tables) P.root_launches.push_back(make_launch(false, {(int)f}, t));
     }
     if (P.root_launches.empty()) P.root_launches.push_back(make_launch(false, {}, -1));
+    // the root scan addresses columns and view records with 32-bit byte offsets
+    if (root.n_rows > ((int64_t)1 << 30)) return fail(c, LMFAO_ERR_TOO_LARGE, "root relation above 2^30 rows");
+    for (int ch : P.children[P.root])
+        if ((int64_t)P.n_keys[ch] * P.rec_stride[ch] * 4 >= ((int64_t)1 << 32))
+            return fail(c, LMFAO_ERR_TOO_LARGE, "view record array above 4 GiB");
     P.grid_x = P.root_launches[0].grid_x;
     P.rows_per_block = P.root_launches[0].desc.rows_per_block;
     for (auto &L : P.root_launches) {
@@ -1224,10 +1231,13 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     const size_t feat_src_off = B.vec(feat_src), comp_src_off = B.vec(comp_map);
     std::vector<uint64_t> fact_ptrs;
     for (int f : P.own_feats[r0]) fact_ptrs.push_back((uint64_t)(uintptr_t)c->rels[r0].cols[P.feats[f].col].data);
-    if (fact_ptrs.empty()) fact_ptrs.push_back(0);
+    while (fact_ptrs.size() % 16) fact_ptrs.push_back(0);   // the scan preloads 16 entries at a time
+    if (fact_ptrs.empty()) fact_ptrs.assign(16, 0);
     const size_t fact_cols_off = B.vec(fact_ptrs);
     std::vector<uint64_t> aux_ptrs;
     for (int col : aux_cols) aux_ptrs.push_back((uint64_t)(uintptr_t)c->rels[r0].cols[col].data);
+    while (aux_ptrs.size() % 8) aux_ptrs.push_back(0);
+    if (aux_ptrs.empty()) aux_ptrs.assign(8, 0);
     const size_t aux_off = B.vec(aux_ptrs);
     if (thr_all.empty()) thr_all.push_back(0.f);
     const size_t thr_all_off = B.vec(thr_all);
@@ -1534,6 +1544,9 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->grid_blocks = P.grid_x;
     s->gram_block = P.mode == 1 ? P.gram_block : (P.mode >= 2 ? 16 * P.n_tiles16 : 0);
     s->lds_tables = P.lds_policy;
+    s->waves = P.waves;
+    s->nbuf = P.nbuf;
+    s->lds_bytes = (int32_t)P.root_launches[0].lds_bytes;
     return LMFAO_OK;
 }
 
@@ -1717,24 +1730,29 @@ extern "C" lmfao_status lmfao_time_root_group(lmfao_ctx *c, void *hip_stream, in
 static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
     const Plan &P = c->plan;
     std::vector<TileCfg> out;
-    std::vector<int> grids;
-    for (int g : {256, 512, 1024, 2048}) grids.push_back(g * c->n_cu / 256);
     std::vector<int> gbs{0};
     if (P.mode == 1) {
         gbs.clear();
-        for (int gb : {2, 4, 6, 8})
+        for (int gb : {2, 4, 6})
             if (gram_block_ok(P.n_gram, gb)) gbs.push_back(gb);
+        if (gbs.empty()) gbs.push_back(8);
     }
     std::vector<int> pols{0};
     if (!P.tables.empty()) pols = {0, 1, 2};
-    for (int g : grids)
-        for (int gb : gbs)
-            for (int pl : pols) {
-                TileCfg t;
-                t.grid_x = g;
-                t.gram_block = gb;
-                t.lds_policy = pl;
-                out.push_back(t);
+    for (int wv : {1, 2, 4})
+        for (int nb : {1, 2})
+            for (int per_cu : {2, 3, 4, 6, 8}) {
+                if (per_cu % wv) continue;
+                for (int gb : gbs)
+                    for (int pl : pols) {
+                        TileCfg t;
+                        t.waves = wv;
+                        t.nbuf = nb;
+                        t.grid_x = per_cu / wv * c->n_cu;   // workgroups: a whole number of waves per CU
+                        t.gram_block = gb;
+                        t.lds_policy = pl;
+                        out.push_back(t);
+                    }
             }
     return out;
 }
@@ -1746,15 +1764,16 @@ extern "C" lmfao_status lmfao_candidates(const lmfao_ctx *c, int32_t *n) {
     return LMFAO_OK;
 }
 
-extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t cfg[4]) {
+extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t cfg[5]) {
     if (!c || !cfg) return LMFAO_ERR_INVALID_ARG;
     if (!c->plan.ok) return LMFAO_ERR_STATE;
     auto v = enumerate_candidates(c);
     if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
-    cfg[0] = kBlock;
-    cfg[1] = v[i].grid_x;
-    cfg[2] = v[i].gram_block;
-    cfg[3] = v[i].lds_policy;
+    cfg[0] = v[i].waves;
+    cfg[1] = v[i].nbuf;
+    cfg[2] = v[i].grid_x;
+    cfg[3] = v[i].gram_block;
+    cfg[4] = v[i].lds_policy;
     return LMFAO_OK;
 }
 
@@ -1781,8 +1800,8 @@ static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
     f[11] = (float)(mode == 1 ? t.gram_block : 0);
     f[12] = (float)mode;
     f[13] = (float)std::log2((double)child_keys + 1.0);
-    f[14] = (float)std::log2(rows * (double)std::max(1, P.n_feat) * 4.0 + 1.0);
-    f[15] = (float)P.n_feat;
+    f[14] = (float)t.waves;
+    f[15] = (float)t.nbuf;
 }
 
 extern "C" lmfao_status lmfao_candidate_features(const lmfao_ctx *c, int32_t i, float *features) {
@@ -1835,13 +1854,16 @@ extern "C" lmfao_status lmfao_autotune(lmfao_ctx *c, void *hip_stream, const cha
             float f[LMFAO_N_FEATURES];
             features_of(c, cands[i], f);
             for (int k = 0; k < LMFAO_N_FEATURES; ++k) std::fprintf(db, "%.6g,", f[k]);
-            std::fprintf(db, "%d,%d,%d,%.6f\n", cands[i].grid_x, cands[i].gram_block, cands[i].lds_policy, ms);
+            std::fprintf(db, "%d,%d,%d,%d,%d,%.6f\n", cands[i].waves, cands[i].nbuf, cands[i].grid_x, cands[i].gram_block,
+                         cands[i].lds_policy, ms);
         }
         if (ms < best_ms) { best_ms = ms; best_i = (int)i; }
     }
     if (db) std::fclose(db);
     if (best_i < 0) return fail(c, LMFAO_ERR_HIP, "no candidate ran");
     lmfao_status s = select_cfg(c, cands[best_i]);
+    if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);   // leave the views current for timing
+    if (s == LMFAO_OK) s = lmfao_sync(c);
     if (s != LMFAO_OK) return s;
     if (best) *best = best_i;
     return LMFAO_OK;
@@ -1905,6 +1927,8 @@ extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, 
     }
     if (bi < 0) return LMFAO_OK;
     lmfao_status s = select_cfg(c, cands[bi]);
+    if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);
+    if (s == LMFAO_OK) s = lmfao_sync(c);
     if (s != LMFAO_OK) return s;
     if (best) *best = bi;
     return LMFAO_OK;

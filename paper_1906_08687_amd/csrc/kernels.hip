@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     const auto aux_cols = cst(d.aux_cols);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: LDS bases stay scalar
     const int nwaves = blockDim.x >> 6;
     const int part = blockIdx.y;
     const bool do_gram = MODE != 0 && part == d.gram_part && d.n_gram > 0;
@@ -356,33 +356,43 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         for (int c = 0; c < kMaxChild; ++c)
             if (c < s.n_child) fk[c] = gld(children[c].fk)[row];
     };
+    // copies address scalar bases plus 32-bit per-lane byte offsets (row * 4 and
+    // key * record bytes stay below 4 GiB: the planner bounds table sizes)
     auto issue = [&](int64_t tile, int buf) {
-        const int64_t row = min(w_begin + tile * 64 + lane, last_row);
+        const uint32_t roff = (uint32_t)min(w_begin + tile * 64 + lane, last_row) * 4u;
         uint32_t *fb = W + d.w_fact + buf * d.n_fact * kColPitch;
-        for (int f0 = 0; f0 < d.n_fact; f0 += 8) {
+        // the pointer array is padded to 16 entries: the first 16 bases load together,
+        // unconditionally, before any copy is issued
+        const char *fp[16];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (f0 + i < d.n_fact) lds_dma4(fact_cols[f0 + i] + row, fb + (f0 + i) * kColPitch);
-        }
+        for (int f = 0; f < 16; ++f) fp[f] = reinterpret_cast<const char *>(fact_cols[f]);
+#pragma unroll
+        for (int f = 0; f < 16; ++f)
+            if (f < d.n_fact) lds_dma4(fp[f] + roff, fb + f * kColPitch);
+        for (int f = 16; f < d.n_fact; ++f) lds_dma4(reinterpret_cast<const char *>(fact_cols[f]) + roff, fb + f * kColPitch);
         uint32_t *ab = W + d.w_aux + buf * d.n_aux * kColPitch;
-        for (int a0 = 0; a0 < d.n_aux; a0 += 8) {
+        const char *ap[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (a0 + i < d.n_aux) lds_dma4(aux_cols[a0 + i] + row, ab + (a0 + i) * kColPitch);
-        }
+        for (int a = 0; a < 8; ++a) ap[a] = reinterpret_cast<const char *>(aux_cols[a]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (a < d.n_aux) lds_dma4(ap[a] + roff, ab + a * kColPitch);
+        for (int a = 8; a < d.n_aux; ++a) lds_dma4(reinterpret_cast<const char *>(aux_cols[a]) + roff, ab + a * kColPitch);
         uint32_t *rb = W + d.w_rec + buf * d.n_quads * 256;
 #pragma unroll
         for (int c = 0; c < kMaxChild; ++c) {
             if (c < s.n_child) {
                 const AS_CONST ChildSrc &ch = children[c];
                 const int32_t k = fk[c];
-                const uint32_t *rec = (k >= 0 && k < ch.n_keys) ? ch.rec + (int64_t)k * ch.stride : d.zero_rec;
+                const bool hit = k >= 0 && k < ch.n_keys;
+                const char *base = reinterpret_cast<const char *>(hit ? ch.rec : d.zero_rec);
+                const uint32_t koff = hit ? (uint32_t)k * (uint32_t)ch.stride * 4u : 0u;
                 const int nq = ch.stride >> 2;
                 uint32_t *dst = rb + ch.quad_base * 256;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (q < nq) lds_dma16(rec + 4 * q, dst + q * 256);
-                for (int q = 4; q < nq; ++q) lds_dma16(rec + 4 * q, dst + q * 256);
+                    if (q < nq) lds_dma16(base + koff + 16 * q, dst + q * 256);
+                for (int q = 4; q < nq; ++q) lds_dma16(base + koff + 16 * q, dst + q * 256);
             }
         }
     };
@@ -483,6 +493,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             }
         }
         if (MODE >= 2 && do_gram) {
+            const bool all_rows = vm == ~0ull;   // wave-uniform: the common case needs no masking
 #pragma unroll 1
             for (int ks = 0; ks < 2; ++ks) {
                 const int row0 = 32 * ks + 8 * (lane >> 4);
@@ -490,11 +501,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 bf16x8 fh[NT], fl[NT];
 #pragma unroll
                 for (int t2 = 0; t2 < NT; ++t2) {
-                    const int w0 = lt[t2].base + buf * lt[t2].step + row0 * lt[t2].stride;
                     const int st = lt[t2].stride;
+                    const float *p = fsm + lt[t2].base + buf * lt[t2].step + row0 * st;
                     float x[8];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) x[i] = ((vbits >> i) & 1u) ? fsm[w0 + i * st] : 0.f;
+                    for (int i = 0; i < 8; ++i) { x[i] = *p; p += st; }
+                    if (!all_rows) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (!((vbits >> i) & 1u)) x[i] = 0.f;
+                    }
                     split_bf16x8(x, fh[t2], fl[t2]);
                 }
                 int ih = 0;
@@ -667,22 +683,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // ---------------------------------------------------------------------------
 
 __global__ void merge_kernel(const MergeDesc *__restrict__ dp) {
+    // one wave per covariance entry: lane l sums partials l, l+64, ... in order, then a
+    // fixed shuffle tree combines the lanes (the same order every run: deterministic)
     const MergeDesc &d = *dp;
     const int n = d.n_gram;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (e < n * n) {
         const int i = e / n, j = e % n;
         if (i <= j) {
             double s = 0.0;
-            for (int b = 0; b < d.grid; ++b) s += d.gram_partial[(int64_t)b * n * n + e];
-            d.gram[i * n + j] = s;
-            d.gram[j * n + i] = s;
+            for (int b = lane; b < d.grid; b += 64) s += gld(d.gram_partial)[(int64_t)b * n * n + e];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) {
+                gst(d.gram)[i * n + j] = s;
+                gst(d.gram)[j * n + i] = s;
+            }
         }
     }
-    if (e == 0 && d.count_partial) {
+    if (e == 0 && lane == 0 && d.count_partial) {
         unsigned long long t = 0;
-        for (int b = 0; b < d.grid; ++b) t += d.count_partial[b];
-        *d.count = t;
+        for (int b = 0; b < d.grid; ++b) t += gld(d.count_partial)[b];
+        *gst(d.count) = t;
     }
 }
 
@@ -781,8 +803,8 @@ hipError_t set_root_lds_limit(RootKernel k, size_t bytes) {
 }
 
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st) {
-    const int n = n_gram * n_gram > 0 ? n_gram * n_gram : 1;
-    hipLaunchKernelGGL(merge_kernel, dim3((n + 255) / 256), dim3(256), 0, st, desc);
+    const int n = n_gram * n_gram > 0 ? n_gram * n_gram : 1;   // entries, 4 per 256-thread workgroup
+    hipLaunchKernelGGL(merge_kernel, dim3((n + 3) / 4), dim3(256), 0, st, desc);
     return hipGetLastError();
 }
 

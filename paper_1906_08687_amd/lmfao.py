@@ -73,7 +73,8 @@ class _Stats(ctypes.Structure):
                 ("views", ctypes.c_int32), ("groups", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("features", ctypes.c_int32), ("filters", ctypes.c_int32), ("tables", ctypes.c_int32),
                 ("table_cells", ctypes.c_int64), ("launches", ctypes.c_int32), ("block_rows", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("nbuf", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
 
 
 # every symbol the header declares
@@ -277,7 +278,7 @@ class Context:
         self._check(self.lib.lmfao_candidates(self.ptr, ctypes.byref(n)))
         out = []
         for i in range(n.value):
-            cfg = (ctypes.c_int32 * 4)()
+            cfg = (ctypes.c_int32 * 5)()
             self._check(self.lib.lmfao_candidate(self.ptr, i, cfg))
             out.append(list(cfg))
         return out
@@ -379,3 +380,57 @@ def upload_columns(db, dev):
         for c in r.columns:
             out[(r.name, c.attr)] = torch.from_numpy(np.ascontiguousarray(c.data)).to(dev)
     return out
+
+
+# ---------------------------------------------------------------------------
+# cost-model network kernels (device tensors in, device tensors out)
+# ---------------------------------------------------------------------------
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise LmfaoError(status, what)
+
+
+def mlp_param_count(hidden: int) -> int:
+    return int(load().lmfao_mlp_param_count(hidden))
+
+
+def mlp_forward(hidden: int, params, x, stream=None):
+    """y[n] = network(x[n][16]) for fp32 device tensors."""
+    import torch
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(load().lmfao_mlp_forward(hidden, _ptr(params), _ptr(x), x.shape[0], _ptr(y), _stream_handle(stream)),
+           "mlp_forward")
+    return y
+
+
+def mlp_loss_grad(hidden: int, params, x, target, stream=None):
+    import torch
+    lib = load()
+    n = x.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty_like(params)
+    scratch = torch.empty(int(lib.lmfao_mlp_scratch_floats(hidden, n)), dtype=torch.float32, device=x.device)
+    _check(lib.lmfao_mlp_loss_grad(hidden, _ptr(params), _ptr(x), _ptr(target), n, _ptr(loss), _ptr(grad),
+                                   _ptr(scratch), _stream_handle(stream)), "mlp_loss_grad")
+    return loss, grad
+
+
+def adam_step(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().lmfao_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2,
+                                  eps, _stream_handle(stream)), "adam_step")
+
+
+def mlp_train(hidden: int, params, x, target, epochs: int, lr: float, stream=None):
+    """Full-batch Adam training on the device; returns the per-step losses."""
+    import torch
+    lib = load()
+    n = x.shape[0]
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    scratch = torch.empty(int(lib.lmfao_mlp_scratch_floats(hidden, n)), dtype=torch.float32, device=x.device)
+    losses = torch.empty(epochs, dtype=torch.float32, device=x.device)
+    _check(lib.lmfao_mlp_train(hidden, _ptr(params), _ptr(m), _ptr(v), _ptr(x), _ptr(target), n, epochs, lr,
+                               _ptr(grad), _ptr(scratch), _ptr(losses), _stream_handle(stream)), "mlp_train")
+    return losses

@@ -1,0 +1,143 @@
+"""Cost-model network: the fp64 reference pinned on the CPU, the device
+kernels checked against it, and the learned tile choice against the
+heuristic one."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+
+H_LIST = [8, 16, 32, 64]
+
+
+def _data(n=257, seed=3):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, ref.N_IN))
+    t = np.sin(x[:, 0]) + 0.5 * x[:, 1] * x[:, 2] - 0.25 * x[:, 3]
+    return x, t
+
+
+# --------------------------------------------------------------------------
+# the reference, pinned
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("h", [4, 8])
+def test_reference_gradient_matches_finite_differences(h):
+    x, t = _data(40)
+    p = ref.init(h, seed=h) + 0.01
+    loss, g = ref.loss_grad(p, x, t, h)
+    eps = 1e-6
+    for i in range(len(p)):
+        d = np.zeros_like(p)
+        d[i] = eps
+        num = (ref.loss_grad(p + d, x, t, h)[0] - ref.loss_grad(p - d, x, t, h)[0]) / (2 * eps)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(num)), (i, num, g[i])
+    assert abs(loss - np.mean((ref.forward(p, x, h) - t) ** 2)) < 1e-12
+
+
+def test_reference_constant_network_closed_form():
+    """All weights zero except b3: y = b3 everywhere, so L = mean((b3 - t)^2)
+    and the only non-zero gradient entry is dL/db3 = 2 mean(b3 - t)."""
+    h = 8
+    x, t = _data(50)
+    p = np.zeros(ref.param_count(h))
+    p[-1] = 0.7
+    loss, g = ref.loss_grad(p, x, t, h)
+    assert np.isclose(loss, np.mean((0.7 - t) ** 2))
+    assert np.isclose(g[-1], 2 * np.mean(0.7 - t))
+    assert np.all(g[:-1] == 0)
+
+
+def test_reference_adam_first_step_moves_by_lr_times_sign():
+    """With zero moments, the bias-corrected first Adam step is
+    lr * g / (|g| + eps), i.e. lr * sign(g) for |g| >> eps."""
+    g = np.array([3.0, -0.5, 2e-3, -7.0])
+    p1, m, v = ref.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
+    np.testing.assert_allclose(p1, -0.01 * np.sign(g), rtol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# device kernels against the reference
+# --------------------------------------------------------------------------
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("h", H_LIST)
+def test_device_forward_and_gradient(h):
+    import torch
+    from paper_1906_08687_amd import lmfao
+    dev = torch.device("cuda", 0)
+    x, t = _data(1001, seed=h)
+    p = ref.init(h, seed=h).astype(np.float32)
+    assert lmfao.mlp_param_count(h) == ref.param_count(h)
+    pt = torch.from_numpy(p).to(dev)
+    xt = torch.from_numpy(x.astype(np.float32)).to(dev)
+    tt = torch.from_numpy(t.astype(np.float32)).to(dev)
+    y = lmfao.mlp_forward(h, pt, xt).cpu().numpy()
+    yr = ref.forward(p.astype(np.float64), x.astype(np.float32).astype(np.float64), h)
+    np.testing.assert_allclose(y, yr, rtol=1e-4, atol=1e-4 * np.abs(yr).max())
+    loss, g = lmfao.mlp_loss_grad(h, pt, xt, tt)
+    lr_, gr = ref.loss_grad(p.astype(np.float64), x.astype(np.float32).astype(np.float64),
+                            t.astype(np.float32).astype(np.float64), h)
+    assert abs(float(loss.item()) - lr_) <= 1e-4 * lr_
+    g = g.cpu().numpy()
+    np.testing.assert_allclose(g, gr, rtol=0, atol=1e-4 * np.abs(gr).max())
+
+
+@pytest.mark.gpu
+def test_device_adam_and_training_follow_reference():
+    import torch
+    from paper_1906_08687_amd import lmfao
+    dev = torch.device("cuda", 0)
+    h = 16
+    x, t = _data(512)
+    p = ref.init(h, seed=5).astype(np.float32)
+    # one Adam step on a fixed gradient
+    g = np.random.default_rng(1).normal(size=p.size).astype(np.float32)
+    pt, gt = torch.from_numpy(p.copy()).to(dev), torch.from_numpy(g).to(dev)
+    m, v = torch.zeros_like(pt), torch.zeros_like(pt)
+    lmfao.adam_step(pt, gt, m, v, 1, 0.01)
+    lmfao.adam_step(pt, gt, m, v, 2, 0.01)
+    pr, mr, vr = ref.adam(p.astype(np.float64), g, np.zeros(p.size), np.zeros(p.size), 1, 0.01)
+    pr, mr, vr = ref.adam(pr, g, mr, vr, 2, 0.01)
+    np.testing.assert_allclose(pt.cpu().numpy(), pr, rtol=0, atol=1e-6)
+    # training: the device loss trajectory tracks the fp64 reference and decreases
+    pt = torch.from_numpy(p.copy()).to(dev)
+    xt = torch.from_numpy(x.astype(np.float32)).to(dev)
+    tt = torch.from_numpy(t.astype(np.float32)).to(dev)
+    losses = lmfao.mlp_train(h, pt, xt, tt, 60, 3e-3).cpu().numpy()
+    pr, mr, vr = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    ref_losses = []
+    for s in range(1, 61):
+        l, gr = ref.loss_grad(pr, x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64), h)
+        ref_losses.append(l)
+        pr, mr, vr = ref.adam(pr, gr, mr, vr, s, 3e-3)
+    np.testing.assert_allclose(losses, ref_losses, rtol=2e-3)
+    assert losses[-1] < 0.7 * losses[0]
+
+
+# --------------------------------------------------------------------------
+# what the trained network gains over the heuristic tile choice
+# --------------------------------------------------------------------------
+
+@pytest.mark.gpu
+def test_learned_choice_against_heuristic_on_held_out_workloads():
+    import torch
+    from datagen.configs import random_workload
+    from paper_1906_08687_amd import costmodel, lmfao
+    if not os.path.exists(costmodel.WEIGHTS):
+        pytest.skip("no trained cost model in the tree")
+    stream = torch.cuda.Stream()
+    t_heur = t_learn = 0.0
+    for j in (180, 181, 182, 183):       # held out: training uses workloads below 150
+        db, qs = random_workload(j, max_rows=2_000_000)
+        eng = lmfao.Engine(db, qs, precision="bf16x3")
+        eng.run(stream)
+        t_heur += eng.ctx.time_root_group(stream, 2, 10)
+        eng.ctx.choose_learned(costmodel.WEIGHTS, stream)
+        eng._bind()
+        eng.run(stream)
+        t_learn += eng.ctx.time_root_group(stream, 2, 10)
+    print("held-out root-scan time: heuristic %.3f ms, learned %.3f ms (gain %.2fx)" %
+          (t_heur, t_learn, t_heur / t_learn))
+    assert t_learn <= 1.15 * t_heur

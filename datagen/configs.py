@@ -2,11 +2,11 @@
 
 The paper measures on Retailer, Favorita, Yelp and TPC-DS, none of which is
 available here; these relations stand in for them: a large fact table sorted
-by its foreign keys (Appendix C: relations are given sorted by their join
+by its foreign keys (Appendix B: relations are given sorted by their join
 attributes; Section 3.5 orders join attributes by increasing domain size),
 small dimension tables with dense unique keys, continuous and categorical
 attributes, 20-bucket discretisation of continuous attributes for decision
-trees (Appendix C), and batches of the paper's application families
+trees (Appendix B), and batches of the paper's application families
 (Section 2: covariance matrix, regression-tree node, mutual information).
 
 Five workloads (all sizes are parameters; defaults are the full sizes):
@@ -353,7 +353,7 @@ def config5(n_fact: int = 50_000_000, dims: Sequence[int] = (100_000, 10_000, 1_
 
 def batch5(db: Database) -> List[Query]:
     """All marginal and pairwise COUNT GROUP BY queries over the categorical
-    attributes (Section 2, mutual information, equation (5))."""
+    attributes (Section 2, mutual information, equation (7))."""
     cats = cat_attrs(db)
     qs = [Query(groupby=[GroupBy(c)]) for c in cats]
     for i in range(len(cats)):

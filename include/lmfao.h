@@ -164,9 +164,10 @@ typedef struct {
     int32_t planner;       /* HEURISTIC: fixed rules; AUTOTUNE: time every candidate tile config
                               on the device during lmfao_plan_tune; LEARNED: cost-model prediction
                               (falls back to HEURISTIC without a model) */
-    int32_t block_rows;    /* override: rows per tile (0 = planner's choice) */
+    int32_t block_rows;    /* reserved, must be 0: rows per workgroup follow from grid_blocks */
     int32_t grid_blocks;   /* override: workgroups of the fact scan (0 = planner's choice) */
-    int32_t gram_block;    /* override: FP32 register block edge 2/4/6/8 (0 = planner's choice) */
+    int32_t gram_block;    /* override: FP32 register block edge 2/4/6/8 (0 = planner's choice);
+                              other values are INVALID_ARG */
     const char *cost_model;/* LEARNED: path of the weights file written by lmfao_train_cost_model */
 } lmfao_plan_opts;
 
@@ -185,7 +186,10 @@ typedef struct {
     int32_t tables;              /* grouped result tables */
     int64_t table_cells;         /* cells over all grouped tables */
     int32_t launches;            /* kernel launches per execution */
-    int32_t block_rows, grid_blocks, gram_block, lds_tables; /* chosen tile configuration */
+    int32_t block_rows;          /* fact rows per workgroup of the root scan (a multiple of 64 * waves) */
+    int32_t grid_blocks;         /* workgroups of the root scan */
+    int32_t gram_block;          /* FP32: register block edge; BF16: padded feature count */
+    int32_t lds_tables;          /* grouped tables: 0 global atomics, 1 greedy LDS, 2 partitioned LDS */
     int32_t waves;               /* waves per workgroup of the root scan */
     int32_t nbuf;                /* staging buffers per wave (2: next tile copied during this one) */
     int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */

@@ -9,7 +9,7 @@
 //                  carries the join key and exactly the parts of the query
 //                  that live in T_i -- its continuous factors, its group-by
 //                  components and its conjuncts, evaluated once per key
-//                  (Appendix D, "evaluate each UDAF once");
+//                  (Appendix C, avoiding repeated UDAF evaluation);
 //   merge          views with the same direction and group-by attributes are
 //                  merged (Section 3.4, cases 1-3): per child relation the
 //                  plan keeps ONE view record holding the union of what all
@@ -22,7 +22,7 @@
 //   levels         a relation's group depends on its children's groups; the
 //                  groups of one tree level are independent (Section 1.2,
 //                  parallelization) and run in one launch when batched.
-// Code specialisation (Section 3.5, Appendix D) is replaced by templated
+// Code specialisation (Section 3.5, Appendix C) is replaced by templated
 // kernels and runtime descriptors.
 #include <hip/hip_runtime.h>
 
@@ -494,11 +494,13 @@ extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int3
 // planner
 // ============================================================================
 
+// FP32 register block edge: GB x GB accumulators per lane.  GB = 8 (64
+// accumulators plus operands) spills on gfx950, so 6 is the largest used
+// unless fewer block pairs than lanes would leave the wave idle.
 static int estimate_gram_block(int n_gram) {
     if (n_gram <= 8) return 2;
     if (n_gram <= 24) return 4;
-    if (n_gram <= 36) return 6;
-    return 8;
+    return 6;
 }
 
 static bool gram_block_ok(int n_gram, int gb) {
@@ -1501,7 +1503,8 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     o.planner = LMFAO_HEURISTIC;
     if (opts) o = *opts;
     if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X4 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
-        o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED)
+        o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED || o.block_rows != 0 || o.grid_blocks < 0 ||
+        !(o.gram_block == 0 || o.gram_block == 2 || o.gram_block == 4 || o.gram_block == 6 || o.gram_block == 8))
         return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
     invalidate(c);
     c->opts = o;
@@ -1540,7 +1543,7 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     if (P.n_gram > 0 || P.need_count) launches += 1;
     launches += 1;   // assemble
     s->launches = launches;
-    s->block_rows = kBlock;
+    s->block_rows = (int32_t)std::min<int64_t>(P.rows_per_block, INT32_MAX);
     s->grid_blocks = P.grid_x;
     s->gram_block = P.mode == 1 ? P.gram_block : (P.mode >= 2 ? 16 * P.n_tiles16 : 0);
     s->lds_tables = P.lds_policy;

@@ -9,11 +9,11 @@
 //                        views are looked up by key and every outgoing view
 //                        is updated: the covariance block sum x x^T over the
 //                        features x = [1, continuous attributes] (Section 2,
-//                        equation (2) and Appendix D's lockstep aggregate
+//                        equation (2) and Appendix C's lockstep aggregate
 //                        arrays), the total count, and grouped tables
 //                        (COUNT and SUM of monomials GROUP BY components,
 //                        optionally restricted by a filter; equations (3),
-//                        (4), (5), (8)).
+//                        (4), (7), (8)).
 //  * merge_kernel        fp64 cross-workgroup reduction of the covariance
 //                        partials and counts (the domain-parallel partition
 //                        merge implied by Section 1.2)

@@ -1,0 +1,289 @@
+"""The C ABI without a GPU: every declared symbol is exported, planning is
+host-only and deterministic, and every documented error path returns its
+status code.  Column pointers here are placeholders: planning never reads
+device memory, and binding without a device is refused."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1906_08687_amd import lmfao
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lmfao.h")
+FAKE = 0x100000          # a placeholder device address, never dereferenced on the host
+
+
+def _lib():
+    if not os.path.exists(lmfao.LIB_PATH):
+        pytest.skip("liblmfao.so not built")
+    return lmfao.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lmfao_\w+)\s*\(", text)))
+
+
+def test_header_declares_exactly_the_binding_symbols():
+    assert declared_functions() == sorted(lmfao.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_library_loads_only_from_the_tree_and_fails_loudly_when_missing(tmp_path):
+    with pytest.raises(ImportError):
+        saved = lmfao._lib
+        lmfao._lib = None
+        try:
+            lmfao.load(str(tmp_path / "missing.so"))
+        finally:
+            lmfao._lib = saved
+
+
+# --------------------------------------------------------------------------
+# a small star schema built from placeholder pointers
+# --------------------------------------------------------------------------
+
+def star(ctx, fact_rows=1000):
+    """F(k1, k2, f0, f1, fc) with D1(k1, a0, a1, ac) and D2(k2, b0)."""
+    ctx.add_relation("F", fact_rows, [("k1", lmfao.I32, lmfao.KEY, 50, FAKE), ("k2", lmfao.I32, lmfao.KEY, 20, FAKE),
+                                      ("f0", lmfao.F32, lmfao.CONT, 0, FAKE), ("f1", lmfao.F32, lmfao.CONT, 0, FAKE),
+                                      ("fc", lmfao.I32, lmfao.CAT, 7, FAKE)])
+    ctx.add_relation("D1", 50, [("k1", lmfao.I32, lmfao.KEY, 50, FAKE), ("a0", lmfao.F32, lmfao.CONT, 0, FAKE),
+                                ("a1", lmfao.F32, lmfao.CONT, 0, FAKE), ("ac", lmfao.I32, lmfao.CAT, 5, FAKE)])
+    ctx.add_relation("D2", 20, [("k2", lmfao.I32, lmfao.KEY, 20, FAKE), ("b0", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    ctx.set_join_tree([(0, 1), (0, 2)])
+
+
+def covariance(attrs):
+    from datagen.configs import covariance_queries
+    return covariance_queries(attrs)
+
+
+def new_ctx():
+    _lib()
+    return lmfao.Context(0)
+
+
+def test_plan_is_host_only_and_reports_the_batch():
+    from datagen.schema import Agg, GroupBy, Pred, Query
+    ctx = new_ctx()
+    star(ctx)
+    feats = ["f0", "f1", "a0", "a1", "b0"]
+    qs = covariance(feats)
+    qs += [Query(groupby=[GroupBy("ac")], aggs=[Agg.monomial("f0")]),
+           Query(groupby=[GroupBy("fc"), GroupBy("ac")]),
+           Query(groupby=[GroupBy("b0", [-1.0, 0.0, 1.0])], aggs=[Agg.monomial("a1")]),
+           Query(where=[Pred("a0", "le", 0.5)], aggs=[Agg.monomial("f1")])]
+    for q in qs:
+        ctx.add_query(q)
+    n = len(feats)
+    for prec in ("fp32", "bf16x3", "bf16x4"):
+        for sched in ("plain", "batched"):
+            ctx.plan(prec, sched)
+            s = ctx.stats()
+            assert s["app_aggregates"] == sum(1 + len(q.aggs) for q in qs)      # one COUNT per query
+            assert s["features"] == n + 1                  # the constant 1 plus the attributes
+            # two child views, the covariance output, one output view per grouped table
+            assert s["tables"] == 4 and s["table_cells"] == 5 + 7 * 5 + 4 + 1
+            assert s["views"] == 2 + 1 + s["tables"] and s["filters"] == 1
+            assert s["groups"] == 3 and s["levels"] == 2
+            assert ctx.workspace_size() > 0 and ctx.result_size() > 0
+            if sched == "batched":
+                assert s["launches"] >= 1
+    # dense output cells: the product of the group-by domains
+    expect = [1] * len(covariance(feats)) + [5, 7 * 5, 4, 1]
+    for qid, cells in enumerate(expect):
+        nc, na, co, so = ctx.result_layout(qid)
+        assert nc == cells, qid
+        assert co % 8 == 0 and so % 8 == 0
+    # the planner is deterministic
+    a = (ctx.workspace_size(), ctx.result_size(), ctx.stats())
+    ctx.plan("fp32", "plain")
+    ctx.plan("bf16x4", "batched")
+    assert (ctx.workspace_size(), ctx.result_size(), ctx.stats()) == a
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tile_candidates_are_distinct_and_featurised(precision):
+    ctx = new_ctx()
+    star(ctx, fact_rows=50_000_000)                  # large enough that no candidate grid is clamped
+    for q in covariance(["f0", "f1", "a0", "b0"]):
+        ctx.add_query(q)
+    ctx.plan(precision, "batched")
+    cands = ctx.candidates()
+    assert len(cands) >= 4
+    assert len({tuple(c) for c in cands}) == len(cands)
+    for i, c in enumerate(cands):
+        waves, nbuf, grid, gb, policy = c
+        assert waves in (1, 2, 4) and nbuf in (1, 2) and grid > 0
+        f = ctx.candidate_features(i)
+        assert f.shape == (16,) and all(map(lambda v: v == v, f))
+        assert f[14] == waves and f[15] == nbuf
+        ctx.select_candidate(i)
+        s = ctx.stats()
+        assert (s["waves"], s["nbuf"]) == (waves, nbuf)
+        # rows per workgroup: whole 64-row wave tiles; the grid covers the fact exactly
+        rows, br, gx = 50_000_000, s["block_rows"], s["grid_blocks"]
+        assert br % (64 * waves) == 0 and gx <= grid
+        assert (gx - 1) * br < rows <= gx * br
+        if precision == "fp32":
+            assert s["gram_block"] == gb
+        else:
+            assert gb == 0 and s["gram_block"] == 16         # 5 features padded to one 16-wide MFMA tile
+
+
+def test_bind_and_execute_need_a_device_and_a_plan():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only error paths")
+    ctx = new_ctx()
+    star(ctx)
+    with pytest.raises(lmfao.LmfaoError) as e:
+        ctx.plan()
+    assert e.value.code == "STATE"                   # no queries yet
+    ctx.add_query(covariance(["f0"])[0])
+    with pytest.raises(lmfao.LmfaoError) as e:
+        ctx.bind(FAKE, 1 << 20, FAKE, 1 << 20)
+    assert e.value.code == "STATE"                   # not planned
+    ctx.plan()
+    with pytest.raises(lmfao.LmfaoError) as e:
+        ctx.bind(FAKE, 1 << 30, FAKE, 1 << 30)
+    assert e.value.code == "HIP"                     # no device
+    for call in (lambda: ctx.execute(None), lambda: ctx.sync(), lambda: ctx.time_root_group(None, 1, 1),
+                 lambda: ctx.autotune(None, None, 1)):
+        with pytest.raises(lmfao.LmfaoError) as e:
+            call()
+        assert e.value.code == "STATE"
+
+
+# --------------------------------------------------------------------------
+# documented error statuses
+# --------------------------------------------------------------------------
+
+def expect(code, fn):
+    with pytest.raises(lmfao.LmfaoError) as e:
+        fn()
+    assert e.value.code == code, str(e.value)
+    assert str(e.value).split(": ", 1)[1]            # a message accompanies every error
+
+
+def test_relation_errors():
+    ctx = new_ctx()
+    expect("TYPE", lambda: ctx.add_relation("A", 10, [("x", lmfao.I32, lmfao.CONT, 0, FAKE)]))
+    expect("TYPE", lambda: ctx.add_relation("A", 10, [("k", lmfao.F32, lmfao.KEY, 10, FAKE)]))
+    expect("INVALID_ARG", lambda: ctx.add_relation("A", 10, [("c", lmfao.I32, lmfao.CAT, 0, FAKE)]))
+    expect("INVALID_ARG", lambda: ctx.add_relation("A", 10, [("x", lmfao.F32, lmfao.CONT, 0, 0)]))
+    expect("INVALID_ARG", lambda: ctx.add_relation("A", 10, [("x", lmfao.F32, lmfao.CONT, 0, FAKE),
+                                                             ("x", lmfao.F32, lmfao.CONT, 0, FAKE)]))
+    expect("TOO_LARGE", lambda: ctx.add_relation("A", (1 << 40) + 1, [("x", lmfao.F32, lmfao.CONT, 0, FAKE)]))
+    ctx.add_relation("A", 10, [("x", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    expect("INVALID_ARG", lambda: ctx.add_relation("A", 10, [("y", lmfao.F32, lmfao.CONT, 0, FAKE)]))
+    # an empty relation needs no data pointer
+    ctx.add_relation("E", 0, [("z", lmfao.F32, lmfao.CONT, 0, 0)])
+
+
+def three(ctx, shared=("k1", "k2"), d2_extra=None):
+    ctx.add_relation("F", 100, [("k1", lmfao.I32, lmfao.KEY, 10, FAKE), ("k2", lmfao.I32, lmfao.KEY, 10, FAKE),
+                                ("x", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    ctx.add_relation("D1", 10, [(shared[0], lmfao.I32, lmfao.KEY, 10, FAKE), ("y", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    cols = [(shared[1], lmfao.I32, lmfao.KEY, 10, FAKE), ("z", lmfao.F32, lmfao.CONT, 0, FAKE)]
+    if d2_extra:
+        cols.append(d2_extra)
+    ctx.add_relation("D2", 10, cols)
+
+
+@pytest.mark.parametrize("edges,code", [
+    ([(0, 1)], "NOT_ACYCLIC"),                       # m-1 edges needed
+    ([(0, 1), (0, 2), (1, 2)], "NOT_ACYCLIC"),
+    ([(0, 1), (2, 1)], "NOT_ACYCLIC"),               # D1 with two parents
+    ([(1, 2), (2, 1)], "NOT_ACYCLIC"),               # a cycle, F unconnected
+    ([(0, 1), (0, 7)], "INVALID_ARG"),
+])
+def test_join_tree_shape_errors(edges, code):
+    ctx = new_ctx()
+    three(ctx)
+    expect(code, lambda: ctx.set_join_tree(edges))
+
+
+def test_join_tree_attribute_errors():
+    ctx = new_ctx()                                  # F-D1 share no attribute
+    three(ctx, shared=("k9", "k2"))
+    expect("UNSUPPORTED", lambda: ctx.set_join_tree([(0, 1), (0, 2)]))
+    ctx = new_ctx()                                  # join attribute continuous in the child
+    ctx.add_relation("F", 100, [("k1", lmfao.I32, lmfao.KEY, 10, FAKE), ("x", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    ctx.add_relation("D1", 10, [("k1", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    expect("TYPE", lambda: ctx.set_join_tree([(0, 1)]))
+    ctx = new_ctx()                                  # y held by D1 and D2 only: running intersection fails
+    three(ctx, d2_extra=("y", lmfao.F32, lmfao.CONT, 0, FAKE))
+    expect("NOT_ACYCLIC", lambda: ctx.set_join_tree([(0, 1), (0, 2)]))
+
+
+def test_state_errors():
+    from datagen.schema import Agg, Query
+    ctx = new_ctx()
+    expect("STATE", lambda: ctx.set_join_tree([]))   # no relations
+    three(ctx)
+    expect("STATE", lambda: ctx.add_query(Query(aggs=[Agg.monomial("x")])))
+    ctx.set_join_tree([(0, 1), (0, 2)])
+    expect("STATE", lambda: ctx.set_join_tree([(0, 1), (0, 2)]))
+    expect("STATE", lambda: ctx.add_relation("G", 1, [("w", lmfao.F32, lmfao.CONT, 0, FAKE)]))
+
+
+def test_query_errors():
+    from datagen.schema import Agg, GroupBy, Pred, Query
+    ctx = new_ctx()
+    three(ctx)
+    ctx.set_join_tree([(0, 1), (0, 2)])
+    expect("UNKNOWN_ATTR", lambda: ctx.add_query(Query(aggs=[Agg.monomial("nope")])))
+    expect("UNKNOWN_ATTR", lambda: ctx.add_query(Query(groupby=[GroupBy("nope")])))
+    expect("UNKNOWN_ATTR", lambda: ctx.add_query(Query(where=[Pred("nope", "le", 0.0)])))
+    expect("TYPE", lambda: ctx.add_query(Query(groupby=[GroupBy("y")])))                  # continuous, no thresholds
+    expect("TYPE", lambda: ctx.add_query(Query(aggs=[Agg.monomial("k1")])))               # key as a factor
+    expect("INVALID_ARG", lambda: ctx.add_query(Query(groupby=[GroupBy("y", [1.0, 0.0])])))
+    expect("INVALID_ARG", lambda: ctx.add_query(Query(groupby=[GroupBy("y", [1.0, 1.0])])))
+    # a term names at most two factors: n_factors = 3 is refused before the array is read
+    names = (ctypes.c_char_p * 2)(b"x", b"y")
+    term = (lmfao._Term * 1)(lmfao._Term(1.0, 3, names))
+    agg = (lmfao._Agg * 1)(lmfao._Agg(1, term))
+    q = lmfao._Query(0, None, 0, None, 1, agg)
+    qid = ctypes.c_int32()
+    assert ctx.lib.lmfao_add_query(ctx.ptr, ctypes.byref(q), ctypes.byref(qid)) == -6
+    ctx.add_query(Query(aggs=[Agg.monomial("x", "z")]))
+    ctx.plan()
+
+
+def test_plan_option_errors():
+    ctx = new_ctx()
+    star(ctx)
+    ctx.add_query(covariance(["f0"])[1])
+    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None)
+    for field, bad in (("precision", 3), ("schedule", 2), ("planner", 9), ("block_rows", 128), ("grid_blocks", -1),
+                       ("gram_block", 5)):
+        x = lmfao._PlanOpts.from_buffer_copy(o)
+        setattr(x, field, bad)
+        assert ctx.lib.lmfao_plan(ctx.ptr, ctypes.byref(x)) == -1, field
+    assert ctx.lib.lmfao_plan(ctx.ptr, ctypes.byref(o)) == 0
+
+
+def test_plan_size_limits():
+    from datagen.schema import Agg, Query
+    ctx = new_ctx()
+    ctx.add_relation("F", (1 << 30) + 1, [("x", lmfao.F32, lmfao.CONT, 0, FAKE)])
+    ctx.set_join_tree([])
+    ctx.add_query(Query(aggs=[Agg.monomial("x")]))
+    expect("TOO_LARGE", lambda: ctx.plan())
+
+
+def test_mlp_parameter_count_matches_reference():
+    from oracle import mlp as ref
+    _lib()
+    for h in (1, 8, 32, 64):
+        assert lmfao.mlp_param_count(h) == ref.param_count(h)

@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x4"],
+                    help="split form of the full form: three products (hi*hi + hi*lo + lo*hi) or four (+ lo*lo)")
     ap.add_argument("--forms", default="both", choices=["both", "full"],
                     help="full: skip the plain form (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -109,7 +111,7 @@ def main():
         del plain
 
     # full form: bf16x3 on MFMA, batched in a hipGraph, learned (or autotuned) tiles
-    full = Engine(db, qs, precision="bf16x3", schedule="batched", columns=cols)
+    full = Engine(db, qs, precision=args.precision, schedule="batched", columns=cols)
     full.ctx.execute(stream)
     full.ctx.sync()
     chosen = "heuristic"
@@ -124,7 +126,7 @@ def main():
     res_full = full.results()
     root_ms = full.ctx.time_root_group(stream, 2, 10)
     stats = full.stats()
-    print("[bench] full bf16x3/batched/%s: %.3f ms/step, root scan %.3f ms" % (chosen, t_full * 1e3, root_ms),
+    print("[bench] full %s/batched/%s: %.3f ms/step, root scan %.3f ms" % (args.precision, chosen, t_full * 1e3, root_ms),
           file=sys.stderr, flush=True)
 
     # accuracy of both forms against the oracle on sampled aggregates over the full join
@@ -176,7 +178,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3-split/f32-acc/f64-merge",
+        "dtype": "%s-split/f32-acc/f64-merge" % args.precision,
         "data": "synthetic (seeded; workload 4 recipe)",
         "config": {"workload": "covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with "
                                "4 dims (1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates",
@@ -190,7 +192,8 @@ def main():
         "errors_vs_oracle": errors,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "root_scan_kernel (bf16x3)", "algorithmic_bytes": alg, "kernel_ms": root_ms},
+                     "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % args.precision,
+                     "algorithmic_bytes": alg, "kernel_ms": root_ms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -193,6 +193,7 @@ typedef struct {
     int32_t waves;               /* waves per workgroup of the root scan */
     int32_t nbuf;                /* staging buffers per wave (2: next tile copied during this one) */
     int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */
+    int32_t dedicated_scan;      /* 1: the covariance-only root scan runs on the dedicated BF16 kernel */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);

@@ -188,6 +188,53 @@ struct RootDesc {
     uint32_t *err;
 };
 
+// ---- covariance-only root scan ------------------------------------------------
+//
+// When the root group is the covariance block (and the total count) alone and
+// the block is computed in BF16 on matrix cores, a dedicated scan runs it.  Its
+// features live in "slots": [fact features][child record features][the
+// constant 1][zero padding], so that a 16-wide MFMA tile draws all of its
+// lanes from one kind of source where the counts allow.  Fact slots are loaded
+// from HBM straight into registers in the MFMA operand layout; record slots
+// and the constant slot are read out of LDS, where child view records are
+// gathered with buffer loads that bypass registers.
+
+constexpr int kGramMaxChild = 4;
+constexpr int kGramMaxSlots = 64;
+constexpr int kQuadBytes = 1040;  // one 16-byte quad of 64 rows, plus 16 bytes of bank skew
+
+struct GramSlot {
+    int32_t fact;         // >= 0: fact column of this slot; -1: read from LDS
+    int32_t lds;          // LDS byte offset of row 0 (record buffer relative when per_buf)
+    int32_t per_buf;      // 1: inside a wave's record buffer; 0: the block's constant quad
+    int32_t feat;         // staged feature whose covariance row this slot feeds; -1: padding
+};
+
+struct GramChild {
+    const int32_t *fk;    // foreign-key column of the root relation
+    const uint32_t *rec;  // child view records
+    uint32_t n_keys;      // records (keys >= n_keys read as a zero record: no join)
+    uint32_t rec_bytes;   // bytes per record (multiple of 16)
+    int32_t quad0;        // first quad of this child in a record buffer
+    int32_t n_quads;
+};
+
+struct GramDesc {
+    int64_t n_rows;
+    int64_t rows_per_block;      // multiple of 64 * waves
+    int32_t n_child;
+    int32_t n_fact;              // fact slots [0, n_fact)
+    int32_t n_gram;              // staged features (rows of the covariance block)
+    int32_t do_count;
+    int32_t lds_wave0;           // byte offset of wave 0's record buffer (after the constant quad)
+    int32_t wave_bytes;          // one record buffer: n_quads * kQuadBytes
+    GramChild ch[kGramMaxChild];
+    GramSlot slot[kGramMaxSlots];
+    const float *const *fact_cols;       // [n_fact]
+    double *gram_partial;                // [grid][n_gram * n_gram], entries i <= j
+    unsigned long long *count_partial;   // [grid]
+};
+
 // ---- final merge and result assembly -----------------------------------------
 
 struct MergeDesc {

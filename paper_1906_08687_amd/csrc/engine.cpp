@@ -53,6 +53,10 @@ hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hi
 hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, int waves, size_t lds_bytes,
                        hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
+typedef void (*GramKernel)(const GramDesc *);
+GramKernel gram_kernel(int nt, int nf, bool x4);
+hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st);
+hipError_t set_gram_lds_limit(GramKernel k, size_t bytes);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
 hipError_t launch_assemble(const AssembleDesc *desc, int n_out, hipStream_t st);
 // cost-model network (mlp.hip)
@@ -183,6 +187,10 @@ struct RootLaunch {         // one launch of the root scan (batched: one; plain:
     int single_table = -1;           // plain mode: the one table of this launch
     bool with_gram = false;
     size_t desc_off = 0;
+    // covariance-only launch on the dedicated BF16 scan (slot tiles gnt, fact tiles gnf)
+    bool gram = false;
+    int gnt = 0, gnf = 0;
+    GramDesc gdesc;
 };
 
 struct Plan {
@@ -218,6 +226,7 @@ struct Plan {
     int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
     TileCfg cfg;                      // chosen tile configuration
     int gram_block = 4, n_tiles16 = 1, mode = 0, lds_policy = 0, parts = 1, nbuf = 2, waves = 2;
+    int gram_waves = 4;          // waves per workgroup of the dedicated covariance scan
     int grid_x = 1;
     int64_t rows_per_block = kBlock;
     std::vector<RootLaunch> root_launches;
@@ -912,6 +921,29 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
     (void)c;
 }
 
+// The dedicated covariance scan applies to a BF16 covariance block of at most 64
+// features (16 to 48 of them from the root relation rounded to whole 16-wide tiles:
+// at most 2 such tiles), at most kGramMaxChild children with keys below 2^24, and a
+// root of at least 64 rows.  *nt and *nf receive its slot tiles and fact tiles.
+static bool gram_eligible(const lmfao_ctx *c, const Plan &P, int *nt, int *nf) {
+    if (P.mode < 2 || P.n_gram <= 0 || P.n_gram > kGramMaxSlots) return false;
+    if ((int)P.children[P.root].size() > kGramMaxChild) return false;
+    if (c->rels[P.root].n_rows < 64) return false;
+    for (int ch : P.children[P.root])
+        if (P.n_keys[ch] >= (1 << 24) || P.rec_stride[ch] * 4 > 4096) return false;
+    const int n_fact = (int)P.own_feats[P.root].size();
+    *nt = (P.n_gram + 15) / 16;
+    *nf = (n_fact + 15) / 16;
+    return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, P.mode == 3) != nullptr;
+}
+
+static size_t gram_lds_bytes(const Plan &P, int waves) {
+    int quads = 0;
+    for (int ch : P.children[P.root]) quads += P.rec_stride[ch] / 4;
+    const size_t stage = 1024 + (size_t)waves * quads * kQuadBytes;
+    return std::max(stage, (size_t)P.n_gram * P.n_gram * 8);
+}
+
 static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     Plan &P = c->plan;
     const Rel &root = c->rels[P.root];
@@ -950,6 +982,9 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     }
     const int budget = table_words_fit(c, P, P.mode, p1, has_tables, P.nbuf, P.waves);
     place_tables(c, P, P.lds_policy, budget);
+    int gnt = 0, gnf = 0;
+    P.gram_waves = cfg.waves > 0 ? cfg.waves : 4;
+    const bool gram_ok = gram_eligible(c, P, &gnt, &gnf) && gram_lds_bytes(P, P.gram_waves) <= c->lds_limit;
     // root launches
     P.root_launches.clear();
     auto make_launch = [&](bool with_gram, const std::vector<int> &fams, int single_table) {
@@ -972,14 +1007,24 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, w[p]);
             parts = P.parts;
         }
-        const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
-        L.lds_bytes = (size_t)Ly.total * 4;
+        L.gram = with_gram && gram_ok && !L.tables;
+        int occ_waves = 8;   // resident waves per CU the kernel's registers allow
+        if (L.gram) {
+            L.gnt = gnt;
+            L.gnf = gnf;
+            L.waves = P.gram_waves;
+            L.lds_bytes = gram_lds_bytes(P, L.waves);
+            occ_waves = gnt >= 4 ? 8 : 12;
+        } else {
+            const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
+            L.lds_bytes = (size_t)Ly.total * 4;
+            L.waves = P.waves;
+        }
         L.parts = parts;
-        L.waves = P.waves;
-        // grid: enough workgroups to cover the chip twice at its LDS-limited residency
-        const int tile = 64 * P.waves;
+        // grid: enough workgroups to cover the chip twice at its residency
+        const int tile = 64 * L.waves;
         const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, tile));
-        const int occ = (int)std::max<size_t>(1, std::min<size_t>(8 / P.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
+        const int occ = (int)std::max<size_t>(1, std::min<size_t>(occ_waves / L.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
         int gx = cfg.grid_x > 0 ? cfg.grid_x : 2 * c->n_cu * occ;
         gx = (int)std::min<int64_t>(gx, blocks_needed);
         gx = std::max(1, std::min(gx, kGridMax));
@@ -1008,7 +1053,8 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     P.rows_per_block = P.root_launches[0].desc.rows_per_block;
     for (auto &L : P.root_launches) {
         if (L.lds_bytes > c->lds_limit) return fail(c, LMFAO_ERR_TOO_LARGE, "root scan exceeds the LDS limit");
-        if (!root_kernel(L.mode, L.p1, L.tables)) return fail(c, LMFAO_ERR_TOO_LARGE, "no kernel variant for this covariance size");
+        if (!L.gram && !root_kernel(L.mode, L.p1, L.tables))
+            return fail(c, LMFAO_ERR_TOO_LARGE, "no kernel variant for this covariance size");
     }
     return LMFAO_OK;
 }
@@ -1386,6 +1432,45 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         D.count_partial = reinterpret_cast<unsigned long long *>(ws + c->off_cpart);
         D.err = err;
         L.desc = D;
+        if (L.gram) {
+            GramDesc G{};
+            G.n_rows = c->rels[r0].n_rows;
+            G.rows_per_block = D.rows_per_block;
+            G.n_child = (int)rch.size();
+            G.n_fact = (int)P.own_feats[r0].size();
+            G.n_gram = P.n_gram;
+            G.do_count = D.do_count;
+            G.lds_wave0 = 1024;
+            int quads = 0;
+            for (size_t k = 0; k < rch.size(); ++k) {
+                G.ch[k].fk = rch[k].fk;
+                G.ch[k].rec = rch[k].rec;
+                G.ch[k].n_keys = (uint32_t)rch[k].n_keys;
+                G.ch[k].rec_bytes = (uint32_t)rch[k].stride * 4u;
+                G.ch[k].quad0 = rch[k].quad_base;
+                G.ch[k].n_quads = rch[k].stride / 4;
+                quads += rch[k].stride / 4;
+            }
+            G.wave_bytes = quads * kQuadBytes;
+            // slots: fact features, then every child's subtree features, the constant, padding
+            int ns = 0;
+            for (int j = 0; j < G.n_fact; ++j) G.slot[ns++] = GramSlot{j, 0, 0, P.own_feats[r0][j]};
+            for (size_t k = 0; k < P.children[r0].size(); ++k) {
+                const int ch = P.children[r0][k];
+                for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
+                    const int w = P.rec_feat_off[ch] + i;
+                    G.slot[ns++] = GramSlot{-1, (rch[k].quad_base + w / 4) * kQuadBytes + (w % 4) * 4, 1,
+                                            P.sub_feat_lo[ch] + i};
+                }
+            }
+            G.slot[ns++] = GramSlot{-1, 0, 0, 0};
+            if (ns != P.n_gram) return fail(c, LMFAO_ERR_STATE, "covariance slots do not cover the staged features");
+            for (; ns < kGramMaxSlots; ++ns) G.slot[ns] = GramSlot{-1, 4, 0, -1};
+            G.fact_cols = D.fact_cols;
+            G.gram_partial = D.gram_partial;
+            G.count_partial = D.count_partial;
+            L.gdesc = G;
+        }
     }
     // keys/vals/filter bits are shared by all root launches: patch pointers after all were appended
     const size_t keys_off = B.vec(keys), vals_off = B.vec(vals), fb_off = B.vec(fbits);
@@ -1393,7 +1478,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         L.desc.keys = reinterpret_cast<const KeyDesc *>(dev(keys_off));
         L.desc.vals = reinterpret_cast<const ValDesc *>(dev(vals_off));
         L.desc.filt_bits = reinterpret_cast<const int32_t *>(dev(fb_off));
-        L.desc_off = B.put(&L.desc, sizeof(RootDesc));
+        L.desc_off = L.gram ? B.put(&L.gdesc, sizeof(GramDesc)) : B.put(&L.desc, sizeof(RootDesc));
     }
     // ---- merge and assembly ---------------------------------------------------------------------
     MergeDesc md{};
@@ -1547,9 +1632,12 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->grid_blocks = P.grid_x;
     s->gram_block = P.mode == 1 ? P.gram_block : (P.mode >= 2 ? 16 * P.n_tiles16 : 0);
     s->lds_tables = P.lds_policy;
-    s->waves = P.waves;
-    s->nbuf = P.nbuf;
+    s->waves = P.root_launches[0].waves;
+    s->nbuf = P.root_launches[0].gram ? 1 : P.nbuf;
     s->lds_bytes = (int32_t)P.root_launches[0].lds_bytes;
+    s->dedicated_scan = 0;
+    for (auto &L : P.root_launches)
+        if (L.gram) s->dedicated_scan = 1;
     return LMFAO_OK;
 }
 
@@ -1587,8 +1675,13 @@ static lmfao_status upload(lmfao_ctx *c) {
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipMemcpy(c->ws + c->off_desc, c->blob.data(), c->blob.size(), hipMemcpyHostToDevice));
     for (auto &L : c->plan.root_launches) {
-        RootKernel k = root_kernel(L.mode, L.p1, L.tables);
-        if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_root_lds_limit(k, L.lds_bytes));
+        if (L.gram) {
+            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3);
+            if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_gram_lds_limit(k, L.lds_bytes));
+        } else {
+            RootKernel k = root_kernel(L.mode, L.p1, L.tables);
+            if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_root_lds_limit(k, L.lds_bytes));
+        }
     }
     return LMFAO_OK;
 }
@@ -1622,6 +1715,12 @@ extern "C" lmfao_status lmfao_bind(lmfao_ctx *c, void *workspace, size_t ws_byte
 
 static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
     for (auto &L : c->plan.root_launches) {
+        if (L.gram) {
+            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3);
+            HIP_TRY(c, launch_gram(k, reinterpret_cast<const GramDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x,
+                                   L.waves, L.lds_bytes, st));
+            continue;
+        }
         RootKernel k = root_kernel(L.mode, L.p1, L.tables);
         HIP_TRY(c, launch_root(k, reinterpret_cast<const RootDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x, L.parts,
                                L.waves, L.lds_bytes, st));
@@ -1742,6 +1841,21 @@ static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
     }
     std::vector<int> pols{0};
     if (!P.tables.empty()) pols = {0, 1, 2};
+    if (!P.root_launches.empty() && P.root_launches[0].gram && P.root_launches.size() == 1) {
+        // the dedicated covariance scan: one record buffer, no register blocks or tables
+        for (int wv : {1, 2, 4})
+            for (int per_cu : {4, 8, 12, 24}) {
+                if (per_cu % wv) continue;
+                TileCfg t;
+                t.waves = wv;
+                t.nbuf = 1;
+                t.grid_x = per_cu / wv * c->n_cu;
+                t.gram_block = 0;
+                t.lds_policy = 0;
+                out.push_back(t);
+            }
+        return out;
+    }
     for (int wv : {1, 2, 4})
         for (int nb : {1, 2})
             for (int per_cu : {2, 3, 4, 6, 8}) {

@@ -738,6 +738,316 @@ __global__ void assemble_kernel(const AssembleDesc *__restrict__ dp) {
 }
 
 // ---------------------------------------------------------------------------
+// covariance-only root scan (BF16 hi+lo split on matrix cores)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    // raw buffer: stride 0, range `bytes`; loads beyond the range return zeros
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// One wave scans its rows in 64-row tiles.  Per tile t:
+//   1. the fact slots of tile t+1 are requested: lane (i, g) = (lane % 16,
+//      lane / 16) loads rows 8g..8g+7 and 32+8g..32+8g+7 of its slot's column
+//      with four 16-byte loads into the second register set;
+//   2. once tile t's records, facts and the next keys have landed, every slot
+//      value is split x = hi + lo in bf16 and every upper-triangle 16x16 tile
+//      pair accumulates hi*hi + hi*lo + lo*hi (+ lo*lo) on MFMA; record and
+//      constant slots read their 8 rows out of LDS (16 bytes apart);
+//   3. the child records of tile t+1 are gathered into the wave's LDS record
+//      buffer with buffer loads that bypass registers (a key outside
+//      [0, n_keys) reads past the buffer range and lands as zeros, i.e. no
+//      join), and the keys of tile t+2 are requested.
+// The vector-memory operations issued between a load and its use do not
+// depend on the data, so every wait is "all but the newest fact loads".
+template <int NT, int NF, bool X4>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 3))) void gram_scan_kernel(
+    const GramDesc *__restrict__ dp) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    const AS_CONST GramDesc &d = *cst(dp);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr int NFA = NF > 0 ? NF : 1;
+
+    // the constant quad: 64 rows of [1, 0, 0, 0]
+    if (tid < 64) {
+        smem[4 * tid + 0] = __float_as_uint(1.f);
+        smem[4 * tid + 1] = 0u;
+        smem[4 * tid + 2] = 0u;
+        smem[4 * tid + 3] = 0u;
+    }
+    __syncthreads();
+
+    // row indices fit 32 bits: the planner refuses a root above 2^30 rows
+    const int n_rows = (int)d.n_rows;
+    const int rpb = (int)d.rows_per_block;
+    const int blk_begin = (int)blockIdx.x * rpb;
+    const int blk_end = min(blk_begin + rpb, n_rows);
+    const int per_wave = rpb / nwaves;
+    const int w_begin = blk_begin + wave * per_wave;
+    const int w_end = min(w_begin + per_wave, blk_end);
+    const int n_tiles = w_end > w_begin ? (w_end - w_begin + 63) / 64 : 0;
+    const int n_child = d.n_child;
+    const int rbase = d.lds_wave0 + wave * d.wave_bytes;     // this wave's record buffer (bytes)
+    const uint32_t last_row = (uint32_t)(n_rows - 1);
+
+    // per-lane sources of the NT slots this lane feeds
+    const char *colp[NFA];
+    bool is_fact[NT];
+    int lds_off[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int s = 16 * t + li;
+        const int fc = gld(&dp->slot[s].fact)[0];
+        is_fact[t] = fc >= 0;
+        const int off = gld(&dp->slot[s].lds)[0] + 8 * lg * 16;
+        lds_off[t] = gld(&dp->slot[s].per_buf)[0] ? rbase + off : off;
+        if (t < NF) colp[t] = fc >= 0 ? reinterpret_cast<const char *>(gld(d.fact_cols)[fc]) + 32 * lg : nullptr;
+    }
+    const bool mixed = NF > 0 && d.n_fact < 16 * NF;   // wave-uniform: the last fact tile has LDS lanes too
+
+    // per-child constants, hoisted out of the tile loop (wave-uniform)
+    __amdgpu_buffer_rsrc_t rrs[kGramMaxChild];
+    const int32_t *fkp[kGramMaxChild];
+    uint32_t nkey[kGramMaxChild], rbytes[kGramMaxChild];
+    int cdst[kGramMaxChild], cnq[kGramMaxChild];
+#pragma unroll
+    for (int c = 0; c < kGramMaxChild; ++c)
+        if (c < n_child) {
+            const AS_CONST GramChild &ch = d.ch[c];
+            nkey[c] = ch.n_keys;
+            rbytes[c] = ch.rec_bytes;
+            rrs[c] = buffer_rsrc(ch.rec, nkey[c] * rbytes[c]);
+            fkp[c] = ch.fk;
+            cdst[c] = rbase + ch.quad0 * kQuadBytes;
+            cnq[c] = ch.n_quads;
+        }
+
+    f32x4 acc[NP], sacc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        acc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+        sacc[p] = acc[p];
+    }
+    unsigned long long count = 0;
+    int since_flush = 0;
+
+    uint32_t key[kGramMaxChild];
+    f32x4 Fn[NFA][4], Fc[NFA][4];   // next tile's facts (in flight), this tile's facts
+
+    auto tile_row = [&](int t) -> int { return w_begin + 64 * t; };
+    auto load_keys = [&](int t) {
+        const uint32_t row = min((uint32_t)(tile_row(t) + lane), last_row);
+#pragma unroll
+        for (int c = 0; c < kGramMaxChild; ++c)
+            if (c < n_child) key[c] = (uint32_t)gld(fkp[c])[row];
+    };
+    auto issue_rec = [&]() {
+#pragma unroll
+        for (int c = 0; c < kGramMaxChild; ++c)
+            if (c < n_child) {
+                uint32_t koff = __umul24(min(key[c], nkey[c]), rbytes[c]);
+                char *dst = reinterpret_cast<char *>(smem) + cdst[c];
+                // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
+#pragma unroll 1
+                for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+            }
+    };
+    // fact slots of tile t into Fn.  A tile that ends past the last row loads clamped
+    // (in-bounds) chunks; its rows are re-read one by one before it is computed.
+    auto load_fact = [&](int t) {
+        const int r0 = tile_row(t);
+        if (r0 + 64 <= n_rows) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (is_fact[f]) {
+                    const f32x4 *p = reinterpret_cast<const f32x4 *>(colp[f] + (uint32_t)r0 * 4u);
+                    Fn[f][0] = gld(p)[0];
+                    Fn[f][1] = gld(p)[1];
+                    Fn[f][2] = gld(p)[8];
+                    Fn[f][3] = gld(p)[9];
+                }
+        } else {
+            const int last = n_rows - 4;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (is_fact[f]) {
+                    const char *base = colp[f] - 32 * lg;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int rq = min(r0 + 8 * lg + (q >> 1) * 32 + (q & 1) * 4, last);
+                        Fn[f][q] = gld(reinterpret_cast<const f32x4 *>(base + (uint32_t)rq * 4u))[0];
+                    }
+                }
+        }
+    };
+
+    auto compute = [&](int t) {
+        const int r0 = tile_row(t);
+        bool valid = r0 + lane < w_end;
+        uint32_t cnt[kGramMaxChild];
+#pragma unroll
+        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + 4 * lane] : 1u;
+#pragma unroll
+        for (int c = 0; c < kGramMaxChild; ++c)
+            if (cnt[c] == 0u) valid = false;
+        const uint64_t vm = __ballot(valid);
+        count += (unsigned long long)__popcll(vm);
+        const bool all_rows = vm == ~0ull;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 fh[NT], fl[NT];
+            const uint32_t vbits = (uint32_t)(vm >> (32 * ks + 8 * lg)) & 0xFFu;
+#pragma unroll
+            for (int t2 = 0; t2 < NT; ++t2) {
+                float x[8];
+                if (t2 < NF) {
+                    const int fi = t2 < NF ? t2 : 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        x[e] = Fc[fi][2 * ks][e];
+                        x[4 + e] = Fc[fi][2 * ks + 1][e];
+                    }
+                }
+                if (t2 >= NF || (t2 == NF - 1 && mixed)) {
+                    if (t2 >= NF || !is_fact[t2]) {
+                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
+                                                                         lds_off[t2] + 512 * ks);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) x[i] = p[4 * i];
+                    }
+                }
+                if (!all_rows) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((vbits >> i) & 1u)) x[i] = 0.f;
+                }
+                split_bf16x8(x, fh[t2], fl[t2]);
+            }
+            int p = 0;
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[a], fh[b], acc[p], 0, 0, 0);
+            p = 0;
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[a], fl[b], acc[p], 0, 0, 0);
+            p = 0;
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[a], fh[b], acc[p], 0, 0, 0);
+            if (X4) {
+                p = 0;
+#pragma unroll
+                for (int a = 0; a < NT; ++a)
+#pragma unroll
+                    for (int b = a; b < NT; ++b, ++p)
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[a], fl[b], acc[p], 0, 0, 0);
+            }
+        }
+        if (++since_flush == kFlushTiles) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                sacc[p] += acc[p];
+                acc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            since_flush = 0;
+        }
+    };
+
+    if (n_tiles > 0) {
+        load_keys(0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        issue_rec();
+        load_fact(0);
+        if (n_tiles > 1) load_keys(1);
+    }
+    for (int t = 0; t < n_tiles; ++t) {
+        // this tile's records and facts and the next tile's keys have landed
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        wave_sync();
+#pragma unroll
+        for (int f = 0; f < NFA; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Fc[f][q] = Fn[f][q];
+        if (tile_row(t) + 64 > n_rows) {
+            // the last tile ends past the last row: its fact rows one by one, waited for here
+            // so that no load stays pending into the common path
+            const int r0 = tile_row(t);
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (is_fact[f]) {
+                    const float *p = reinterpret_cast<const float *>(colp[f] + (uint32_t)r0 * 4u);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int i = (q >> 1) * 32 + (q & 1) * 4 + e;
+                            Fc[f][q][e] = r0 + 8 * lg + i < n_rows ? gld(p)[i] : 0.f;
+                        }
+                }
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+        if (t + 1 < n_tiles) load_fact(t + 1);   // in flight during this tile
+        compute(t);
+        if (t + 1 < n_tiles) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this tile's record reads are done
+            wave_sync();
+            issue_rec();
+            if (t + 2 < n_tiles) load_keys(t + 2);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+
+    // ---- workgroup reduction in fp64 over the staged feature order -----------------------
+    __syncthreads();
+    const int ng = d.n_gram;
+    double *red = reinterpret_cast<double *>(smem);
+    for (int i = tid; i < ng * ng; i += blockDim.x) red[i] = 0.0;
+    __shared__ unsigned long long wcount[kMaxWaves];
+    if (lane == 0) wcount[wave] = count;
+    __syncthreads();
+    {
+        int p = 0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = a; b < NT; ++b, ++p) {
+                const int sb = 16 * b + li;
+                const int fb = gld(&dp->slot[sb].feat)[0];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int sa = 16 * a + 4 * lg + e;
+                    if (a == b && sa > sb) continue;
+                    const int fa = gld(&dp->slot[sa].feat)[0];
+                    if (fa < 0 || fb < 0) continue;
+                    const int i = min(fa, fb), j = max(fa, fb);
+                    atomicAdd(&red[i * ng + j], (double)sacc[p][e] + (double)acc[p][e]);
+                }
+            }
+    }
+    __syncthreads();
+    double *out = d.gram_partial + (int64_t)blockIdx.x * ng * ng;
+    for (int e = tid; e < ng * ng; e += blockDim.x) {
+        const int i = e / ng, j = e % ng;
+        if (i <= j) gst(out)[e] = red[e];
+    }
+    if (d.do_count && tid == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < nwaves; ++w) t += wcount[w];
+        gst(d.count_partial)[blockIdx.x] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // kernel table for the host
 // ---------------------------------------------------------------------------
 
@@ -778,6 +1088,41 @@ RootKernel root_kernel(int mode, int p1, bool tables) {
             return nullptr;
     }
     return nullptr;
+}
+
+typedef void (*GramKernel)(const GramDesc *);
+
+template <int NT, int NF>
+static GramKernel pick_gram(bool x4) {
+    return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true> : (GramKernel)gram_scan_kernel<NT, NF, false>;
+}
+
+// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2))
+GramKernel gram_kernel(int nt, int nf, bool x4) {
+    if (nf < 0 || nf > 2 || nf > nt) return nullptr;
+    switch (nt * 4 + nf) {
+        case 4: return pick_gram<1, 0>(x4);
+        case 5: return pick_gram<1, 1>(x4);
+        case 8: return pick_gram<2, 0>(x4);
+        case 9: return pick_gram<2, 1>(x4);
+        case 10: return pick_gram<2, 2>(x4);
+        case 12: return pick_gram<3, 0>(x4);
+        case 13: return pick_gram<3, 1>(x4);
+        case 14: return pick_gram<3, 2>(x4);
+        case 16: return pick_gram<4, 0>(x4);
+        case 17: return pick_gram<4, 1>(x4);
+        case 18: return pick_gram<4, 2>(x4);
+    }
+    return nullptr;
+}
+
+hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k, dim3(grid_x), dim3(64 * waves), lds_bytes, st, desc);
+    return hipGetLastError();
+}
+
+hipError_t set_gram_lds_limit(GramKernel k, size_t bytes) {
+    return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_fill(const void *fills, int n, hipStream_t st) {

@@ -78,3 +78,28 @@ def check_sums(got, ref, abs_sums, rtol, what=""):
             msg.append("  #%d got %r ref %r strict %.3e normwise %.3e kappa %.3g" % (b, g[b], r[b], s[b], nw[b], kk[b]))
         raise AssertionError("\n".join(msg))
     return float(np.max(strict, initial=0.0)), float(np.max(normwise, initial=0.0))
+
+
+def bf16_split(x):
+    """x = hi + lo + d with hi = bf16(x), lo = bf16(x - hi), both round to
+    nearest even (the split of the BF16 covariance forms), as exact float64."""
+    def bf16(v):
+        u = np.asarray(v, np.float32).view(np.uint32).astype(np.uint64)
+        return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32).view(np.float32)
+    x = np.asarray(x, np.float32)
+    hi = bf16(x)
+    lo = bf16((x - hi).astype(np.float32))
+    return hi.astype(np.float64), lo.astype(np.float64)
+
+
+def split_gram(columns, four):
+    """The covariance block the BF16 split computes, over features
+    [1, columns...] of the materialised join: sum of hi*hi + hi*lo + lo*hi
+    (+ lo*lo), every product exact in float64 (8-bit significands)."""
+    n = len(columns[0]) if columns else 0
+    X = np.stack([np.ones(n, np.float32)] + [np.asarray(c, np.float32) for c in columns], axis=1)
+    H, L = bf16_split(X)
+    G = H.T @ H + H.T @ L + L.T @ H
+    if four:
+        G += L.T @ L
+    return G

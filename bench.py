@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"])
+    ap.add_argument("--timing-db", default=None, help="autotune: append every candidate's timing to this file")
+    ap.add_argument("--candidate", type=int, default=-1,
+                    help="run tile candidate I of the full form instead of choosing one (profiling runs)")
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x4"],
                     help="split form of the full form: three products (hi*hi + hi*lo + lo*hi) or four (+ lo*lo)")
     ap.add_argument("--forms", default="both", choices=["both", "full"],
@@ -98,6 +101,18 @@ def main():
         print("[bench] calibration copy: %d bytes read, %d bytes written" % (src.numel(), dst.numel()),
               file=sys.stderr, flush=True)
         del src, dst
+        # read-only rate: a device-wide sum over 8 GB of fp32 (context for the roofline)
+        x = torch.ones(1 << 31, dtype=torch.float32, device=dev)
+        for _ in range(2):
+            x.sum()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            x.sum()
+        torch.cuda.synchronize()
+        print("[bench] read-only sum over %d bytes: %.1f GB/s" % (x.numel() * 4, x.numel() * 4 * 5 / (time.perf_counter() - t) / 1e9),
+              file=sys.stderr, flush=True)
+        del x
 
     # plain form: fp32 covariance, one launch per view, heuristic tiles
     t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
@@ -114,12 +129,15 @@ def main():
     full = Engine(db, qs, precision=args.precision, schedule="batched", columns=cols)
     full.ctx.execute(stream)
     full.ctx.sync()
-    chosen = "heuristic"
-    if args.plan in ("auto", "learned") and os.path.exists(WEIGHTS):
+    chosen, best = "heuristic", -1
+    if args.candidate >= 0:
+        full.ctx.select_candidate(args.candidate)
+        chosen, best = "fixed", args.candidate
+    elif args.plan in ("auto", "learned") and os.path.exists(WEIGHTS):
         best = full.ctx.choose_learned(WEIGHTS, stream)
         chosen = "learned" if best >= 0 else "heuristic"
     if chosen == "heuristic" and args.plan in ("auto", "autotune"):
-        full.ctx.autotune(stream, None, 3)
+        best = full.ctx.autotune(stream, args.timing_db, 3)
         chosen = "autotune"
     full._bind()
     t_full = time_steps(full, stream, args.steps, args.warmup)
@@ -182,7 +200,7 @@ def main():
         "data": "synthetic (seeded; workload 4 recipe)",
         "config": {"workload": "covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with "
                                "4 dims (1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates",
-                   "fact_rows": n_join, "aggregates": len(qs), "plan": chosen,
+                   "fact_rows": n_join, "aggregates": len(qs), "plan": chosen, "candidate": best,
                    "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
                    "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
                    "lds_bytes": stats["lds_bytes"]},

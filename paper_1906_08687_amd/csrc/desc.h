@@ -202,12 +202,17 @@ struct RootDesc {
 constexpr int kGramMaxChild = 4;
 constexpr int kGramMaxSlots = 64;
 constexpr int kQuadBytes = 1040;  // one 16-byte quad of 64 rows, plus 16 bytes of bank skew
+constexpr int kFactPitch = 272;   // one fact column of a 64-row tile in LDS, plus 16 bytes of bank skew
+
+constexpr int kGramConstChild = 31;   // "child" of the constant and padding slots: every row alike
 
 struct GramSlot {
     int32_t fact;         // >= 0: fact column of this slot; -1: read from LDS
     int32_t lds;          // LDS byte offset of row 0 (record buffer relative when per_buf)
     int32_t per_buf;      // 1: inside a wave's record buffer; 0: the block's constant quad
     int32_t feat;         // staged feature whose covariance row this slot feeds; -1: padding
+    int32_t child;        // record slots: the child whose record holds it; kGramConstChild otherwise
+    int32_t pad[3];
 };
 
 struct GramChild {
@@ -226,8 +231,10 @@ struct GramDesc {
     int32_t n_fact;              // fact slots [0, n_fact)
     int32_t n_gram;              // staged features (rows of the covariance block)
     int32_t do_count;
-    int32_t lds_wave0;           // byte offset of wave 0's record buffer (after the constant quad)
-    int32_t wave_bytes;          // one record buffer: n_quads * kQuadBytes
+    int32_t lds_wave0;           // byte offset of wave 0's region (after the constant quad)
+    int32_t wave_bytes;          // a wave's region: n_quads * kQuadBytes of records, then the fact tile
+    int32_t fact_off;            // offset of the fact tile in a wave's region (16 * NF columns of kFactPitch)
+    int32_t pad1;
     GramChild ch[kGramMaxChild];
     GramSlot slot[kGramMaxSlots];
     const float *const *fact_cols;       // [n_fact]
@@ -237,11 +244,19 @@ struct GramDesc {
 
 // ---- final merge and result assembly -----------------------------------------
 
+// Covariance partials hold the upper triangle (i <= j) packed row by row:
+// entry (i, j) at tri_index(i, j, n).
+__host__ __device__ inline int tri_index(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
+
+constexpr int kMergeGroups = 32;     // first merge pass: partials summed in this many ordered groups
+
 struct MergeDesc {
     int32_t grid;                      // partials to reduce
     int32_t n_gram;
-    const double *gram_partial;
-    const unsigned long long *count_partial;
+    const double *gram_partial;        // [grid][n_gram * (n_gram + 1) / 2]
+    const unsigned long long *count_partial;   // [grid], or null
+    double *group_sum;                 // [kMergeGroups][n_gram * (n_gram + 1) / 2]
+    unsigned long long *group_count;   // [kMergeGroups]
     double *gram;                      // [n_gram * n_gram], symmetric
     unsigned long long *count;         // total joined tuples
 };

@@ -69,7 +69,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxRecWords = 128;   // largest view record (the zero record stands in for missing keys)
-constexpr int kGridMax = 2048;
+constexpr int kGridMax = 2048;    // workgroups of the general root scan (one covariance partial each)
+constexpr int kPartMax = 8192;    // covariance partials (the dedicated scan writes one per wave)
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -256,7 +257,7 @@ struct lmfao_ctx {
     size_t res_len = 0;
     bool bound = false;
     // device layout (offsets into ws)
-    size_t off_err = 0, off_gcnt = 0, off_gval = 0, off_gpart = 0, off_cpart = 0, off_gram = 0, off_count = 0;
+    size_t off_err = 0, off_gcnt = 0, off_gval = 0, off_gpart = 0, off_cpart = 0, off_gsum = 0, off_gram = 0, off_count = 0;
     size_t off_desc = 0, off_mlp = 0, off_zero = 0;
     std::vector<size_t> off_rec, off_seen;
     std::vector<uint8_t> blob;       // descriptor image copied to ws + off_desc
@@ -937,11 +938,11 @@ static bool gram_eligible(const lmfao_ctx *c, const Plan &P, int *nt, int *nf) {
     return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, P.mode == 3) != nullptr;
 }
 
-static size_t gram_lds_bytes(const Plan &P, int waves) {
+static size_t gram_lds_bytes(const Plan &P, int waves, int nf) {
     int quads = 0;
     for (int ch : P.children[P.root]) quads += P.rec_stride[ch] / 4;
-    const size_t stage = 1024 + (size_t)waves * quads * kQuadBytes;
-    return std::max(stage, (size_t)P.n_gram * P.n_gram * 8);
+    // the constant quad; per wave one record buffer and one fact tile
+    return 1024 + (size_t)waves * ((size_t)quads * kQuadBytes + (size_t)nf * 16 * kFactPitch);
 }
 
 static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
@@ -984,7 +985,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     place_tables(c, P, P.lds_policy, budget);
     int gnt = 0, gnf = 0;
     P.gram_waves = cfg.waves > 0 ? cfg.waves : 4;
-    const bool gram_ok = gram_eligible(c, P, &gnt, &gnf) && gram_lds_bytes(P, P.gram_waves) <= c->lds_limit;
+    const bool gram_ok = gram_eligible(c, P, &gnt, &gnf) && gram_lds_bytes(P, P.gram_waves, gnf) <= c->lds_limit;
     // root launches
     P.root_launches.clear();
     auto make_launch = [&](bool with_gram, const std::vector<int> &fams, int single_table) {
@@ -1013,7 +1014,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             L.gnt = gnt;
             L.gnf = gnf;
             L.waves = P.gram_waves;
-            L.lds_bytes = gram_lds_bytes(P, L.waves);
+            L.lds_bytes = gram_lds_bytes(P, L.waves, gnf);
             occ_waves = gnt >= 4 ? 8 : 12;
         } else {
             const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
@@ -1027,7 +1028,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         const int occ = (int)std::max<size_t>(1, std::min<size_t>(occ_waves / L.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
         int gx = cfg.grid_x > 0 ? cfg.grid_x : 2 * c->n_cu * occ;
         gx = (int)std::min<int64_t>(gx, blocks_needed);
-        gx = std::max(1, std::min(gx, kGridMax));
+        gx = std::max(1, std::min(gx, L.gram ? kPartMax / L.waves : kGridMax));
         const int64_t rpb = round_up((int)std::min<int64_t>(ceil_div(root.n_rows, gx), 1 << 30), tile);
         L.grid_x = (int)std::max<int64_t>(1, ceil_div(root.n_rows, std::max<int64_t>(rpb, tile)));
         L.desc.rows_per_block = std::max<int64_t>(rpb, tile);
@@ -1094,10 +1095,13 @@ static size_t compute_ws(lmfao_ctx *c) {
     o = align_up(o + (size_t)P.table_cells * 8);
     c->off_gval = o;
     o = align_up(o + (size_t)P.table_vals * 8);
+    const size_t ntri = (size_t)P.n_gram * (P.n_gram + 1) / 2;
     c->off_gpart = o;
-    o = align_up(o + (size_t)kGridMax * P.n_gram * P.n_gram * 8);
+    o = align_up(o + (size_t)kPartMax * ntri * 8);
     c->off_cpart = o;
-    o = align_up(o + (size_t)kGridMax * 8);
+    o = align_up(o + (size_t)kPartMax * 8);
+    c->off_gsum = o;
+    o = align_up(o + (size_t)kMergeGroups * (ntri + 1) * 8);
     c->off_gram = o;
     o = align_up(o + (size_t)P.n_gram * P.n_gram * 8 + 8);
     c->off_count = o;
@@ -1451,21 +1455,22 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                 G.ch[k].n_quads = rch[k].stride / 4;
                 quads += rch[k].stride / 4;
             }
-            G.wave_bytes = quads * kQuadBytes;
+            G.fact_off = quads * kQuadBytes;
+            G.wave_bytes = G.fact_off + L.gnf * 16 * kFactPitch;
             // slots: fact features, then every child's subtree features, the constant, padding
             int ns = 0;
-            for (int j = 0; j < G.n_fact; ++j) G.slot[ns++] = GramSlot{j, 0, 0, P.own_feats[r0][j]};
+            for (int j = 0; j < G.n_fact; ++j) G.slot[ns++] = GramSlot{j, 0, 0, P.own_feats[r0][j], kGramConstChild, {0, 0, 0}};
             for (size_t k = 0; k < P.children[r0].size(); ++k) {
                 const int ch = P.children[r0][k];
                 for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
                     const int w = P.rec_feat_off[ch] + i;
                     G.slot[ns++] = GramSlot{-1, (rch[k].quad_base + w / 4) * kQuadBytes + (w % 4) * 4, 1,
-                                            P.sub_feat_lo[ch] + i};
+                                            P.sub_feat_lo[ch] + i, (int)k, {0, 0, 0}};
                 }
             }
-            G.slot[ns++] = GramSlot{-1, 0, 0, 0};
+            G.slot[ns++] = GramSlot{-1, 0, 0, 0, kGramConstChild, {0, 0, 0}};
             if (ns != P.n_gram) return fail(c, LMFAO_ERR_STATE, "covariance slots do not cover the staged features");
-            for (; ns < kGramMaxSlots; ++ns) G.slot[ns] = GramSlot{-1, 4, 0, -1};
+            for (; ns < kGramMaxSlots; ++ns) G.slot[ns] = GramSlot{-1, 4, 0, -1, kGramConstChild, {0, 0, 0}};
             G.fact_cols = D.fact_cols;
             G.gram_partial = D.gram_partial;
             G.count_partial = D.count_partial;
@@ -1486,6 +1491,11 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     for (auto &L : P.root_launches)
         if (L.with_gram) md.grid = L.grid_x;
     md.n_gram = P.n_gram;
+    for (auto &L : P.root_launches)
+        if (L.with_gram && L.gram) md.grid = L.grid_x * L.waves;   // one partial per wave
+    md.group_sum = reinterpret_cast<double *>(ws + c->off_gsum);
+    md.group_count = reinterpret_cast<unsigned long long *>(ws + c->off_gsum + (size_t)kMergeGroups *
+                                                            ((size_t)P.n_gram * (P.n_gram + 1) / 2) * 8);
     md.gram_partial = reinterpret_cast<const double *>(ws + c->off_gpart);
     md.count_partial = P.need_count ? reinterpret_cast<const unsigned long long *>(ws + c->off_cpart) : nullptr;
     md.gram = reinterpret_cast<double *>(ws + c->off_gram);
@@ -1844,7 +1854,7 @@ static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
     if (!P.root_launches.empty() && P.root_launches[0].gram && P.root_launches.size() == 1) {
         // the dedicated covariance scan: one record buffer, no register blocks or tables
         for (int wv : {1, 2, 4})
-            for (int per_cu : {4, 8, 12, 24}) {
+            for (int per_cu : {4, 8, 12, 16, 24}) {
                 if (per_cu % wv) continue;
                 TileCfg t;
                 t.waves = wv;

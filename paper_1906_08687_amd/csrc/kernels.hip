@@ -607,10 +607,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 }
         }
         __syncthreads();
-        double *out = d.gram_partial + (int64_t)blockIdx.x * d.n_gram * d.n_gram;
+        const int ntri = d.n_gram * (d.n_gram + 1) / 2;
+        double *out = d.gram_partial + (int64_t)blockIdx.x * ntri;
         for (int e = tid; e < d.n_gram * d.n_gram; e += blockDim.x) {
             const int i = e / d.n_gram, j = e % d.n_gram;
-            if (i <= j) gst(out)[e] = red[i * ngp + j];
+            if (i <= j) gst(out)[tri_index(i, j, d.n_gram)] = red[i * ngp + j];
         }
     }
     if (MODE >= 2 && do_gram) {
@@ -638,13 +639,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 for (int e = 0; e < 4; ++e)
                     atomicAdd(&rhl[(16 * t + ci + e) * n16 + 16 * u + cj], (double)chl[t * NT + u][e]);
         __syncthreads();
-        double *out = d.gram_partial + (int64_t)blockIdx.x * d.n_gram * d.n_gram;
+        const int ntri = d.n_gram * (d.n_gram + 1) / 2;
+        double *out = d.gram_partial + (int64_t)blockIdx.x * ntri;
         for (int e = tid; e < d.n_gram * d.n_gram; e += blockDim.x) {
             const int i = e / d.n_gram, j = e % d.n_gram;
             if (i <= j) {
                 double v = rhh[i * n16 + j] + rhl[i * n16 + j] + rhl[j * n16 + i];
                 if (MODE == 3) v += rll[i * n16 + j];
-                gst(out)[e] = v;
+                gst(out)[tri_index(i, j, d.n_gram)] = v;
             }
         }
     }
@@ -682,28 +684,47 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // cross-workgroup merge (fp64, fixed order: deterministic)
 // ---------------------------------------------------------------------------
 
-__global__ void merge_kernel(const MergeDesc *__restrict__ dp) {
-    // one wave per covariance entry: lane l sums partials l, l+64, ... in order, then a
-    // fixed shuffle tree combines the lanes (the same order every run: deterministic)
+// Two ordered passes, so the result does not depend on scheduling.  Pass 1:
+// workgroup (x, g) sums partials g*P/G .. (g+1)*P/G - 1 in order for 64
+// consecutive packed entries (lane = entry: every load is one coalesced 512-byte
+// row).  Pass 2: each entry sums its G group sums in order and is written to
+// both (i, j) and (j, i).
+__global__ void merge_groups_kernel(const MergeDesc *__restrict__ dp) {
+    const MergeDesc &d = *dp;
+    const int ntri = d.n_gram * (d.n_gram + 1) / 2;
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    const int g = blockIdx.y;
+    const int p0 = (int)((int64_t)d.grid * g / kMergeGroups), p1 = (int)((int64_t)d.grid * (g + 1) / kMergeGroups);
+    if (e < ntri) {
+        double s = 0.0;
+        for (int p = p0; p < p1; ++p) s += gld(d.gram_partial)[(int64_t)p * ntri + e];
+        gst(d.group_sum)[(int64_t)g * ntri + e] = s;
+    }
+    if (blockIdx.x == 0 && d.count_partial) {
+        unsigned long long t = 0;
+        for (int p = p0 + threadIdx.x; p < p1; p += 64) t += gld(d.count_partial)[p];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (threadIdx.x == 0) gst(d.group_count)[g] = t;
+    }
+}
+
+__global__ void merge_final_kernel(const MergeDesc *__restrict__ dp) {
     const MergeDesc &d = *dp;
     const int n = d.n_gram;
-    const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (e < n * n) {
-        const int i = e / n, j = e % n;
-        if (i <= j) {
-            double s = 0.0;
-            for (int b = lane; b < d.grid; b += 64) s += gld(d.gram_partial)[(int64_t)b * n * n + e];
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            if (lane == 0) {
-                gst(d.gram)[i * n + j] = s;
-                gst(d.gram)[j * n + i] = s;
-            }
-        }
+    const int ntri = n * (n + 1) / 2;
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    if (e < ntri) {
+        double s = 0.0;
+        for (int g = 0; g < kMergeGroups; ++g) s += gld(d.group_sum)[(int64_t)g * ntri + e];
+        int i = 0;
+        while (tri_index(i + 1, i + 1, n) <= e) ++i;
+        const int j = i + (e - tri_index(i, i, n));
+        gst(d.gram)[i * n + j] = s;
+        gst(d.gram)[j * n + i] = s;
     }
-    if (e == 0 && lane == 0 && d.count_partial) {
+    if (e == 0 && d.count_partial) {
         unsigned long long t = 0;
-        for (int b = 0; b < d.grid; ++b) t += gld(d.count_partial)[b];
+        for (int g = 0; g < kMergeGroups; ++g) t += gld(d.group_count)[g];
         *gst(d.count) = t;
     }
 }
@@ -746,20 +767,28 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// One wave scans its rows in 64-row tiles.  Per tile t:
-//   1. the fact slots of tile t+1 are requested: lane (i, g) = (lane % 16,
-//      lane / 16) loads rows 8g..8g+7 and 32+8g..32+8g+7 of its slot's column
-//      with four 16-byte loads into the second register set;
-//   2. once tile t's records, facts and the next keys have landed, every slot
-//      value is split x = hi + lo in bf16 and every upper-triangle 16x16 tile
-//      pair accumulates hi*hi + hi*lo + lo*hi (+ lo*lo) on MFMA; record and
-//      constant slots read their 8 rows out of LDS (16 bytes apart);
-//   3. the child records of tile t+1 are gathered into the wave's LDS record
-//      buffer with buffer loads that bypass registers (a key outside
-//      [0, n_keys) reads past the buffer range and lands as zeros, i.e. no
-//      join), and the keys of tile t+2 are requested.
-// The vector-memory operations issued between a load and its use do not
-// depend on the data, so every wait is "all but the newest fact loads".
+// One wave scans its rows in 64-row tiles.  Lane (i, g) = (lane % 16,
+// lane / 16) feeds slot i of each 16-slot tile; in k-step ks (32 rows) it
+// holds rows 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3}.  (Any pairing of
+// rows to MFMA k-indices is valid as long as every operand uses the same one;
+// this one keeps the four lane groups on different LDS banks and lets every
+// fact chunk be one 16-byte load.)  Per tile t:
+//   1. wait until tile t's records and facts and tile t+1's keys have landed
+//      (only the facts of tile t+1 may still be in flight);
+//   2. split every slot value x = hi + lo in bf16 into operand registers:
+//      fact slots from registers, record and constant slots from LDS;
+//   3. gather tile t+1's child records into the wave's LDS record buffer with
+//      buffer loads that bypass registers (a key outside [0, n_keys) reads
+//      past the buffer range and lands as zeros: no join), request the keys of
+//      tile t+2, then the facts of tile t+2 into the register set tile t just
+//      freed.  Issued in that order, the in-order wait counter of step 1 never
+//      waits for facts it does not need yet.  (After the last tile these
+//      requests repeat the last tile and are never used.)
+//   4. accumulate hi*hi + hi*lo + lo*hi (+ lo*lo) for every upper-triangle
+//      16x16 tile pair on MFMA while those copies are in flight.
+// Fact columns and keys are streamed once: their loads are non-temporal, so
+// they do not push the gathered view records out of the caches.  Each wave
+// writes its own fp64 partial of the upper triangle (no LDS reduction).
 template <int NT, int NF, bool X4>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 3))) void gram_scan_kernel(
     const GramDesc *__restrict__ dp) {
@@ -787,27 +816,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     const int rpb = (int)d.rows_per_block;
     const int blk_begin = (int)blockIdx.x * rpb;
     const int blk_end = min(blk_begin + rpb, n_rows);
-    const int per_wave = rpb / nwaves;
-    const int w_begin = blk_begin + wave * per_wave;
-    const int w_end = min(w_begin + per_wave, blk_end);
-    const int n_tiles = w_end > w_begin ? (w_end - w_begin + 63) / 64 : 0;
+    // the waves of a workgroup take its 64-row tiles in turn, so that at any time they stream
+    // neighbouring stretches of every column (DRAM pages are opened once for several waves)
+    const int blk_tiles = blk_end > blk_begin ? (blk_end - blk_begin + 63) / 64 : 0;
+    const int n_tiles = blk_tiles > wave ? (blk_tiles - wave + nwaves - 1) / nwaves : 0;
     const int n_child = d.n_child;
     const int rbase = d.lds_wave0 + wave * d.wave_bytes;     // this wave's record buffer (bytes)
     const uint32_t last_row = (uint32_t)(n_rows - 1);
 
-    // per-lane sources of the NT slots this lane feeds
-    const char *colp[NFA];
+    // per-lane sources of the NT slots this lane feeds (in fact tiles, fact lanes read the
+    // fact tile in LDS at lds_off; other lanes their record word or the constant quad)
     bool is_fact[NT];
-    int lds_off[NT];
+    int lds_off[NT], schild[NT];
+    const int fbase = rbase + d.fact_off;                      // this wave's fact tile in LDS
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int s = 16 * t + li;
         const int fc = gld(&dp->slot[s].fact)[0];
         is_fact[t] = fc >= 0;
-        const int off = gld(&dp->slot[s].lds)[0] + 8 * lg * 16;
-        lds_off[t] = gld(&dp->slot[s].per_buf)[0] ? rbase + off : off;
-        if (t < NF) colp[t] = fc >= 0 ? reinterpret_cast<const char *>(gld(d.fact_cols)[fc]) + 32 * lg : nullptr;
+        schild[t] = gld(&dp->slot[s].child)[0];
+        const int off = gld(&dp->slot[s].lds)[0];       // row 0 of the slot's word
+        lds_off[t] = fc >= 0 ? fbase + s * kFactPitch : (gld(&dp->slot[s].per_buf)[0] ? rbase + off : off);
     }
+    // fact loads: in load q of fact tile f, lane (i, g) reads rows 4i..4i+3 of fact column
+    // 16f + 4q + g, so 16 lanes read 256 contiguous bytes of one column.  Lanes past the last
+    // fact column read column 0 (ignored), so every load is issued by the whole wave.
+    const char *fld[NFA][4];
+    int fst[NFA][4];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 16 * f + 4 * q + lg;
+            fld[f][q] = reinterpret_cast<const char *>(gld(d.fact_cols)[c < d.n_fact ? c : 0]) + 16 * li;
+            fst[f][q] = fbase + c * kFactPitch + 16 * li;
+        }
     const bool mixed = NF > 0 && d.n_fact < 16 * NF;   // wave-uniform: the last fact tile has LDS lanes too
 
     // per-child constants, hoisted out of the tile loop (wave-uniform)
@@ -837,62 +880,96 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     int since_flush = 0;
 
     uint32_t key[kGramMaxChild];
-    f32x4 Fn[NFA][4], Fc[NFA][4];   // next tile's facts (in flight), this tile's facts
+    // children whose keys are equal on all 64 rows of the next / this tile (the fact is sorted
+    // by its keys, so long runs are common): their record is gathered once, into row 0, and
+    // every row reads it there.  The constant slots read row 0 of the constant quad always.
+    uint32_t uni_next = 1u << kGramConstChild, uni_cur = 1u << kGramConstChild;
+    f32x4 F[NFA][4];      // the next tile's fact chunks, in flight (see fld)
 
-    auto tile_row = [&](int t) -> int { return w_begin + 64 * t; };
+    auto tile_row = [&](int t) -> int { return blk_begin + 64 * (wave + t * nwaves); };
     auto load_keys = [&](int t) {
         const uint32_t row = min((uint32_t)(tile_row(t) + lane), last_row);
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
-            if (c < n_child) key[c] = (uint32_t)gld(fkp[c])[row];
+            if (c < n_child) key[c] = (uint32_t)__builtin_nontemporal_load(gld(fkp[c]) + row);
     };
     auto issue_rec = [&]() {
+        uni_next = 1u << kGramConstChild;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (c < n_child) {
+                const uint32_t k0 = __builtin_amdgcn_readfirstlane(key[c]);
+                const bool uni = __ballot(key[c] != k0) == 0ull;
                 uint32_t koff = __umul24(min(key[c], nkey[c]), rbytes[c]);
                 char *dst = reinterpret_cast<char *>(smem) + cdst[c];
-                // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
+                if (uni) {
+                    uni_next |= 1u << c;
+                    // one lane: the record lands in row 0 of each quad
+                    if (lane == 0) {
 #pragma unroll 1
-                for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+                        for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+                    }
+                } else {
+                    // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
+#pragma unroll 1
+                    for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+                }
             }
     };
-    // fact slots of tile t into Fn.  A tile that ends past the last row loads clamped
-    // (in-bounds) chunks; its rows are re-read one by one before it is computed.
+    // fact chunks of tile t into F: always four loads per fact tile by the whole wave, so the
+    // count of operations in flight never depends on the data.  A tile that ends past the
+    // last row loads clamped (in-bounds) chunks; its rows are re-read one by one before use.
     auto load_fact = [&](int t) {
         const int r0 = tile_row(t);
         if (r0 + 64 <= n_rows) {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
-                if (is_fact[f]) {
-                    const f32x4 *p = reinterpret_cast<const f32x4 *>(colp[f] + (uint32_t)r0 * 4u);
-                    Fn[f][0] = gld(p)[0];
-                    Fn[f][1] = gld(p)[1];
-                    Fn[f][2] = gld(p)[8];
-                    Fn[f][3] = gld(p)[9];
-                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    F[f][q] = __builtin_nontemporal_load(gld(reinterpret_cast<const f32x4 *>(fld[f][q] + (uint32_t)r0 * 4u)));
         } else {
-            const int last = n_rows - 4;
+            const int rq = min(r0 + 4 * li, n_rows - 4);
 #pragma unroll
             for (int f = 0; f < NF; ++f)
-                if (is_fact[f]) {
-                    const char *base = colp[f] - 32 * lg;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int rq = min(r0 + 8 * lg + (q >> 1) * 32 + (q & 1) * 4, last);
-                        Fn[f][q] = gld(reinterpret_cast<const f32x4 *>(base + (uint32_t)rq * 4u))[0];
-                    }
-                }
+                for (int q = 0; q < 4; ++q)
+                    F[f][q] = gld(reinterpret_cast<const f32x4 *>(fld[f][q] - 16 * li + (uint32_t)rq * 4u))[0];
         }
     };
-
-    auto compute = [&](int t) {
+    // the tile's facts from F into the wave's LDS fact tile (a tile ending past the last row
+    // is re-read row by row first, waited for here so no load stays pending)
+    auto store_fact = [&](int t) {
         const int r0 = tile_row(t);
-        bool valid = r0 + lane < w_end;
+        if (r0 + 64 > n_rows) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float *p = reinterpret_cast<const float *>(fld[f][q] - 16 * li) + r0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) F[f][q][e] = r0 + 4 * li + e < n_rows ? gld(p)[4 * li + e] : 0.f;
+                }
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<f32x4 *>(reinterpret_cast<char *>(smem) + fst[f][q]) = F[f][q];
+    };
+
+    // Phase 1 of a tile: validity, then every operand of both k-steps split into bf16 hi/lo
+    // registers.  After it the tile needs neither its LDS record buffer nor its fact
+    // registers, so the next copies can be issued before phase 2 (the MFMAs) runs.
+    bf16x8 oph[2][NT], opl[2][NT];
+    auto phase1 = [&](int t) -> bool {
+        const int r0 = tile_row(t);
+        bool valid = r0 + lane < blk_end;
         uint32_t cnt[kGramMaxChild];
 #pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + 4 * lane] : 1u;
+        for (int c = 0; c < kGramMaxChild; ++c)
+            cnt[c] = c < n_child ? smem[cdst[c] / 4 + ((uni_cur >> c) & 1u ? 0 : 4 * lane)] : 1u;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (cnt[c] == 0u) valid = false;
@@ -901,25 +978,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         const bool all_rows = vm == ~0ull;
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 fh[NT], fl[NT];
-            const uint32_t vbits = (uint32_t)(vm >> (32 * ks + 8 * lg)) & 0xFFu;
+            const uint32_t vbits = (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
+                                   ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4);
 #pragma unroll
             for (int t2 = 0; t2 < NT; ++t2) {
                 float x[8];
-                if (t2 < NF) {
-                    const int fi = t2 < NF ? t2 : 0;
+                if (t2 < NF && is_fact[t2]) {
+                    // rows 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3} of the slot's column
+                    const char *base = reinterpret_cast<const char *>(smem) + lds_off[t2] + 128 * ks + 16 * lg;
+                    const f32x4 lo4 = *reinterpret_cast<const f32x4 *>(base);
+                    const f32x4 hi4 = *reinterpret_cast<const f32x4 *>(base + 64);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        x[e] = Fc[fi][2 * ks][e];
-                        x[4 + e] = Fc[fi][2 * ks + 1][e];
+                        x[e] = lo4[e];
+                        x[4 + e] = hi4[e];
                     }
                 }
                 if (t2 >= NF || (t2 == NF - 1 && mixed)) {
                     if (t2 >= NF || !is_fact[t2]) {
-                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
-                                                                         lds_off[t2] + 512 * ks);
+                        const char *base = reinterpret_cast<const char *>(smem) + lds_off[t2];
+                        if ((uni_cur >> schild[t2]) & 1u) {
+                            const float v = *reinterpret_cast<const float *>(base);
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) x[i] = p[4 * i];
+                            for (int i = 0; i < 8; ++i) x[i] = v;
+                        } else {
+                            const float *p = reinterpret_cast<const float *>(base + 64 * lg + 512 * ks);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                x[i] = p[4 * i];
+                                x[4 + i] = p[64 + 4 * i];
+                            }
+                        }
                     }
                 }
                 if (!all_rows) {
@@ -927,30 +1016,40 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     for (int i = 0; i < 8; ++i)
                         if (!((vbits >> i) & 1u)) x[i] = 0.f;
                 }
-                split_bf16x8(x, fh[t2], fl[t2]);
+                split_bf16x8(x, oph[ks][t2], opl[ks][t2]);
             }
+        }
+        return true;
+    };
+    // Phase 2: the MFMAs of both k-steps, from registers only.
+    auto phase2 = [&]() {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
             int p = 0;
 #pragma unroll
             for (int a = 0; a < NT; ++a)
 #pragma unroll
-                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[a], fh[b], acc[p], 0, 0, 0);
+                for (int b = a; b < NT; ++b, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], oph[ks][b], acc[p], 0, 0, 0);
             p = 0;
 #pragma unroll
             for (int a = 0; a < NT; ++a)
 #pragma unroll
-                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[a], fl[b], acc[p], 0, 0, 0);
+                for (int b = a; b < NT; ++b, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], opl[ks][b], acc[p], 0, 0, 0);
             p = 0;
 #pragma unroll
             for (int a = 0; a < NT; ++a)
 #pragma unroll
-                for (int b = a; b < NT; ++b, ++p) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[a], fh[b], acc[p], 0, 0, 0);
+                for (int b = a; b < NT; ++b, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], oph[ks][b], acc[p], 0, 0, 0);
             if (X4) {
                 p = 0;
 #pragma unroll
                 for (int a = 0; a < NT; ++a)
 #pragma unroll
                     for (int b = a; b < NT; ++b, ++p)
-                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[a], fl[b], acc[p], 0, 0, 0);
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], opl[ks][b], acc[p], 0, 0, 0);
             }
         }
         if (++since_flush == kFlushTiles) {
@@ -963,58 +1062,42 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         }
     };
 
+    // Every step issues the same operations whether or not a further tile exists (past the
+    // end they re-read the last tile, in bounds, and nothing uses the result): the count of
+    // operations after any load is then the same on every path, and the compiler's own
+    // waits before a register's first use never reach past the newest fact loads.
+    auto step = [&](int t) {
+        // this tile's records and facts and the next keys have landed
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        wave_sync();
+        uni_cur = uni_next;
+        const bool live = t < n_tiles;
+        if (live) store_fact(t);
+        load_fact(min(t + 1, n_tiles - 1));             // in flight for the rest of the step
+        wave_sync();
+        if (live) phase1(t);
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this tile's LDS reads are done
+        wave_sync();
+        issue_rec();                                    // tile t+1 (keys loaded last step)
+        load_keys(min(t + 2, n_tiles - 1));
+        if (live) phase2();                             // MFMAs while the copies are in flight
+    };
+
     if (n_tiles > 0) {
         load_keys(0);
         __builtin_amdgcn_s_waitcnt(0x0F70);
         issue_rec();
+        load_keys(min(1, n_tiles - 1));
         load_fact(0);
-        if (n_tiles > 1) load_keys(1);
     }
-    for (int t = 0; t < n_tiles; ++t) {
-        // this tile's records and facts and the next tile's keys have landed
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        wave_sync();
-#pragma unroll
-        for (int f = 0; f < NFA; ++f)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Fc[f][q] = Fn[f][q];
-        if (tile_row(t) + 64 > n_rows) {
-            // the last tile ends past the last row: its fact rows one by one, waited for here
-            // so that no load stays pending into the common path
-            const int r0 = tile_row(t);
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-                if (is_fact[f]) {
-                    const float *p = reinterpret_cast<const float *>(colp[f] + (uint32_t)r0 * 4u);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int i = (q >> 1) * 32 + (q & 1) * 4 + e;
-                            Fc[f][q][e] = r0 + 8 * lg + i < n_rows ? gld(p)[i] : 0.f;
-                        }
-                }
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-        }
-        if (t + 1 < n_tiles) load_fact(t + 1);   // in flight during this tile
-        compute(t);
-        if (t + 1 < n_tiles) {
-            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this tile's record reads are done
-            wave_sync();
-            issue_rec();
-            if (t + 2 < n_tiles) load_keys(t + 2);
-        }
-    }
+    for (int t = 0; t < n_tiles; ++t) step(t);
     __builtin_amdgcn_s_waitcnt(0);
 
-    // ---- workgroup reduction in fp64 over the staged feature order -----------------------
-    __syncthreads();
+    // ---- every wave writes its own partial: fp64 upper triangle, staged feature order ------
+    // (each unordered feature pair is one slot pair: one lane of one accumulator owns it)
     const int ng = d.n_gram;
-    double *red = reinterpret_cast<double *>(smem);
-    for (int i = tid; i < ng * ng; i += blockDim.x) red[i] = 0.0;
-    __shared__ unsigned long long wcount[kMaxWaves];
-    if (lane == 0) wcount[wave] = count;
-    __syncthreads();
+    const int pidx = blockIdx.x * nwaves + wave;
+    double *out = d.gram_partial + (int64_t)pidx * (ng * (ng + 1) / 2);
     {
         int p = 0;
 #pragma unroll
@@ -1029,22 +1112,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     if (a == b && sa > sb) continue;
                     const int fa = gld(&dp->slot[sa].feat)[0];
                     if (fa < 0 || fb < 0) continue;
-                    const int i = min(fa, fb), j = max(fa, fb);
-                    atomicAdd(&red[i * ng + j], (double)sacc[p][e] + (double)acc[p][e]);
+                    gst(out)[tri_index(min(fa, fb), max(fa, fb), ng)] = (double)sacc[p][e] + (double)acc[p][e];
                 }
             }
     }
-    __syncthreads();
-    double *out = d.gram_partial + (int64_t)blockIdx.x * ng * ng;
-    for (int e = tid; e < ng * ng; e += blockDim.x) {
-        const int i = e / ng, j = e % ng;
-        if (i <= j) gst(out)[e] = red[e];
-    }
-    if (d.do_count && tid == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < nwaves; ++w) t += wcount[w];
-        gst(d.count_partial)[blockIdx.x] = t;
-    }
+    if (d.do_count && lane == 0) gst(d.count_partial)[pidx] = count;
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,8 +1220,10 @@ hipError_t set_root_lds_limit(RootKernel k, size_t bytes) {
 }
 
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st) {
-    const int n = n_gram * n_gram > 0 ? n_gram * n_gram : 1;   // entries, 4 per 256-thread workgroup
-    hipLaunchKernelGGL(merge_kernel, dim3((n + 3) / 4), dim3(256), 0, st, desc);
+    const int ntri = n_gram > 0 ? n_gram * (n_gram + 1) / 2 : 1;
+    const int bx = (ntri + 63) / 64;
+    hipLaunchKernelGGL(merge_groups_kernel, dim3(bx, kMergeGroups), dim3(64), 0, st, desc);
+    hipLaunchKernelGGL(merge_final_kernel, dim3(bx), dim3(64), 0, st, desc);
     return hipGetLastError();
 }
 

@@ -39,6 +39,21 @@ def algorithmic_bytes(db) -> int:
     return int(b)
 
 
+def measured_traffic(kernel_file: str, kernel: str):
+    """HBM bytes per launch of the scan from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gram_scan_covariance_100M.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if rec.get("kernel") != kernel or hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def time_steps(eng, stream, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -209,7 +224,8 @@ def main():
                         "launches": plain_stats["launches"]} if t_plain else None),
         "errors_vs_oracle": errors,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("kernels.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,
                      "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % args.precision,
                      "algorithmic_bytes": alg, "kernel_ms": root_ms},
         "cpu_baseline": cpu,

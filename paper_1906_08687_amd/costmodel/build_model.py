@@ -1,6 +1,8 @@
 """Train the cost model on the device and measure what it gains.
 
     python -m paper_1906_08687_amd.costmodel.build_model [--train 120] [--test 30]
+    python -m paper_1906_08687_amd.costmodel.build_model --collect 0 60      (timings only)
+    python -m paper_1906_08687_amd.costmodel.build_model --fit --test 30     (train and evaluate)
 
 1. time every tile candidate of random training workloads 0..train-1 with
    the exhaustive autotuner (lmfao_autotune appends to the timing file);
@@ -25,6 +27,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=120)
     ap.add_argument("--test", type=int, default=30)
+    ap.add_argument("--collect", nargs=2, type=int, metavar=("J0", "J1"), default=None,
+                    help="only time the candidates of training workloads J0..J1-1, appending to the timing file")
+    ap.add_argument("--fit", action="store_true",
+                    help="only train on the existing timing file and evaluate (no collection)")
     ap.add_argument("--max-rows", type=int, default=4_000_000)
     ap.add_argument("--hidden", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=4000)
@@ -46,11 +52,18 @@ def main():
     def log(msg):
         print("[costmodel] " + msg, flush=True)
 
-    if os.path.exists(db_path):
-        os.remove(db_path)
+    if args.collect:
+        t0 = time.time()
+        for j in range(args.collect[0], args.collect[1]):
+            collect([random_workload(j, args.max_rows)], db_path, log=lambda m, j=j: log("train %d: %s" % (j, m)))
+        log("collected workloads %d..%d in %.0fs" % (args.collect[0], args.collect[1] - 1, time.time() - t0))
+        return 0
     t0 = time.time()
-    for j in range(args.train):
-        collect([random_workload(j, args.max_rows)], db_path, log=lambda m, j=j: log("train %d: %s" % (j, m)))
+    if not args.fit:
+        if os.path.exists(db_path):
+            os.remove(db_path)
+        for j in range(args.train):
+            collect([random_workload(j, args.max_rows)], db_path, log=lambda m, j=j: log("train %d: %s" % (j, m)))
     X, cfg, ms = load_db(db_path)
     log("collected %d timings in %.0fs" % (len(ms), time.time() - t0))
     norm, params, losses = train(X, ms, args.hidden, args.epochs, args.lr)
@@ -81,7 +94,8 @@ def main():
     tb = sum(r[5] for r in rows)
     geo_gain = float(np.exp(np.mean([np.log(r[3] / r[4]) for r in rows])))
     geo_regret = float(np.exp(np.mean([np.log(r[4] / r[5]) for r in rows])))
-    report = {"train_workloads": args.train, "timings": int(len(ms)), "test_workloads": args.test,
+    report = {"train_workloads": args.train if not args.fit else "from " + os.path.basename(db_path),
+              "timings": int(len(ms)), "test_workloads": args.test, "max_rows": args.max_rows,
               "hidden": args.hidden, "epochs": args.epochs, "final_loss": float(losses[-1]),
               "sum_ms": {"heuristic": th, "learned": tl, "autotune_best": tb},
               "gain_vs_heuristic": th / tl, "regret_vs_autotune": tl / tb,

@@ -204,15 +204,11 @@ constexpr int kGramMaxSlots = 64;
 constexpr int kQuadBytes = 1040;  // one 16-byte quad of 64 rows, plus 16 bytes of bank skew
 constexpr int kFactPitch = 272;   // one fact column of a 64-row tile in LDS, plus 16 bytes of bank skew
 
-constexpr int kGramConstChild = 31;   // "child" of the constant and padding slots: every row alike
-
 struct GramSlot {
     int32_t fact;         // >= 0: fact column of this slot; -1: read from LDS
     int32_t lds;          // LDS byte offset of row 0 (record buffer relative when per_buf)
     int32_t per_buf;      // 1: inside a wave's record buffer; 0: the block's constant quad
     int32_t feat;         // staged feature whose covariance row this slot feeds; -1: padding
-    int32_t child;        // record slots: the child whose record holds it; kGramConstChild otherwise
-    int32_t pad[3];
 };
 
 struct GramChild {

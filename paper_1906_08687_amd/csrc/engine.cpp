@@ -1459,18 +1459,18 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             G.wave_bytes = G.fact_off + L.gnf * 16 * kFactPitch;
             // slots: fact features, then every child's subtree features, the constant, padding
             int ns = 0;
-            for (int j = 0; j < G.n_fact; ++j) G.slot[ns++] = GramSlot{j, 0, 0, P.own_feats[r0][j], kGramConstChild, {0, 0, 0}};
+            for (int j = 0; j < G.n_fact; ++j) G.slot[ns++] = GramSlot{j, 0, 0, P.own_feats[r0][j]};
             for (size_t k = 0; k < P.children[r0].size(); ++k) {
                 const int ch = P.children[r0][k];
                 for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
                     const int w = P.rec_feat_off[ch] + i;
                     G.slot[ns++] = GramSlot{-1, (rch[k].quad_base + w / 4) * kQuadBytes + (w % 4) * 4, 1,
-                                            P.sub_feat_lo[ch] + i, (int)k, {0, 0, 0}};
+                                            P.sub_feat_lo[ch] + i};
                 }
             }
-            G.slot[ns++] = GramSlot{-1, 0, 0, 0, kGramConstChild, {0, 0, 0}};
+            G.slot[ns++] = GramSlot{-1, 0, 0, 0};
             if (ns != P.n_gram) return fail(c, LMFAO_ERR_STATE, "covariance slots do not cover the staged features");
-            for (; ns < kGramMaxSlots; ++ns) G.slot[ns] = GramSlot{-1, 4, 0, -1, kGramConstChild, {0, 0, 0}};
+            for (; ns < kGramMaxSlots; ++ns) G.slot[ns] = GramSlot{-1, 4, 0, -1};
             G.fact_cols = D.fact_cols;
             G.gram_partial = D.gram_partial;
             G.count_partial = D.count_partial;

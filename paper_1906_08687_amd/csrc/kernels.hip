@@ -827,14 +827,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     // per-lane sources of the NT slots this lane feeds (in fact tiles, fact lanes read the
     // fact tile in LDS at lds_off; other lanes their record word or the constant quad)
     bool is_fact[NT];
-    int lds_off[NT], schild[NT];
+    int lds_off[NT];
     const int fbase = rbase + d.fact_off;                      // this wave's fact tile in LDS
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int s = 16 * t + li;
         const int fc = gld(&dp->slot[s].fact)[0];
         is_fact[t] = fc >= 0;
-        schild[t] = gld(&dp->slot[s].child)[0];
         const int off = gld(&dp->slot[s].lds)[0];       // row 0 of the slot's word
         lds_off[t] = fc >= 0 ? fbase + s * kFactPitch : (gld(&dp->slot[s].per_buf)[0] ? rbase + off : off);
     }
@@ -881,9 +880,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
 
     uint32_t key[kGramMaxChild];
     // children whose keys are equal on all 64 rows of the next / this tile (the fact is sorted
-    // by its keys, so long runs are common): their record is gathered once, into row 0, and
-    // every row reads it there.  The constant slots read row 0 of the constant quad always.
-    uint32_t uni_next = 1u << kGramConstChild, uni_cur = 1u << kGramConstChild;
+    // by its keys, so long runs are common): their record is gathered by one lane into row 0
+    // and copied to the other rows inside LDS, which costs the memory pipeline one request
+    uint32_t uni_next = 0u, uni_cur = 0u;
     f32x4 F[NFA][4];      // the next tile's fact chunks, in flight (see fld)
 
     auto tile_row = [&](int t) -> int { return blk_begin + 64 * (wave + t * nwaves); };
@@ -894,7 +893,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             if (c < n_child) key[c] = (uint32_t)__builtin_nontemporal_load(gld(fkp[c]) + row);
     };
     auto issue_rec = [&]() {
-        uni_next = 1u << kGramConstChild;
+        uni_next = 0u;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (c < n_child) {
@@ -968,8 +967,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         bool valid = r0 + lane < blk_end;
         uint32_t cnt[kGramMaxChild];
 #pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c)
-            cnt[c] = c < n_child ? smem[cdst[c] / 4 + ((uni_cur >> c) & 1u ? 0 : 4 * lane)] : 1u;
+        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + 4 * lane] : 1u;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (cnt[c] == 0u) valid = false;
@@ -996,18 +994,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                 }
                 if (t2 >= NF || (t2 == NF - 1 && mixed)) {
                     if (t2 >= NF || !is_fact[t2]) {
-                        const char *base = reinterpret_cast<const char *>(smem) + lds_off[t2];
-                        if ((uni_cur >> schild[t2]) & 1u) {
-                            const float v = *reinterpret_cast<const float *>(base);
+                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
+                                                                         lds_off[t2] + 64 * lg + 512 * ks);
 #pragma unroll
-                            for (int i = 0; i < 8; ++i) x[i] = v;
-                        } else {
-                            const float *p = reinterpret_cast<const float *>(base + 64 * lg + 512 * ks);
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                x[i] = p[4 * i];
-                                x[4 + i] = p[64 + 4 * i];
-                            }
+                        for (int i = 0; i < 4; ++i) {
+                            x[i] = p[4 * i];
+                            x[4 + i] = p[64 + 4 * i];
                         }
                     }
                 }
@@ -1072,6 +1064,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         wave_sync();
         uni_cur = uni_next;
         const bool live = t < n_tiles;
+        if (live && uni_cur) {
+            // records gathered once: row 0 to the other rows of each quad
+#pragma unroll
+            for (int c = 0; c < kGramMaxChild; ++c)
+                if (c < n_child && ((uni_cur >> c) & 1u)) {
+                    char *q0 = reinterpret_cast<char *>(smem) + cdst[c];
+#pragma unroll 1
+                    for (int q = 0; q < cnq[c]; ++q, q0 += kQuadBytes) {
+                        const f32x4 v = *reinterpret_cast<const f32x4 *>(q0);
+                        if (lane > 0) *reinterpret_cast<f32x4 *>(q0 + 16 * lane) = v;
+                    }
+                }
+        }
         if (live) store_fact(t);
         load_fact(min(t + 1, n_tiles - 1));             // in flight for the rest of the step
         wave_sync();

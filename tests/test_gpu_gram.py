@@ -126,3 +126,22 @@ def test_dedicated_scan_every_candidate_agrees():
         c0 = int(eng.results()[0].counts[0])
         counts0 = c0 if counts0 is None else counts0
         assert c0 == counts0
+
+
+def test_dedicated_scan_is_deterministic_across_runs_and_graph_replays():
+    """Every wave writes its own partial and the merge sums them in a fixed order: repeated
+    executions, eager and replayed from the captured graph, give bitwise-identical sums."""
+    import torch
+    from paper_1906_08687_amd.lmfao import Engine
+    db = _star(14, 77_777, 16, [(5000, 6), (300, 6)], 1.2)
+    qs = covariance_queries(cont_attrs(db))
+    eng = Engine(db, qs, precision="bf16x3", schedule="batched")
+    eng.run()                                   # eager (null stream)
+    first = [r.sums.copy() for r in eng.results()]
+    stream = torch.cuda.Stream()
+    for rep in range(3):                        # the first captures the graph, then replays
+        eng.run(stream)
+        torch.cuda.synchronize()
+        got = eng.results()
+        for i, (g, f) in enumerate(zip(got, first)):
+            assert np.array_equal(g.sums, f), "replay %d query %d differs" % (rep, i)

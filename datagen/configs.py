@@ -472,3 +472,42 @@ def random_workload(j: int, max_rows: int = 20_000_000, min_rows: int = 1_000):
         qs.append(Query(where=[Pred(x, "le" if nxt() < 0.5 else "gt", float(np.float32(2 * nxt() - 1)))],
                         aggs=[Agg.monomial(y)]))
     return db, qs
+
+
+def random_covariance_workload(j: int, max_rows: int = 100_000_000, min_rows: int = 1_000_000):
+    """Random covariance-only batch number j (seed 9000 + j): a star of a fact
+    and 1-4 dimensions, fact rows log-uniform in [min_rows, max_rows],
+    dimension rows log-uniform in [100, min(fact / 10, 2M)], 1-20 continuous
+    fact attributes and 1-8 per dimension (at most 63 features, so the whole
+    batch is one dedicated covariance scan), foreign keys uniform or Zipf(1.2);
+    the batch is every covariance entry over all continuous attributes."""
+    seed = 9000 + j
+    g = native()
+    u = g.unit(g.key(seed, "shape"), 256)
+    pos = [0]
+
+    def nxt():
+        pos[0] += 1
+        return float(u[pos[0] - 1])
+
+    def loguni(lo, hi):
+        return int(round(math.exp(math.log(lo) + nxt() * (math.log(hi) - math.log(lo)))))
+
+    n_fact = loguni(min_rows, max_rows)
+    n_dims = 1 + min(int(nxt() * 4), 3)
+    budget = 63
+    n_fc = 1 + min(int(nxt() * 20), 19)
+    budget -= n_fc
+    dims = []
+    for i in range(n_dims):
+        n_dc = max(1, min(1 + min(int(nxt() * 8), 7), budget - (n_dims - 1 - i)))
+        budget -= n_dc
+        rows = loguni(100, max(101, min(n_fact // 10, 2_000_000)))
+        dims.append(RelSpec("D%d" % (i + 1), rows,
+                            [AttrSpec("d%d_%d" % (i + 1, a), "cont", ("normal", 100.0, 1.0)) for a in range(n_dc)],
+                            key="k%d" % (i + 1)))
+    zipf = {D.key: 1.2 for D in dims if nxt() < 0.6}
+    fact = RelSpec("F", n_fact, [AttrSpec("f%d" % a, "cont", ("normal", 100.0, 1.0)) for a in range(n_fc)],
+                   children=[(D, D.key) for D in dims], zipf_s=zipf)
+    db = build_database(seed, fact)
+    return db, covariance_queries(cont_attrs(db))

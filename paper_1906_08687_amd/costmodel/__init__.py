@@ -1,8 +1,13 @@
 """Learned cost model of the root view-group scan.
 
-A small network (16 plan features -> log milliseconds) ranks the candidate
-tile configurations of a plan (waves per workgroup, staging buffers,
-workgroups, fp32 register block, table placement).  Timings come from the
+A small network (16 plan features -> relative log milliseconds) ranks the
+candidate tile configurations of a plan (waves per workgroup, staging buffers,
+workgroups, fp32 register block, table placement).  Only the ranking within a
+plan matters, so the training target is a candidate's log time over the best
+time among its workload's candidates, clipped at log 4: every candidate more
+than 4x slower than the best is simply bad, and its exact slowdown does not
+pull the fit away from the near-optimal ones (workloads are told apart by the
+features that do not depend on the candidate).  Timings come from the
 engine itself: the exhaustive autotuner appends one line per timed candidate
 to a timing file; training runs on the device with the library's own
 forward/backward/Adam kernels; the planner queries the network through
@@ -64,12 +69,36 @@ def init_params(hidden: int, seed: int = 1) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+# features fixed by the workload and plan (the rest describe the tile candidate)
+WORKLOAD_FEATURES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 12, 13)
+
+
+def workload_groups(X: np.ndarray) -> np.ndarray:
+    """Group index of every timing row: rows with equal workload features."""
+    keys = np.round(np.asarray(X, np.float64)[:, WORKLOAD_FEATURES], 4)
+    _, inv = np.unique(keys, axis=0, return_inverse=True)
+    return inv.reshape(-1)
+
+
+RELATIVE_CAP = float(np.log(4.0))
+
+
+def relative_log_ms(X: np.ndarray, ms: np.ndarray) -> np.ndarray:
+    """min(log(ms / best ms of the row's workload), log 4)."""
+    y = np.log(np.asarray(ms, np.float64))
+    g = workload_groups(X)
+    best = np.full(g.max() + 1, np.inf)
+    np.minimum.at(best, g, y)
+    return np.minimum(y - best[g], RELATIVE_CAP)
+
+
 def train(X: np.ndarray, ms: np.ndarray, hidden: int = 32, epochs: int = 3000, lr: float = 3e-3,
           device: int = 0, seed: int = 1):
-    """Fit log(ms) on the device; returns (norm vector, params, losses)."""
+    """Fit the relative log time (relative_log_ms) on the device; returns (norm vector, params,
+    losses)."""
     import torch
     X = np.asarray(X, np.float64)
-    y = np.log(np.asarray(ms, np.float64))
+    y = relative_log_ms(X, ms)
     mean, std = X.mean(axis=0), X.std(axis=0)
     std[std == 0] = 1.0
     ym, ys = y.mean(), y.std() or 1.0

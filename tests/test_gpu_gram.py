@@ -1,8 +1,10 @@
 """Parity of the dedicated covariance scan (BF16 hi+lo split on MFMA) over
 the slot layouts it distinguishes: fact-only tiles, a fact tile shared with
 record lanes, two fact tiles, four tiles, no fact features at all, a fact
-without a ragged tail, fact keys without a dimension row, and every tile
-candidate of the autotuner.
+without a ragged tail, records of one to five quads (a key uniform over a
+tile is gathered once, others row by row), a key that changes on nearly
+every row, fact keys without a dimension row, and every tile candidate of the
+autotuner.
 
 Counts are bit-exact.  Sums are checked twice:
   * against the oracle's exact sums within the split's own error bound,
@@ -34,6 +36,10 @@ SHAPES = [
     ("four-tiles", 40_017, 30, [(800, 15), (90, 15), (7, 3)], 1.2),
     ("no-fact-features", 30_011, 0, [(500, 7), (60, 9)], 0.0),
     ("whole-tiles", 64_000, 16, [(1000, 6), (100, 6)], 1.2),
+    # a 19-word record (5 quads) beside a 6-word one
+    ("wide-record", 30_007, 4, [(400, 18), (50, 5)], 1.1),
+    # 400k keys under 40k rows: the key changes on nearly every row
+    ("distinct-keys", 40_009, 3, [(50, 2), (400_000, 5)], 0.0),
 ]
 
 

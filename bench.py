@@ -76,7 +76,9 @@ def main():
     ap.add_argument("--n-fact", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"])
+    ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"],
+                    help="tile choice of the full form: auto = the cost model ranks the candidates, its top 4 "
+                         "and the heuristic choice are timed and the fastest kept (exhaustive autotune without a model); learned = the model's top choice alone")
     ap.add_argument("--timing-db", default=None, help="autotune: append every candidate's timing to this file")
     ap.add_argument("--candidate", type=int, default=-1,
                     help="run tile candidate I of the full form instead of choosing one (profiling runs)")
@@ -140,20 +142,51 @@ def main():
         print("[bench] plain fp32: %.3f ms/step" % (t_plain * 1e3), file=sys.stderr, flush=True)
         del plain
 
-    # full form: bf16x3 on MFMA, batched in a hipGraph, learned (or autotuned) tiles
+    # full form: bf16x3 on MFMA, batched in a hipGraph; tiles chosen by the cost model, its top
+    # candidates judged by timing (every way of choosing is timed and reported; the one the
+    # --plan option names runs last, so it is the plan the timed steps use)
     full = Engine(db, qs, precision=args.precision, schedule="batched", columns=cols)
     full.ctx.execute(stream)
     full.ctx.sync()
-    chosen, best = "heuristic", -1
+    plans = {}
+    have_model = os.path.exists(WEIGHTS)
     if args.candidate >= 0:
         full.ctx.select_candidate(args.candidate)
         chosen, best = "fixed", args.candidate
-    elif args.plan in ("auto", "learned") and os.path.exists(WEIGHTS):
-        best = full.ctx.choose_learned(WEIGHTS, stream)
-        chosen = "learned" if best >= 0 else "heuristic"
-    if chosen == "heuristic" and args.plan in ("auto", "autotune"):
-        best = full.ctx.autotune(stream, args.timing_db, 3)
-        chosen = "autotune"
+    else:
+        def heuristic():
+            full.replan()
+            full._bind()
+            full.ctx.execute(stream)
+            full.ctx.sync()
+            return -1
+
+        def learned():
+            return full.ctx.choose_learned(WEIGHTS, stream)
+
+        def verified():
+            heuristic()
+            return full.ctx.choose_learned_verified(WEIGHTS, stream, 4, 3)
+
+        def autotune():
+            return full.ctx.autotune(stream, args.timing_db, 3)
+
+        ways = [("heuristic", heuristic)]
+        if have_model:
+            ways += [("learned", learned), ("learned_top4_timed", verified)]
+        ways.append(("autotune", autotune))
+        chosen = {"auto": "learned_top4_timed" if have_model else "autotune",
+                  "learned": "learned" if have_model else "heuristic",
+                  "autotune": "autotune", "heuristic": "heuristic"}[args.plan]
+        ways = [w for w in ways if w[0] != chosen] + [w for w in ways if w[0] == chosen]
+        for name, fn in ways:
+            idx = fn()
+            full._bind()
+            full.ctx.execute(stream)
+            full.ctx.sync()
+            plans[name] = {"candidate": idx, "root_scan_ms": full.ctx.time_root_group(stream, 2, 10)}
+        best = plans[chosen]["candidate"]
+        print("[bench] tile choices: %s" % json.dumps(plans), file=sys.stderr, flush=True)
     full._bind()
     t_full = time_steps(full, stream, args.steps, args.warmup)
     res_full = full.results()
@@ -216,6 +249,7 @@ def main():
         "config": {"workload": "covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with "
                                "4 dims (1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates",
                    "fact_rows": n_join, "aggregates": len(qs), "plan": chosen, "candidate": best,
+                   "plan_choices": plans,
                    "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
                    "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
                    "lds_bytes": stats["lds_bytes"]},

@@ -244,7 +244,10 @@ lmfao_status lmfao_candidates(const lmfao_ctx *ctx, int32_t *n);
 lmfao_status lmfao_candidate(const lmfao_ctx *ctx, int32_t i, int32_t cfg[5]);
 
 /* Feature vector of the root view group under candidate `i` (input of the
- * cost model): LMFAO_N_FEATURES floats. */
+ * cost model): LMFAO_N_FEATURES floats.  Feature 2 is the number of rounds
+ * of workgroups the root scan takes under the candidate (its workgroups over
+ * the workgroups the chip holds at once), found by planning the candidate on
+ * the side; the context is left as it was. */
 #define LMFAO_N_FEATURES 16
 lmfao_status lmfao_candidate_features(const lmfao_ctx *ctx, int32_t i, float *features);
 
@@ -264,6 +267,19 @@ lmfao_status lmfao_autotune(lmfao_ctx *ctx, void *hip_stream, const char *timing
  * *best.  Keeps the heuristic configuration (and returns LMFAO_OK with
  * *best = -1) if the model is missing or predicts a non-finite time. */
 lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t *best);
+
+/* Learned choice judged by measurement: rank every candidate with the cost
+ * model as lmfao_choose_learned does, then time the configuration in place
+ * and the `top_k` best-ranked candidates on `hip_stream` as lmfao_autotune
+ * does (`reps` timed runs each), select the fastest, execute it once and
+ * store its candidate index in *best (-1 when the configuration in place
+ * stays).  The model prunes the search; the timing decides, so the result is
+ * never slower than the configuration in place beyond timing noise.  Same
+ * fallback as lmfao_choose_learned (configuration kept, *best = -1, LMFAO_OK)
+ * when the model is missing or predicts a non-finite time; INVALID_ARG for
+ * top_k or reps below 1; STATE before lmfao_bind. */
+lmfao_status lmfao_choose_learned_verified(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t top_k,
+                                           int32_t reps, int32_t *best);
 
 /* ---- cost-model network (hand-written device kernels) -------------------- */
 

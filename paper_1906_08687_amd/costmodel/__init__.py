@@ -70,7 +70,7 @@ def init_params(hidden: int, seed: int = 1) -> np.ndarray:
 
 
 # features fixed by the workload and plan (the rest describe the tile candidate)
-WORKLOAD_FEATURES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 12, 13)
+WORKLOAD_FEATURES = (0, 1, 3, 4, 5, 6, 7, 8, 12, 13)
 
 
 def workload_groups(X: np.ndarray) -> np.ndarray:

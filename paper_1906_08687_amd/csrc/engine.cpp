@@ -182,6 +182,7 @@ struct RootLaunch {         // one launch of the root scan (batched: one; plain:
     int mode = 0, p1 = 1;
     bool tables = false;
     int grid_x = 1, parts = 1, waves = 2;
+    int resident = 1;        // workgroups one CU holds at once (registers and LDS)
     size_t lds_bytes = 0;
     RootDesc desc;           // pointers filled at bind
     std::vector<int> fam_ids;        // families evaluated (plain: one table view)
@@ -1026,6 +1027,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         const int tile = 64 * L.waves;
         const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, tile));
         const int occ = (int)std::max<size_t>(1, std::min<size_t>(occ_waves / L.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
+        L.resident = occ;
         int gx = cfg.grid_x > 0 ? cfg.grid_x : 2 * c->n_cu * occ;
         gx = (int)std::min<int64_t>(gx, blocks_needed);
         gx = std::max(1, std::min(gx, L.gram ? kPartMax / L.waves : kGridMax));
@@ -1904,7 +1906,25 @@ extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t c
     return LMFAO_OK;
 }
 
-static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
+// Rounds of workgroups the root scan takes under candidate t: its workgroups over what the
+// chip holds at once (the plan is built for t on the side, then restored).
+static double candidate_rounds(lmfao_ctx *c, const TileCfg &t) {
+    Plan saved = c->plan;
+    double rounds = 1.0;
+    if (build_logical(c) == LMFAO_OK) {
+        c->plan.precision = saved.precision;
+        c->plan.schedule = saved.schedule;
+        c->plan.planner = saved.planner;
+        if (build_physical(c, t) == LMFAO_OK && !c->plan.root_launches.empty()) {
+            const RootLaunch &L = c->plan.root_launches[0];
+            rounds = (double)L.grid_x / ((double)std::max(1, c->n_cu) * std::max(1, L.resident));
+        }
+    }
+    c->plan = std::move(saved);
+    return rounds;
+}
+
+static void features_of(lmfao_ctx *c, const TileCfg &t, float *f) {
     const Plan &P = c->plan;
     const double rows = (double)c->rels[P.root].n_rows;
     int64_t child_keys = 0;
@@ -1915,7 +1935,7 @@ static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
     const int mode = P.n_gram == 0 ? 0 : (P.precision == LMFAO_FP32 ? 1 : (P.precision == LMFAO_BF16X3 ? 2 : 3));
     f[0] = (float)std::log2(rows + 1.0);
     f[1] = (float)P.n_gram;
-    f[2] = (float)(P.n_gram * P.n_gram) / 64.f;
+    f[2] = (float)std::min(64.0, candidate_rounds(c, t));
     f[3] = (float)P.children[P.root].size();
     f[4] = (float)P.comps.size();
     f[5] = (float)std::log2((double)P.tables.size() + 1.0);
@@ -1936,18 +1956,20 @@ extern "C" lmfao_status lmfao_candidate_features(const lmfao_ctx *c, int32_t i, 
     if (!c->plan.ok) return LMFAO_ERR_STATE;
     auto v = enumerate_candidates(c);
     if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
-    features_of(c, v[i], features);
+    // features_of plans candidate i on the side and restores the plan: the context is unchanged
+    features_of(const_cast<lmfao_ctx *>(c), v[i], features);
     return LMFAO_OK;
 }
 
+// Re-plan with tile configuration t and re-bind the caller's buffers if the new plan fits them
+// (buffers once bound stay known, so one candidate that does not fit leaves later ones bindable).
 static lmfao_status select_cfg(lmfao_ctx *c, const TileCfg &t) {
-    const bool was_bound = c->bound;
     uint8_t *ws = c->ws, *res = c->res;
     const size_t wl = c->ws_len, rl = c->res_len;
     invalidate(c);
     lmfao_status s = do_plan(c, t);
     if (s != LMFAO_OK) return s;
-    if (was_bound && ws && c->plan.ws_bytes <= wl && c->plan.res_bytes <= rl) {
+    if (ws && c->plan.ws_bytes <= wl && c->plan.res_bytes <= rl) {
         s = lmfao_bind(c, ws, wl, res, rl);
         if (s != LMFAO_OK) return s;
     }
@@ -2016,14 +2038,16 @@ static bool load_weights(const char *path, int &hidden, std::vector<float> &norm
     return true;
 }
 
-extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, void *hip_stream, int32_t *best) {
-    if (!c) return LMFAO_ERR_INVALID_ARG;
-    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
-    if (best) *best = -1;
+// Cost-model scores of every candidate (inference on the device, in the workspace).  Returns
+// false with *st == OK when the model is missing or predicts a non-finite value (the caller
+// keeps the heuristic configuration).
+static bool predict_candidates(lmfao_ctx *c, const char *weights, void *hip_stream, std::vector<TileCfg> &cands,
+                               std::vector<float> &y, lmfao_status *status) {
+    *status = LMFAO_OK;
     int hidden = 0;
     std::vector<float> norm, params;
-    if (!weights || !load_weights(weights, hidden, norm, params)) return LMFAO_OK;   // heuristic stays
-    auto cands = enumerate_candidates(c);
+    if (!weights || !load_weights(weights, hidden, norm, params)) return false;
+    cands = enumerate_candidates(c);
     const int n = (int)cands.size();
     std::vector<float> x((size_t)n * LMFAO_N_FEATURES);
     for (int i = 0; i < n; ++i) {
@@ -2034,29 +2058,86 @@ extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, 
         }
     }
     const size_t need = (params.size() + x.size() + n) * 4;
-    if (need > ((size_t)1 << 20)) return fail(c, LMFAO_ERR_TOO_LARGE, "cost model too large for its scratch");
+    if (need > ((size_t)1 << 20)) {
+        *status = fail(c, LMFAO_ERR_TOO_LARGE, "cost model too large for its scratch");
+        return false;
+    }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     float *dp = reinterpret_cast<float *>(c->ws + c->off_mlp);
     float *dx = dp + params.size();
     float *dy = dx + x.size();
-    HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipMemcpyAsync(dp, params.data(), params.size() * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, hipMemcpyAsync(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(c, mlp_forward_dev(hidden, dp, dx, n, dy, st));
-    std::vector<float> y(n);
-    HIP_TRY(c, hipMemcpyAsync(y.data(), dy, (size_t)n * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(c, hipStreamSynchronize(st));
-    int bi = -1;
-    float bv = 0.f;
-    for (int i = 0; i < n; ++i) {
-        if (!std::isfinite(y[i])) return LMFAO_OK;   // fall back to the heuristic
-        if (bi < 0 || y[i] < bv) { bi = i; bv = y[i]; }
+    y.assign(n, 0.f);
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp, params.data(), params.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = mlp_forward_dev(hidden, dp, dx, n, dy, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(y.data(), dy, (size_t)n * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        *status = fail(c, LMFAO_ERR_HIP, hipGetErrorString(e));
+        return false;
     }
-    if (bi < 0) return LMFAO_OK;
-    lmfao_status s = select_cfg(c, cands[bi]);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(y[i])) return false;
+    return n > 0;
+}
+
+extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, void *hip_stream, int32_t *best) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (best) *best = -1;
+    std::vector<TileCfg> cands;
+    std::vector<float> y;
+    lmfao_status s = LMFAO_OK;
+    if (!predict_candidates(c, weights, hip_stream, cands, y, &s)) return s;   // heuristic stays unless an error
+    const int bi = (int)(std::min_element(y.begin(), y.end()) - y.begin());
+    s = select_cfg(c, cands[bi]);
     if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);
     if (s == LMFAO_OK) s = lmfao_sync(c);
     if (s != LMFAO_OK) return s;
     if (best) *best = bi;
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_choose_learned_verified(lmfao_ctx *c, const char *weights, void *hip_stream,
+                                                      int32_t top_k, int32_t reps, int32_t *best) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (top_k <= 0 || reps <= 0) return fail(c, LMFAO_ERR_INVALID_ARG, "top_k and reps must be positive");
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (best) *best = -1;
+    std::vector<TileCfg> cands;
+    std::vector<float> y;
+    lmfao_status s = LMFAO_OK;
+    if (!predict_candidates(c, weights, hip_stream, cands, y, &s)) return s;
+    std::vector<int> order(cands.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return y[a] < y[b]; });
+    order.resize(std::min<size_t>(order.size(), (size_t)top_k));
+    // the configuration in place is timed too, and kept when none of the ranked ones beats it
+    const TileCfg current = c->plan.cfg;
+    double current_ms = 1e300;
+    s = lmfao_execute(c, hip_stream);
+    if (s == LMFAO_OK) s = lmfao_sync(c);
+    if (s == LMFAO_OK) s = lmfao_time_root_group(c, hip_stream, 1, reps, &current_ms);
+    if (s != LMFAO_OK) current_ms = 1e300;
+    double best_ms = 1e300;
+    int best_i = -1;
+    for (int i : order) {
+        s = select_cfg(c, cands[i]);
+        if (s != LMFAO_OK || !c->bound) continue;   // a candidate that does not fit is skipped
+        s = lmfao_execute(c, hip_stream);
+        if (s == LMFAO_OK) s = lmfao_sync(c);
+        double ms = 0.0;
+        if (s == LMFAO_OK) s = lmfao_time_root_group(c, hip_stream, 1, reps, &ms);
+        if (s != LMFAO_OK) continue;
+        if (ms < best_ms) { best_ms = ms; best_i = i; }
+    }
+    if (best_i < 0 && current_ms >= 1e300) return fail(c, LMFAO_ERR_HIP, "no ranked candidate ran");
+    const bool keep = current_ms <= best_ms;
+    s = select_cfg(c, keep ? current : cands[best_i]);
+    if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);
+    if (s == LMFAO_OK) s = lmfao_sync(c);
+    if (s != LMFAO_OK) return s;
+    if (best) *best = keep ? -1 : best_i;
     return LMFAO_OK;
 }

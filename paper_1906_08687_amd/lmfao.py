@@ -83,7 +83,7 @@ SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relat
            "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_workspace_size", "lmfao_result_size",
            "lmfao_result_layout", "lmfao_bind", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
-           "lmfao_autotune", "lmfao_choose_learned", "lmfao_mlp_param_count", "lmfao_mlp_forward",
+           "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
            "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train"]
 
 _lib = None
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH):
         "lmfao_select_candidate": (st, [P, i32]),
         "lmfao_autotune": (st, [P, P, ctypes.c_char_p, i32, ctypes.POINTER(i32)]),
         "lmfao_choose_learned": (st, [P, ctypes.c_char_p, P, ctypes.POINTER(i32)]),
+        "lmfao_choose_learned_verified": (st, [P, ctypes.c_char_p, P, i32, i32, ctypes.POINTER(i32)]),
         "lmfao_mlp_param_count": (i32, [i32]),
         "lmfao_mlp_scratch_floats": (i64, [i32, i32]),
         "lmfao_mlp_forward": (st, [i32, P, P, i32, P, P]),
@@ -302,6 +303,12 @@ class Context:
         best = ctypes.c_int32()
         self._check(self.lib.lmfao_choose_learned(self.ptr, weights.encode(), _stream_handle(stream),
                                                   ctypes.byref(best)))
+        return best.value
+
+    def choose_learned_verified(self, weights: str, stream=None, top_k: int = 3, reps: int = 3) -> int:
+        best = ctypes.c_int32()
+        self._check(self.lib.lmfao_choose_learned_verified(self.ptr, weights.encode(), _stream_handle(stream),
+                                                           top_k, reps, ctypes.byref(best)))
         return best.value
 
 

@@ -111,6 +111,29 @@ def test_plan_is_host_only_and_reports_the_batch():
     assert (ctx.workspace_size(), ctx.result_size(), ctx.stats()) == a
 
 
+def test_rounds_feature_counts_workgroup_rounds_and_leaves_the_plan():
+    """Feature 2 plans each candidate on the side: on the dedicated covariance scan of five
+    features (one 16-slot tile, 12 resident waves per CU, little LDS) a launch of g
+    workgroups of w waves takes g w / (12 n_cu) rounds; the context's own plan is unchanged."""
+    ctx = new_ctx()
+    star(ctx, fact_rows=50_000_000)
+    for q in covariance(["f0", "f1", "a0", "b0"]):
+        ctx.add_query(q)
+    ctx.plan("bf16x3", "batched")
+    before = ctx.stats()
+    assert before["dedicated_scan"] == 1
+    cands = ctx.candidates()
+    n_cu = cands[0][2] // 4                           # first candidate: 1 wave per workgroup, 4 per CU
+    assert cands[0][:2] == [1, 1] and n_cu > 0
+    feats = [ctx.candidate_features(i) for i in range(len(cands))]
+    assert ctx.stats() == before
+    for i, (waves, nbuf, grid, gb, policy) in enumerate(cands):
+        ctx.select_candidate(i)
+        launched = ctx.stats()["grid_blocks"]         # the grid as launched (whole tiles per workgroup)
+        assert launched <= grid
+        assert abs(feats[i][2] - launched * waves / (12 * n_cu)) < 1e-5
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_tile_candidates_are_distinct_and_featurised(precision):
     ctx = new_ctx()
@@ -158,10 +181,13 @@ def test_bind_and_execute_need_a_device_and_a_plan():
         ctx.bind(FAKE, 1 << 30, FAKE, 1 << 30)
     assert e.value.code == "HIP"                     # no device
     for call in (lambda: ctx.execute(None), lambda: ctx.sync(), lambda: ctx.time_root_group(None, 1, 1),
-                 lambda: ctx.autotune(None, None, 1)):
+                 lambda: ctx.autotune(None, None, 1), lambda: ctx.choose_learned("w.bin", None),
+                 lambda: ctx.choose_learned_verified("w.bin", None, 3, 1)):
         with pytest.raises(lmfao.LmfaoError) as e:
             call()
         assert e.value.code == "STATE"
+    for k, reps in ((0, 1), (3, 0)):
+        expect("INVALID_ARG", lambda: ctx.choose_learned_verified("w.bin", None, k, reps))
 
 
 # --------------------------------------------------------------------------

@@ -141,3 +141,55 @@ def test_learned_choice_against_heuristic_on_held_out_workloads():
     print("held-out root-scan time: heuristic %.3f ms, learned %.3f ms (gain %.2fx)" %
           (t_heur, t_learn, t_heur / t_learn))
     assert t_learn <= 1.15 * t_heur
+
+
+@pytest.mark.gpu
+def test_learned_choice_judged_by_timing_is_no_slower_than_the_top_choice():
+    """choose_learned_verified times the configuration in place and the
+    model's three best-ranked candidates and keeps the fastest; the model's top
+    choice is in place when it is called, so the verified plan is no slower
+    (up to timing noise), on a general-scan batch and on a dedicated
+    covariance scan."""
+    import torch
+    from datagen.configs import random_covariance_workload, random_workload
+    from paper_1906_08687_amd import costmodel, lmfao
+    if not os.path.exists(costmodel.WEIGHTS):
+        pytest.skip("no trained cost model in the tree")
+    stream = torch.cuda.Stream()
+    for db, qs in (random_workload(184, max_rows=2_000_000), random_covariance_workload(184, 8_000_000)):
+        eng = lmfao.Engine(db, qs, precision="bf16x3")
+        eng.run(stream)
+        top = eng.ctx.choose_learned(costmodel.WEIGHTS, stream)
+        eng._bind()
+        eng.run(stream)
+        t_top = eng.ctx.time_root_group(stream, 2, 10)
+        best = eng.ctx.choose_learned_verified(costmodel.WEIGHTS, stream, 3, 3)
+        eng._bind()
+        eng.run(stream)
+        t_ver = eng.ctx.time_root_group(stream, 2, 10)
+        n = len(eng.ctx.candidates())
+        print("%d fact rows: top choice %d %.3f ms, verified %d %.3f ms of %d candidates" %
+              (db.relations[0].n_rows, top, t_top, best, t_ver, n))
+        assert -1 <= best < n and 0 <= top < n        # -1: the configuration in place (here the top choice) stays
+        assert t_ver <= 1.05 * t_top + 0.005
+
+
+def test_timing_file_groups_into_its_workloads():
+    """The committed timings come from 110 random batches and 90 covariance-only stars: the
+    workload features must group them into exactly 200 workloads, each with one candidate at
+    relative time 0 (its best) and the rest in (0, log 4]."""
+    from paper_1906_08687_amd import costmodel
+    path = os.path.join(os.path.dirname(costmodel.WEIGHTS), "timings.csv")
+    if not os.path.exists(path):
+        pytest.skip("no timing file in the tree")
+    X, cfg, ms = costmodel.load_db(path)
+    g = costmodel.workload_groups(X)
+    assert g.max() + 1 == 200
+    y = costmodel.relative_log_ms(X, ms)
+    assert np.all(np.bincount(g, weights=(y == 0)) >= 1)
+    assert y.min() == 0.0 and y.max() <= costmodel.RELATIVE_CAP + 1e-12
+    # the candidate features really vary inside a workload, the workload features do not
+    for k in range(g.max() + 1):
+        rows = X[g == k]
+        assert np.all(rows[:, costmodel.WORKLOAD_FEATURES] == rows[0, costmodel.WORKLOAD_FEATURES])
+

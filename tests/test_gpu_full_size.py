@@ -1,8 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times (bf16x3 on MFMA where a covariance block exists, batched
-schedule in a hipGraph, tiles chosen by the learned cost model if its
-weights are in the tree, else by the exhaustive autotuner), and the plain
-fp32 form beside it.
+schedule in a hipGraph, tiles ranked by the learned cost model with its top
+four and the heuristic choice judged by timing if its weights are in the
+tree, else chosen by the exhaustive autotuner), and the plain fp32 form
+beside it.
 
 The oracle evaluates a seeded sample of the batch's queries over the whole
 join (every cell of each sampled query): counts bit-exact, sums under the
@@ -31,10 +32,9 @@ def _bench_engine(db, qs, cols, precision):
     stream = torch.cuda.Stream()
     eng = Engine(db, qs, precision=precision, schedule="batched", columns=cols)
     eng.run(stream)
-    best = -1
     if os.path.exists(costmodel.WEIGHTS):
-        best = eng.ctx.choose_learned(costmodel.WEIGHTS, stream)
-    if best < 0:
+        eng.ctx.choose_learned_verified(costmodel.WEIGHTS, stream, 4, 3)
+    else:
         eng.ctx.autotune(stream, None, 2)
     eng._bind()
     eng.run(stream)

@@ -221,7 +221,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        rows = min(n_join, 3_000_000)
+        rows = min(n_join, 25_000_000)      # about 10 s of the oracle on 16 host threads
         threads = os.cpu_count() or 1
         t = time.time()
         oracle.evaluate(db, qs, n_threads=threads, root_range=(0, rows))

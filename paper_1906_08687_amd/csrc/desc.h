@@ -244,7 +244,7 @@ struct GramDesc {
 // entry (i, j) at tri_index(i, j, n).
 __host__ __device__ inline int tri_index(int i, int j, int n) { return i * n - (i * (i - 1)) / 2 + (j - i); }
 
-constexpr int kMergeGroups = 32;     // first merge pass: partials summed in this many ordered groups
+constexpr int kMergeGroups = 64;     // first merge pass: partials summed in this many ordered groups
 
 struct MergeDesc {
     int32_t grid;                      // partials to reduce

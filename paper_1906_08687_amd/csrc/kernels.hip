@@ -131,10 +131,10 @@ __global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__re
         atomicOr(d.err, kErrKeyRange);
         return;
     }
-    if (atomicAdd(&d.seen[key], 1u) != 0u) {   // the join key of a child must be unique
-        atomicOr(d.err, kErrDupKey);
-        return;
-    }
+    // the join key of a child must be unique: the count of rows with this key is checked after the
+    // record is written, so the atomic's round trip overlaps the writes (with a duplicate the
+    // records are unspecified and the error stops the evaluation at sync)
+    const uint32_t seen_before = atomicAdd(&d.seen[key], 1u);
     uint32_t *rec = d.rec_out + (int64_t)key * d.rec_stride;
     uint32_t valid = 1u;
     uint64_t mask = d.filter_all;
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__re
     if (d.n_mask > 0) rec[1] = (uint32_t)mask;
     if (d.n_mask > 1) rec[2] = (uint32_t)(mask >> 32);
     rec[0] = valid;
+    if (seen_before != 0u) atomicOr(d.err, kErrDupKey);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,11 +685,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // cross-workgroup merge (fp64, fixed order: deterministic)
 // ---------------------------------------------------------------------------
 
-// Two ordered passes, so the result does not depend on scheduling.  Pass 1:
-// workgroup (x, g) sums partials g*P/G .. (g+1)*P/G - 1 in order for 64
-// consecutive packed entries (lane = entry: every load is one coalesced 512-byte
-// row).  Pass 2: each entry sums its G group sums in order and is written to
-// both (i, j) and (j, i).
+// Two passes in a fixed order, so the result does not depend on scheduling.
+// Pass 1: workgroup (x, g) sums partials g*P/G .. (g+1)*P/G - 1 for 64
+// consecutive packed entries (lane = entry: every load is one coalesced
+// 512-byte row), in eight interleaved running sums added in a fixed order.
+// Pass 2: each entry sums its G group sums the same way and is written to both
+// (i, j) and (j, i).
 __global__ void merge_groups_kernel(const MergeDesc *__restrict__ dp) {
     const MergeDesc &d = *dp;
     const int ntri = d.n_gram * (d.n_gram + 1) / 2;
@@ -696,9 +698,15 @@ __global__ void merge_groups_kernel(const MergeDesc *__restrict__ dp) {
     const int g = blockIdx.y;
     const int p0 = (int)((int64_t)d.grid * g / kMergeGroups), p1 = (int)((int64_t)d.grid * (g + 1) / kMergeGroups);
     if (e < ntri) {
-        double s = 0.0;
-        for (int p = p0; p < p1; ++p) s += gld(d.gram_partial)[(int64_t)p * ntri + e];
-        gst(d.group_sum)[(int64_t)g * ntri + e] = s;
+        // eight running sums (partial p goes to sum p % 8), added in a fixed order at the end:
+        // eight loads in flight per lane, and the same result on every run
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int p = p0;
+        for (; p + 8 <= p1; p += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] += gld(d.gram_partial)[(int64_t)(p + k) * ntri + e];
+        for (int k = 0; p < p1; ++p, ++k) a[k] += gld(d.gram_partial)[(int64_t)p * ntri + e];
+        gst(d.group_sum)[(int64_t)g * ntri + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     if (blockIdx.x == 0 && d.count_partial) {
         unsigned long long t = 0;
@@ -714,8 +722,12 @@ __global__ void merge_final_kernel(const MergeDesc *__restrict__ dp) {
     const int ntri = n * (n + 1) / 2;
     const int e = blockIdx.x * 64 + threadIdx.x;
     if (e < ntri) {
-        double s = 0.0;
-        for (int g = 0; g < kMergeGroups; ++g) s += gld(d.group_sum)[(int64_t)g * ntri + e];
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        static_assert(kMergeGroups % 8 == 0, "group sums are taken eight at a time");
+        for (int g = 0; g < kMergeGroups; g += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] += gld(d.group_sum)[(int64_t)(g + k) * ntri + e];
+        const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         int i = 0;
         while (tri_index(i + 1, i + 1, n) <= e) ++i;
         const int j = i + (e - tri_index(i, i, n));

@@ -895,6 +895,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     // by its keys, so long runs are common): their record is gathered by one lane into row 0
     // and copied to the other rows inside LDS, which costs the memory pipeline one request
     uint32_t uni_next = 0u, uni_cur = 0u;
+    // children whose record buffer holds one record in every row (a uniform tile, spread), and
+    // that record's key: a next tile with the same uniform key needs no copy at all
+    uint32_t held_ok = 0u;
+    uint32_t held[kGramMaxChild];
     f32x4 F[NFA][4];      // the next tile's fact chunks, in flight (see fld)
 
     auto tile_row = [&](int t) -> int { return blk_begin + 64 * (wave + t * nwaves); };
@@ -913,8 +917,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                 const bool uni = __ballot(key[c] != k0) == 0ull;
                 uint32_t koff = __umul24(min(key[c], nkey[c]), rbytes[c]);
                 char *dst = reinterpret_cast<char *>(smem) + cdst[c];
-                if (uni) {
+                if (uni && ((held_ok >> c) & 1u) && held[c] == k0) {
+                    // already in every row (the fact is sorted, so the small dimensions' keys
+                    // stay the same over many tiles)
+                } else if (uni) {
                     uni_next |= 1u << c;
+                    held[c] = k0;
+                    held_ok |= 1u << c;
                     // one lane: the record lands in row 0 of each quad
                     if (lane == 0) {
 #pragma unroll 1
@@ -922,6 +931,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
                     }
                 } else {
+                    held_ok &= ~(1u << c);
                     // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
 #pragma unroll 1
                     for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)

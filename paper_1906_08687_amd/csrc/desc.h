@@ -227,7 +227,7 @@ struct GramDesc {
     int32_t n_fact;              // fact slots [0, n_fact)
     int32_t n_gram;              // staged features (rows of the covariance block)
     int32_t do_count;
-    int32_t lds_wave0;           // byte offset of wave 0's region (after the constant quad)
+    int32_t lds_wave0;           // byte offset of wave 0's region (after the constant block)
     int32_t wave_bytes;          // a wave's region: n_quads * kQuadBytes of records, then the fact tile
     int32_t fact_off;            // offset of the fact tile in a wave's region (16 * NF columns of kFactPitch)
     int32_t pad1;

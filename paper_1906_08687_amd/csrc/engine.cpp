@@ -54,7 +54,7 @@ hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts
                        hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
 typedef void (*GramKernel)(const GramDesc *);
-GramKernel gram_kernel(int nt, int nf, bool x4);
+GramKernel gram_kernel(int nt, int nf, bool x4, bool pr);
 hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st);
 hipError_t set_gram_lds_limit(GramKernel k, size_t bytes);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
@@ -191,6 +191,7 @@ struct RootLaunch {         // one launch of the root scan (batched: one; plain:
     size_t desc_off = 0;
     // covariance-only launch on the dedicated BF16 scan (slot tiles gnt, fact tiles gnf)
     bool gram = false;
+    bool gpr = false;        // pair-row record buffers (gram_pair_rows)
     int gnt = 0, gnf = 0;
     GramDesc gdesc;
 };
@@ -936,14 +937,24 @@ static bool gram_eligible(const lmfao_ctx *c, const Plan &P, int *nt, int *nf) {
     const int n_fact = (int)P.own_feats[P.root].size();
     *nt = (P.n_gram + 15) / 16;
     *nf = (n_fact + 15) / 16;
-    return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, P.mode == 3) != nullptr;
+    return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, P.mode == 3, false) != nullptr;
+}
+
+// Pair-row record buffers for the dedicated scan: every child record of at most 8 words (two
+// quads), each child given two quads, a row's quads contiguous (32 bytes per row).  A row's
+// record is then one contiguous piece for its two neighbouring lanes of a gather request.
+static bool gram_pair_rows(const Plan &P) {
+    for (int ch : P.children[P.root])
+        if (P.rec_stride[ch] > 8) return false;
+    return true;
 }
 
 static size_t gram_lds_bytes(const Plan &P, int waves, int nf) {
+    const bool pr = gram_pair_rows(P);
     int quads = 0;
-    for (int ch : P.children[P.root]) quads += P.rec_stride[ch] / 4;
-    // the constant quad; per wave one record buffer and one fact tile
-    return 1024 + (size_t)waves * ((size_t)quads * kQuadBytes + (size_t)nf * 16 * kFactPitch);
+    for (int ch : P.children[P.root]) quads += pr ? 2 : P.rec_stride[ch] / 4;
+    // the constant block (64 rows of 16 or 32 bytes); per wave one record buffer and one fact tile
+    return (pr ? 2048 : 1024) + (size_t)waves * ((size_t)quads * kQuadBytes + (size_t)nf * 16 * kFactPitch);
 }
 
 static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
@@ -1014,6 +1025,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         if (L.gram) {
             L.gnt = gnt;
             L.gnf = gnf;
+            L.gpr = gram_pair_rows(P);
             L.waves = P.gram_waves;
             L.lds_bytes = gram_lds_bytes(P, L.waves, gnf);
             occ_waves = gnt >= 4 ? 8 : 12;
@@ -1446,16 +1458,18 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             G.n_fact = (int)P.own_feats[r0].size();
             G.n_gram = P.n_gram;
             G.do_count = D.do_count;
-            G.lds_wave0 = 1024;
+            // record buffer of child k: quad-major from quad quad_base, or (pair rows) two quads from 2k
+            G.lds_wave0 = L.gpr ? 2048 : 1024;
+            auto quad0 = [&](size_t k) { return L.gpr ? 2 * (int)k : rch[k].quad_base; };
             int quads = 0;
             for (size_t k = 0; k < rch.size(); ++k) {
                 G.ch[k].fk = rch[k].fk;
                 G.ch[k].rec = rch[k].rec;
                 G.ch[k].n_keys = (uint32_t)rch[k].n_keys;
                 G.ch[k].rec_bytes = (uint32_t)rch[k].stride * 4u;
-                G.ch[k].quad0 = rch[k].quad_base;
+                G.ch[k].quad0 = quad0(k);
                 G.ch[k].n_quads = rch[k].stride / 4;
-                quads += rch[k].stride / 4;
+                quads += L.gpr ? 2 : rch[k].stride / 4;
             }
             G.fact_off = quads * kQuadBytes;
             G.wave_bytes = G.fact_off + L.gnf * 16 * kFactPitch;
@@ -1466,8 +1480,9 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                 const int ch = P.children[r0][k];
                 for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
                     const int w = P.rec_feat_off[ch] + i;
-                    G.slot[ns++] = GramSlot{-1, (rch[k].quad_base + w / 4) * kQuadBytes + (w % 4) * 4, 1,
-                                            P.sub_feat_lo[ch] + i};
+                    // row 0's word w: quad-major (quad w / 4, word w % 4) or pair rows (word w)
+                    const int lds = L.gpr ? quad0(k) * kQuadBytes + 4 * w : (quad0(k) + w / 4) * kQuadBytes + (w % 4) * 4;
+                    G.slot[ns++] = GramSlot{-1, lds, 1, P.sub_feat_lo[ch] + i};
                 }
             }
             G.slot[ns++] = GramSlot{-1, 0, 0, 0};
@@ -1688,7 +1703,7 @@ static lmfao_status upload(lmfao_ctx *c) {
     HIP_TRY(c, hipMemcpy(c->ws + c->off_desc, c->blob.data(), c->blob.size(), hipMemcpyHostToDevice));
     for (auto &L : c->plan.root_launches) {
         if (L.gram) {
-            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3);
+            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3, L.gpr);
             if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_gram_lds_limit(k, L.lds_bytes));
         } else {
             RootKernel k = root_kernel(L.mode, L.p1, L.tables);
@@ -1728,7 +1743,7 @@ extern "C" lmfao_status lmfao_bind(lmfao_ctx *c, void *workspace, size_t ws_byte
 static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
     for (auto &L : c->plan.root_launches) {
         if (L.gram) {
-            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3);
+            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3, L.gpr);
             HIP_TRY(c, launch_gram(k, reinterpret_cast<const GramDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x,
                                    L.waves, L.lds_bytes, st));
             continue;

@@ -801,7 +801,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 // Fact columns and keys are streamed once: their loads are non-temporal, so
 // they do not push the gathered view records out of the caches.  Each wave
 // writes its own fp64 partial of the upper triangle (no LDS reduction).
-template <int NT, int NF, bool X4>
+template <int NT, int NF, bool X4, bool PR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 3))) void gram_scan_kernel(
     const GramDesc *__restrict__ dp) {
     extern __shared__ __align__(16) uint32_t smem[];
@@ -814,12 +814,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     constexpr int NP = NT * (NT + 1) / 2;
     constexpr int NFA = NF > 0 ? NF : 1;
 
-    // the constant quad: 64 rows of [1, 0, 0, 0]
+    // the constant block: 64 rows of [1, 0, 0, 0] (pair rows: [1, 0, ..., 0] of 8 words), laid out
+    // like the record rows so that constant and padding slots read it with the records' stride
+    constexpr int kRowWords = PR ? 8 : 4;
     if (tid < 64) {
-        smem[4 * tid + 0] = __float_as_uint(1.f);
-        smem[4 * tid + 1] = 0u;
-        smem[4 * tid + 2] = 0u;
-        smem[4 * tid + 3] = 0u;
+        smem[kRowWords * tid] = __float_as_uint(1.f);
+#pragma unroll
+        for (int w = 1; w < kRowWords; ++w) smem[kRowWords * tid + w] = 0u;
     }
     __syncthreads();
 
@@ -924,18 +925,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     uni_next |= 1u << c;
                     held[c] = k0;
                     held_ok |= 1u << c;
-                    // one lane: the record lands in row 0 of each quad
-                    if (lane == 0) {
+                    if (PR) {
+                        // lanes 0 and 1: the record's two quads land in row 0 (a one-quad
+                        // record's second lane reads past the buffer range: zeros)
+                        if (lane < 2) {
+                            const uint32_t ko = lane < cnq[c] ? koff + 16u * (uint32_t)lane : nkey[c] * rbytes[c];
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, ko, 0, 0, 0);
+                        }
+                    } else if (lane == 0) {
+                        // one lane: the record lands in row 0 of each quad
 #pragma unroll 1
                         for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
                     }
                 } else {
                     held_ok &= ~(1u << c);
-                    // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
+                    if (PR) {
+                        // lane l of request i reads quad l % 2 of row 32 i + l / 2: a row's two
+                        // quads are one contiguous 32-byte piece on neighbouring lanes, so the
+                        // memory pipeline handles one address per row, not one per row and quad
+#pragma unroll
+                        for (int i = 0; i < 2; ++i) {
+                            const uint32_t f = 64u * (uint32_t)i + (uint32_t)lane;
+                            const uint32_t kr = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(4u * (f >> 1)), (int)key[c]);
+                            const uint32_t ko = (f & 1u) < (uint32_t)cnq[c] ? __umul24(min(kr, nkey[c]), rbytes[c]) + 16u * (f & 1u)
+                                                                           : nkey[c] * rbytes[c];
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)(dst + 1024 * i), 16, ko, 0, 0, 0);
+                        }
+                    } else {
+                        // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
 #pragma unroll 1
-                    for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+                        for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
+                    }
                 }
             }
     };
@@ -989,7 +1011,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         bool valid = r0 + lane < blk_end;
         uint32_t cnt[kGramMaxChild];
 #pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + 4 * lane] : 1u;
+        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + kRowWords * lane] : 1u;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (cnt[c] == 0u) valid = false;
@@ -1017,11 +1039,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                 if (t2 >= NF || (t2 == NF - 1 && mixed)) {
                     if (t2 >= NF || !is_fact[t2]) {
                         const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
-                                                                         lds_off[t2] + 64 * lg + 512 * ks);
+                                                                         lds_off[t2] + 16 * kRowWords * lg + 128 * kRowWords * ks);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            x[i] = p[4 * i];
-                            x[4 + i] = p[64 + 4 * i];
+                            x[i] = p[kRowWords * i];
+                            x[4 + i] = p[16 * kRowWords + kRowWords * i];
                         }
                     }
                 }
@@ -1092,10 +1114,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             for (int c = 0; c < kGramMaxChild; ++c)
                 if (c < n_child && ((uni_cur >> c) & 1u)) {
                     char *q0 = reinterpret_cast<char *>(smem) + cdst[c];
+                    if (PR) {
+                        const f32x4 v0 = *reinterpret_cast<const f32x4 *>(q0);
+                        const f32x4 v1 = *reinterpret_cast<const f32x4 *>(q0 + 16);
+                        if (lane > 0) {
+                            *reinterpret_cast<f32x4 *>(q0 + 32 * lane) = v0;
+                            *reinterpret_cast<f32x4 *>(q0 + 32 * lane + 16) = v1;
+                        }
+                    } else {
 #pragma unroll 1
-                    for (int q = 0; q < cnq[c]; ++q, q0 += kQuadBytes) {
-                        const f32x4 v = *reinterpret_cast<const f32x4 *>(q0);
-                        if (lane > 0) *reinterpret_cast<f32x4 *>(q0 + 16 * lane) = v;
+                        for (int q = 0; q < cnq[c]; ++q, q0 += kQuadBytes) {
+                            const f32x4 v = *reinterpret_cast<const f32x4 *>(q0);
+                            if (lane > 0) *reinterpret_cast<f32x4 *>(q0 + 16 * lane) = v;
+                        }
                     }
                 }
         }
@@ -1192,25 +1223,27 @@ RootKernel root_kernel(int mode, int p1, bool tables) {
 typedef void (*GramKernel)(const GramDesc *);
 
 template <int NT, int NF>
-static GramKernel pick_gram(bool x4) {
-    return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true> : (GramKernel)gram_scan_kernel<NT, NF, false>;
+static GramKernel pick_gram(bool x4, bool pr) {
+    if (pr) return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, true> : (GramKernel)gram_scan_kernel<NT, NF, false, true>;
+    return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, false> : (GramKernel)gram_scan_kernel<NT, NF, false, false>;
 }
 
-// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2))
-GramKernel gram_kernel(int nt, int nf, bool x4) {
+// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2)); pr: pair-row record
+// buffers (every child record at most two quads, a row's quads contiguous) instead of quad-major ones
+GramKernel gram_kernel(int nt, int nf, bool x4, bool pr) {
     if (nf < 0 || nf > 2 || nf > nt) return nullptr;
     switch (nt * 4 + nf) {
-        case 4: return pick_gram<1, 0>(x4);
-        case 5: return pick_gram<1, 1>(x4);
-        case 8: return pick_gram<2, 0>(x4);
-        case 9: return pick_gram<2, 1>(x4);
-        case 10: return pick_gram<2, 2>(x4);
-        case 12: return pick_gram<3, 0>(x4);
-        case 13: return pick_gram<3, 1>(x4);
-        case 14: return pick_gram<3, 2>(x4);
-        case 16: return pick_gram<4, 0>(x4);
-        case 17: return pick_gram<4, 1>(x4);
-        case 18: return pick_gram<4, 2>(x4);
+        case 4: return pick_gram<1, 0>(x4, pr);
+        case 5: return pick_gram<1, 1>(x4, pr);
+        case 8: return pick_gram<2, 0>(x4, pr);
+        case 9: return pick_gram<2, 1>(x4, pr);
+        case 10: return pick_gram<2, 2>(x4, pr);
+        case 12: return pick_gram<3, 0>(x4, pr);
+        case 13: return pick_gram<3, 1>(x4, pr);
+        case 14: return pick_gram<3, 2>(x4, pr);
+        case 16: return pick_gram<4, 0>(x4, pr);
+        case 17: return pick_gram<4, 1>(x4, pr);
+        case 18: return pick_gram<4, 2>(x4, pr);
     }
     return nullptr;
 }

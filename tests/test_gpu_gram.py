@@ -4,7 +4,9 @@ record lanes, two fact tiles, four tiles, no fact features at all, a fact
 without a ragged tail, records of one to five quads (a key uniform over a
 tile is gathered once, others row by row), a key that changes on nearly
 every row, fact keys without a dimension row, and every tile candidate of the
-autotuner.
+autotuner.  Record buffers take both layouts: pair rows when every record has
+at most two quads (facts-only-tile, whole-tiles, distinct-keys, whose first
+dimension has one-quad records), quad-major otherwise.
 
 Counts are bit-exact.  Sums are checked twice:
   * against the oracle's exact sums within the split's own error bound,

@@ -785,18 +785,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 // rows to MFMA k-indices is valid as long as every operand uses the same one;
 // this one keeps the four lane groups on different LDS banks and lets every
 // fact chunk be one 16-byte load.)  Per tile t:
-//   1. wait until tile t's records and facts and tile t+1's keys have landed
-//      (only the facts of tile t+1 may still be in flight);
-//   2. split every slot value x = hi + lo in bf16 into operand registers:
-//      fact slots from registers, record and constant slots from LDS;
-//   3. gather tile t+1's child records into the wave's LDS record buffer with
-//      buffer loads that bypass registers (a key outside [0, n_keys) reads
-//      past the buffer range and lands as zeros: no join), request the keys of
-//      tile t+2, then the facts of tile t+2 into the register set tile t just
-//      freed.  Issued in that order, the in-order wait counter of step 1 never
-//      waits for facts it does not need yet.  (After the last tile these
-//      requests repeat the last tile and are never used.)
-//   4. accumulate hi*hi + hi*lo + lo*hi (+ lo*lo) for every upper-triangle
+//   1. wait until tile t's records and facts and tile t+1's keys have landed;
+//   2. spread records gathered once for a uniform key to every row; write tile
+//      t's facts (loaded as 256 contiguous bytes per column) from registers to
+//      the wave's LDS fact tile, and request tile t+1's facts into them;
+//   3. find the tile's valid rows and split every slot value x = hi + lo in
+//      bf16 into operand registers (from the fact tile, the record buffer and
+//      the constant block);
+//   4. gather tile t+1's child records into the record buffer with buffer
+//      loads that bypass registers (a key outside [0, n_keys) reads past the
+//      buffer range and lands as zeros: no join), then request the keys of
+//      tile t+2 (after the last tile these requests repeat it, unused);
+//   5. accumulate hi*hi + hi*lo + lo*hi (+ lo*lo) for every upper-triangle
 //      16x16 tile pair on MFMA while those copies are in flight.
 // Fact columns and keys are streamed once: their loads are non-temporal, so
 // they do not push the gathered view records out of the caches.  Each wave

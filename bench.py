@@ -166,7 +166,7 @@ def main():
 
         def verified():
             heuristic()
-            return full.ctx.choose_learned_verified(WEIGHTS, stream, 4, 3)
+            return full.ctx.choose_learned_verified(WEIGHTS, stream, 4, 10)
 
         def autotune():
             return full.ctx.autotune(stream, args.timing_db, 3)

@@ -273,8 +273,10 @@ lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip
  * and the `top_k` best-ranked candidates on `hip_stream` as lmfao_autotune
  * does (`reps` timed runs each), select the fastest, execute it once and
  * store its candidate index in *best (-1 when the configuration in place
- * stays).  The model prunes the search; the timing decides, so the result is
- * never slower than the configuration in place beyond timing noise.  Same
+ * stays).  A candidate replaces the configuration in place only when it is
+ * more than 2% faster (the run-to-run spread of such timings).  The model
+ * prunes the search; the timing decides, so the result is never slower than
+ * the configuration in place beyond timing noise.  Same
  * fallback as lmfao_choose_learned (configuration kept, *best = -1, LMFAO_OK)
  * when the model is missing or predicts a non-finite time; INVALID_ARG for
  * top_k or reps below 1; STATE before lmfao_bind. */

@@ -2114,6 +2114,8 @@ extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, 
     return LMFAO_OK;
 }
 
+constexpr double kSwitchMargin = 0.02;
+
 extern "C" lmfao_status lmfao_choose_learned_verified(lmfao_ctx *c, const char *weights, void *hip_stream,
                                                       int32_t top_k, int32_t reps, int32_t *best) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
@@ -2148,7 +2150,9 @@ extern "C" lmfao_status lmfao_choose_learned_verified(lmfao_ctx *c, const char *
         if (ms < best_ms) { best_ms = ms; best_i = i; }
     }
     if (best_i < 0 && current_ms >= 1e300) return fail(c, LMFAO_ERR_HIP, "no ranked candidate ran");
-    const bool keep = current_ms <= best_ms;
+    // a ranked candidate replaces the configuration in place only when it is faster by more than
+    // the run-to-run spread of these timings (about 2%), so the choice does not follow noise
+    const bool keep = best_i < 0 || best_ms >= current_ms * (1.0 - kSwitchMargin);
     s = select_cfg(c, keep ? current : cands[best_i]);
     if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);
     if (s == LMFAO_OK) s = lmfao_sync(c);

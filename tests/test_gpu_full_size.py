@@ -33,7 +33,7 @@ def _bench_engine(db, qs, cols, precision):
     eng = Engine(db, qs, precision=precision, schedule="batched", columns=cols)
     eng.run(stream)
     if os.path.exists(costmodel.WEIGHTS):
-        eng.ctx.choose_learned_verified(costmodel.WEIGHTS, stream, 4, 3)
+        eng.ctx.choose_learned_verified(costmodel.WEIGHTS, stream, 4, 10)
     else:
         eng.ctx.autotune(stream, None, 2)
     eng._bind()

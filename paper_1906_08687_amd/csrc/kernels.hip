@@ -93,26 +93,28 @@ __device__ __forceinline__ bool compare(T x, int op, T t) {
     }
 }
 
-__device__ __forceinline__ bool pred_holds(const PredSrc &p, int64_t row) {
-    if (p.is_float) return compare(static_cast<const float *>(p.col)[row], p.op, p.fval);
-    return compare(static_cast<const int32_t *>(p.col)[row], p.op, p.ival);
+template <class PS>   // PredSrc in any address space
+__device__ __forceinline__ bool pred_holds(const PS &p, int64_t row) {
+    if (p.is_float) return compare(gld(static_cast<const float *>(p.col))[row], p.op, p.fval);
+    return compare(gld(static_cast<const int32_t *>(p.col))[row], p.op, p.ival);
 }
 
 // categorical code (checked against its domain) or bucket #{k : thr[k] < x}
-__device__ __forceinline__ int32_t comp_value(const CompSrc &c, int64_t row, uint32_t *err) {
+template <class CS>   // CompSrc in any address space
+__device__ __forceinline__ int32_t comp_value(const CS &c, int64_t row, uint32_t *err) {
     if (c.nthr == 0) {
-        int32_t v = static_cast<const int32_t *>(c.col)[row];
+        int32_t v = gld(static_cast<const int32_t *>(c.col))[row];
         if (v < 0 || v >= c.dom) {
-            atomicOr(err, kErrDomain);
+            gor(err, kErrDomain);
             v = 0;
         }
         return v;
     }
-    const float x = static_cast<const float *>(c.col)[row];
+    const float x = gld(static_cast<const float *>(c.col))[row];
     int lo = 0, hi = c.nthr;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (c.thr[mid] < x) lo = mid + 1;
+        if (gld(c.thr)[mid] < x) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -122,44 +124,78 @@ __device__ __forceinline__ int32_t comp_value(const CompSrc &c, int64_t row, uin
 // view records of non-root relations (one thread per row; grid.y = relation)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__restrict__ descs) {
-    const ScanDesc &d = descs[blockIdx.y];
-    const int64_t row = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (row >= d.n_rows) return;
-    const int32_t key = d.key[row];
-    if (key < 0 || key >= d.n_keys) {
-        atomicOr(d.err, kErrKeyRange);
-        return;
-    }
-    // the join key of a child must be unique: the count of rows with this key is checked after the
-    // record is written, so the atomic's round trip overlaps the writes (with a duplicate the
-    // records are unspecified and the error stops the evaluation at sync)
-    const uint32_t seen_before = atomicAdd(&d.seen[key], 1u);
-    uint32_t *rec = d.rec_out + (int64_t)key * d.rec_stride;
+// One row's record: every word goes through put(w, v).  Records of at most 8 words (REG) are
+// assembled in registers and written as one or two 16-byte stores (records are 16-byte aligned;
+// words no field fills are written as zeros); wider ones are written word by word.
+template <bool REG>
+__device__ __forceinline__ void build_record(const AS_CONST ScanDesc &d, int64_t row, uint32_t *rec) {
+    uint32_t r[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    auto put = [&](int w, uint32_t v) {
+        if (REG) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r[k] = w == k ? v : r[k];
+        } else {
+            gst(rec)[w] = v;
+        }
+    };
     uint32_t valid = 1u;
     uint64_t mask = d.filter_all;
     for (int c = 0; c < d.n_child; ++c) {
-        const ChildSrc &ch = d.children[c];
-        const int32_t k = ch.fk[row];
+        const AS_CONST ChildSrc &ch = cst(d.children)[c];
+        const int32_t k = gld(ch.fk)[row];
         if (k < 0 || k >= ch.n_keys) { valid = 0u; continue; }
-        const uint32_t *cr = ch.rec + (int64_t)k * ch.stride;
+        const AS_GLOBAL uint32_t *cr = gld(ch.rec + (int64_t)k * ch.stride);
         if (cr[0] == 0u) { valid = 0u; continue; }
         if (ch.n_mask > 0) {
             uint64_t m = cr[1];
             if (ch.n_mask > 1) m |= (uint64_t)cr[2] << 32;
             mask &= m;
         }
-        for (int i = 0; i < ch.n_comp; ++i) rec[d.rec_comp_off + ch.comp_dst + i] = cr[ch.comp_off + i];
-        for (int i = 0; i < ch.n_feat; ++i) rec[d.rec_feat_off + ch.feat_dst + i] = cr[ch.feat_off + i];
+        for (int i = 0; i < ch.n_comp; ++i) put(d.rec_comp_off + ch.comp_dst + i, cr[ch.comp_off + i]);
+        for (int i = 0; i < ch.n_feat; ++i) put(d.rec_feat_off + ch.feat_dst + i, cr[ch.feat_off + i]);
     }
-    for (int f = 0; f < d.n_feat; ++f) rec[d.rec_feat_off + d.feats[f].dst] = __float_as_uint(d.feats[f].col[row]);
-    for (int c = 0; c < d.n_comp; ++c) rec[d.rec_comp_off + d.comps[c].dst] = (uint32_t)comp_value(d.comps[c], row, d.err);
-    for (int p = 0; p < d.n_pred; ++p)
-        if (!pred_holds(d.preds[p], row)) mask &= ~(1ull << d.preds[p].filter);
-    if (d.n_mask > 0) rec[1] = (uint32_t)mask;
-    if (d.n_mask > 1) rec[2] = (uint32_t)(mask >> 32);
-    rec[0] = valid;
-    if (seen_before != 0u) atomicOr(d.err, kErrDupKey);
+    for (int f = 0; f < d.n_feat; ++f) {
+        const AS_CONST FeatSrc &fs = cst(d.feats)[f];
+        put(d.rec_feat_off + fs.dst, __float_as_uint(gld(fs.col)[row]));
+    }
+    for (int c = 0; c < d.n_comp; ++c) {
+        const AS_CONST CompSrc &cs = cst(d.comps)[c];
+        put(d.rec_comp_off + cs.dst, (uint32_t)comp_value(cs, row, d.err));
+    }
+    for (int p = 0; p < d.n_pred; ++p) {
+        const AS_CONST PredSrc &ps = cst(d.preds)[p];
+        if (!pred_holds(ps, row)) mask &= ~(1ull << ps.filter);
+    }
+    if (d.n_mask > 0) put(1, (uint32_t)mask);
+    if (d.n_mask > 1) put(2, (uint32_t)(mask >> 32));
+    put(0, valid);
+    if (REG) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        AS_GLOBAL u32x4 *o = gst(reinterpret_cast<u32x4 *>(rec));
+        o[0] = u32x4{r[0], r[1], r[2], r[3]};
+        if (d.rec_stride > 4) o[1] = u32x4{r[4], r[5], r[6], r[7]};
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__restrict__ descs) {
+    const AS_CONST ScanDesc &d = cst(descs)[blockIdx.y];
+    const int64_t row = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (row >= d.n_rows) return;
+    const int32_t key = gld(d.key)[row];
+    if (key < 0 || key >= d.n_keys) {
+        gor(d.err, kErrKeyRange);
+        return;
+    }
+    // the join key of a child must be unique: the count of rows with this key is checked after the
+    // record is written, so the atomic's round trip overlaps the writes (with a duplicate the
+    // records are unspecified and the error stops the evaluation at sync)
+    const uint32_t seen_before = __hip_atomic_fetch_add(gst(d.seen + key), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t *rec = d.rec_out + (int64_t)key * d.rec_stride;
+    if (d.rec_stride <= 8)
+        build_record<true>(d, row, rec);
+    else
+        build_record<false>(d, row, rec);
+    if (seen_before != 0u) gor(d.err, kErrDupKey);
 }
 
 // ---------------------------------------------------------------------------

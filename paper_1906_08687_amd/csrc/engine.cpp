@@ -1035,12 +1035,14 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             L.waves = P.waves;
         }
         L.parts = parts;
-        // grid: enough workgroups to cover the chip twice at its residency
+        // grid: the general scan covers the chip twice at its residency (its workgroups' costs
+        // differ with the tables they update); the dedicated scan gives every workgroup the same
+        // rows, so one round of resident workgroups, with no second-round tail, is enough
         const int tile = 64 * L.waves;
         const int64_t blocks_needed = std::max<int64_t>(1, ceil_div(root.n_rows, tile));
         const int occ = (int)std::max<size_t>(1, std::min<size_t>(occ_waves / L.waves, (160 * 1024) / std::max<size_t>(L.lds_bytes + 1024, 1)));
         L.resident = occ;
-        int gx = cfg.grid_x > 0 ? cfg.grid_x : 2 * c->n_cu * occ;
+        int gx = cfg.grid_x > 0 ? cfg.grid_x : (L.gram ? 1 : 2) * c->n_cu * occ;
         gx = (int)std::min<int64_t>(gx, blocks_needed);
         gx = std::max(1, std::min(gx, L.gram ? kPartMax / L.waves : kGridMax));
         const int64_t rpb = round_up((int)std::min<int64_t>(ceil_div(root.n_rows, gx), 1 << 30), tile);

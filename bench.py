@@ -5,10 +5,15 @@ fills, dimension views, the fused root scan, fp64 merge, result assembly)
 with all inputs resident in HBM.  Reported value = join tuples aggregated
 per second (|J| = 100M tuples per step) of the full form (BF16 hi+lo split
 covariance on MFMA, batched schedule in a hipGraph, tile configuration
-chosen by the learned cost model, else by the exhaustive autotuner), next to
-the plain form (fp32 FMAs, one launch per view, heuristic tiles) and the
-speedup between them.  Both forms are checked against the CPU oracle on a
-sample of aggregates evaluated over the full join.
+ranked by the learned cost model and judged by timing, else chosen by the
+exhaustive autotuner), next to the plain form (fp32 FMAs, one launch per
+view, heuristic tiles) and the speedup between them.  Both forms are checked
+against the CPU oracle on a sample of aggregates evaluated over the full join.
+
+`--batch cube` and `--batch ctree` time the other batch shapes the same way
+(a three-dimensional data cube with five measures over workload 2's schema at
+10M fact rows; a 32-node classification-tree level over workload 3's schema
+at 50M fact rows); the default is the covariance batch.
 """
 from __future__ import annotations
 
@@ -36,6 +41,27 @@ def algorithmic_bytes(db) -> int:
         nfeat = sum(1 for c in r.columns if c.kind == "cont")
         stride = ((1 + nfeat) + 3) // 4 * 4
         b += r.n_rows * stride * 4
+    return int(b)
+
+
+def referenced_bytes(db, queries) -> int:
+    """Bytes a root scan of this batch must move: every fact column a query
+    names and every foreign key of the fact once, plus every dimension view
+    record once (count and the attributes the batch names below it, in whole
+    16-byte quads)."""
+    names = set()
+    for q in queries:
+        names.update(g.attr for g in q.groupby)
+        names.update(p.attr for p in q.where)
+        for a in q.aggs:
+            for _, attrs in a.terms:
+                names.update(attrs)
+    fact = db.relations[0]
+    keys = {c.attr for r in db.relations[1:] for c in r.columns if c.kind == "key"}
+    b = sum(c.data.nbytes for c in fact.columns if c.attr in names or c.attr in keys)
+    for r in db.relations[1:]:
+        words = 1 + sum(1 for c in r.columns if c.attr in names)
+        b += r.n_rows * ((words + 3) // 4 * 4) * 4
     return int(b)
 
 
@@ -73,7 +99,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n-fact", type=int, default=100_000_000)
+    ap.add_argument("--batch", default="covariance", choices=["covariance", "cube", "ctree"],
+                    help="covariance: the 861-aggregate covariance batch (the benchmark); cube: data cube; "
+                         "ctree: classification-tree level")
+    ap.add_argument("--n-fact", type=int, default=None, help="fact rows (default: the batch's full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"],
@@ -97,13 +126,38 @@ def main():
 
     import torch
     from datagen import make_batch, make_database
+    from datagen.configs import classification_tree_batch, data_cube_batch, tree_level
     from paper_1906_08687_amd.lmfao import Engine, upload_columns
 
     t = time.time()
-    db = make_database(4, "full", n_fact=args.n_fact)
-    qs = make_batch(4, db)
-    print("[bench] generated workload 4: %d fact rows, %d queries in %.1fs" % (db.relations[0].n_rows, len(qs),
-                                                                               time.time() - t), file=sys.stderr, flush=True)
+    over = {"n_fact": args.n_fact} if args.n_fact else {}
+    if args.batch == "covariance":
+        db = make_database(4, "full", **over)
+        qs = make_batch(4, db)
+        precision = args.precision
+        metric = "join tuples aggregated/sec (covariance batch, 100M fact) + speedup vs plain FP32"
+        workload = ("covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with 4 dims "
+                    "(1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates")
+        cpu_rows = 25_000_000
+    elif args.batch == "cube":
+        db = make_database(2, "full", **over)
+        qs = data_cube_batch(["c0", "c1", "c4"], ["f1", "f2", "d1_1", "d2_1", "d4_1"])
+        precision = "fp32"
+        metric = "join tuples aggregated/sec (data cube, 10M fact) + speedup vs plain"
+        workload = ("data cube: 3 dimensions (c0 of the fact, c1 and c4 of two dimensions; 60/65/112 values "
+                    "at this seed) x 5 measures, 8 group-bys, over workload 2's snowflake at 10M fact rows")
+        cpu_rows = 10_000_000
+    else:
+        db = make_database(3, "full", **over)
+        qs = classification_tree_batch(db, "g3", tree_level(db, seed=3))
+        precision = "fp32"
+        metric = "join tuples aggregated/sec (classification-tree level, 50M fact) + speedup vs plain"
+        workload = ("classification-tree level: 32 nodes x 29 split attributes (20 bucketed continuous, 9 "
+                    "categorical), COUNT GROUP BY (label g3, bucket) and GROUP BY bucket, over workload 3's star "
+                    "at 50M fact rows")
+        cpu_rows = 2_000_000
+    print("[bench] generated %s batch: %d fact rows, %d queries in %.1fs" % (args.batch, db.relations[0].n_rows, len(qs),
+                                                                             time.time() - t), file=sys.stderr, flush=True)
     dev = torch.device("cuda", 0)
     cols = upload_columns(db, dev)
     torch.cuda.synchronize()
@@ -135,7 +189,9 @@ def main():
     t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
     if args.forms == "both":
         plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols)
-        t_plain = time_steps(plain, stream, args.steps, args.warmup)
+        # the classification-tree level's plain form rescans the fact once per view (about 1,860 scans)
+        ps, pw = (args.steps, args.warmup) if args.batch != "ctree" else (2, 1)
+        t_plain = time_steps(plain, stream, ps, pw)
         res_plain = plain.results()
         plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)
         plain_stats = plain.stats()
@@ -145,7 +201,7 @@ def main():
     # full form: bf16x3 on MFMA, batched in a hipGraph; tiles chosen by the cost model, its top
     # candidates judged by timing (every way of choosing is timed and reported; the one the
     # --plan option names runs last, so it is the plan the timed steps use)
-    full = Engine(db, qs, precision=args.precision, schedule="batched", columns=cols)
+    full = Engine(db, qs, precision=precision, schedule="batched", columns=cols)
     full.ctx.execute(stream)
     full.ctx.sync()
     plans = {}
@@ -174,7 +230,10 @@ def main():
         ways = [("heuristic", heuristic)]
         if have_model:
             ways += [("learned", learned), ("learned_top4_timed", verified)]
-        ways.append(("autotune", autotune))
+        # the exhaustive autotuner is timed for reference when the plan has few candidates (the
+        # dedicated scan has 15; a general scan of a large batch can have hundreds of slow ones)
+        if args.plan == "autotune" or not have_model or len(full.ctx.candidates()) <= 32:
+            ways.append(("autotune", autotune))
         chosen = {"auto": "learned_top4_timed" if have_model else "autotune",
                   "learned": "learned" if have_model else "heuristic",
                   "autotune": "autotune", "heuristic": "heuristic"}[args.plan]
@@ -185,6 +244,8 @@ def main():
             full.ctx.execute(stream)
             full.ctx.sync()
             plans[name] = {"candidate": idx, "root_scan_ms": full.ctx.time_root_group(stream, 2, 10)}
+            print("[bench] tile choice %s: candidate %d, root scan %.3f ms" % (name, idx, plans[name]["root_scan_ms"]),
+                  file=sys.stderr, flush=True)
         best = plans[chosen]["candidate"]
         print("[bench] tile choices: %s" % json.dumps(plans), file=sys.stderr, flush=True)
     full._bind()
@@ -192,7 +253,7 @@ def main():
     res_full = full.results()
     root_ms = full.ctx.time_root_group(stream, 2, 10)
     stats = full.stats()
-    print("[bench] full %s/batched/%s: %.3f ms/step, root scan %.3f ms" % (args.precision, chosen, t_full * 1e3, root_ms),
+    print("[bench] full %s/batched/%s: %.3f ms/step, root scan %.3f ms" % (precision, chosen, t_full * 1e3, root_ms),
           file=sys.stderr, flush=True)
 
     # accuracy of both forms against the oracle on sampled aggregates over the full join
@@ -200,7 +261,7 @@ def main():
     if not args.no_check:
         import oracle
         rng = np.random.default_rng(4)
-        sample = sorted(set([0] + list(rng.choice(np.arange(1, len(qs)), 15, replace=False))))
+        sample = sorted(set([0] + list(rng.choice(np.arange(1, len(qs)), min(15, len(qs) - 1), replace=False))))
         t = time.time()
         ref = oracle.evaluate(db, [qs[i] for i in sample])
         errors = {}
@@ -221,20 +282,20 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        rows = min(n_join, 25_000_000)      # about 10 s of the oracle on 16 host threads
+        rows = min(n_join, cpu_rows)        # about 10 s of the oracle on 16 host threads
         threads = os.cpu_count() or 1
         t = time.time()
         oracle.evaluate(db, qs, n_threads=threads, root_range=(0, rows))
         dt = time.time() - t
         cpu = {"value": rows / dt, "unit": "join tuples/s", "cores": threads, "kind": "oracle",
-               "sample": "first %d fact rows (of %d) joined with all four dimensions, all %d aggregates" %
+               "sample": "first %d fact rows (of %d) joined with every dimension, all %d queries" %
                          (rows, n_join, len(qs))}
         print("[bench] cpu oracle: %.3g tuples/s on %d threads" % (cpu["value"], threads), file=sys.stderr, flush=True)
 
-    alg = algorithmic_bytes(db)
+    alg = algorithmic_bytes(db) if args.batch == "covariance" else referenced_bytes(db, qs)
     achieved = alg / (root_ms * 1e-3) / 1e9
     line = {
-        "metric": "join tuples aggregated/sec (covariance batch, 100M fact) + speedup vs plain FP32",
+        "metric": metric,
         "value": n_join / t_full,
         "unit": "join tuples/s",
         "n_gpus": 1,
@@ -244,10 +305,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "%s-split/f32-acc/f64-merge" % args.precision,
-        "data": "synthetic (seeded; workload 4 recipe)",
-        "config": {"workload": "covariance batch: 100M-row fact (16 fp32 attrs, 4 Zipf(1.2) keys) joined with "
-                               "4 dims (1M/100k/10k/1k rows, 6 fp32 attrs each), values N(100,1); 861 aggregates",
+        "dtype": ("%s-split/f32-acc/f64-merge" % precision) if precision != "fp32" else "f32/u64-counts/f64-merge",
+        "data": "synthetic (seeded; %s recipe)" % {"covariance": "workload 4", "cube": "workload 2",
+                                                    "ctree": "workload 3"}[args.batch],
+        "config": {"workload": workload,
                    "fact_rows": n_join, "aggregates": len(qs), "plan": chosen, "candidate": best,
                    "plan_choices": plans,
                    "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
@@ -260,7 +321,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("kernels.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,
-                     "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % args.precision,
+                     "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % precision,
                      "algorithmic_bytes": alg, "kernel_ms": root_ms},
         "cpu_baseline": cpu,
     }

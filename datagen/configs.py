@@ -315,6 +315,40 @@ def batch3(db: Database, level: Optional[TreeLevel] = None) -> List[Query]:
     return qs
 
 
+def classification_tree_batch(db: Database, label: str, level: Optional[TreeLevel] = None) -> List[Query]:
+    """Classification-tree level (Section 2, equations (9) and (10)): for every
+    node (its conjunction of conditions as WHERE) and every split attribute X
+    other than the label, COUNT GROUP BY (label, bucket(X)) and COUNT GROUP BY
+    bucket(X).  The label's class frequencies per split condition follow from
+    the pair, as the Gini index or entropy need."""
+    level = level or tree_level(db)
+    qs = []
+    for preds in level.nodes:
+        for a in level.features:
+            if a == label:
+                continue
+            gb = GroupBy(a, level.thresholds.get(a))
+            qs.append(Query(groupby=[GroupBy(label), gb], where=list(preds)))
+            qs.append(Query(groupby=[gb], where=list(preds)))
+    return qs
+
+
+# ---------------------------------------------------------------------------
+# data cube (Section 2, equation (6)) over workload 2's schema
+# ---------------------------------------------------------------------------
+
+def data_cube_batch(dims: Sequence[str], measures: Sequence[str]) -> List[Query]:
+    """A k-dimensional data cube: one query per subset of the k dimensions
+    (2^k group-bys, from the empty one to all k), each summing every measure
+    (the paper's experiments use three dimensions and five measures)."""
+    qs = []
+    k = len(dims)
+    for mask in range(1 << k):
+        gb = [GroupBy(dims[i]) for i in range(k) if (mask >> i) & 1]
+        qs.append(Query(groupby=gb, aggs=[Agg.monomial(m) for m in measures]))
+    return qs
+
+
 # ---------------------------------------------------------------------------
 # workload 4: covariance batch (the headline measurement)
 # ---------------------------------------------------------------------------

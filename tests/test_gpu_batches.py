@@ -1,0 +1,44 @@
+"""Parity with the oracle on the batch shapes beyond the five workloads: a
+three-dimensional data cube with five measures over workload 2's schema
+(Section 2, equation (6): one group-by per subset of the dimensions), and a
+classification-tree level over workload 3's schema (equations (9) and (10):
+per node and split attribute, COUNT GROUP BY (label, bucket) and COUNT GROUP
+BY bucket).  Both run on the general root scan (grouped tables; no
+covariance block), in the batched and the plain schedule.
+
+Counts are bit-exact; sums follow tests/helpers.check_sums at 1e-6.
+"""
+import pytest
+
+import oracle
+from datagen import make_database
+from datagen.configs import classification_tree_batch, data_cube_batch, tree_level
+from tests.test_batches import CUBE_DIMS, CUBE_MEASURES
+from tests.test_gpu_parity import compare
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def _batch(name):
+    if name not in _cache:
+        if name == "cube":
+            db = make_database(2, n_fact=100_003)
+            qs = data_cube_batch(CUBE_DIMS, CUBE_MEASURES)
+        else:
+            db = make_database(3, n_fact=30_011)
+            qs = classification_tree_batch(db, "g3", tree_level(db, n_nodes=8, seed=3))
+        _cache[name] = (db, qs, oracle.evaluate(db, qs))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("schedule", ["batched", "plain"])
+@pytest.mark.parametrize("name", ["cube", "classification_tree"])
+def test_batch_parity(name, schedule):
+    from paper_1906_08687_amd.lmfao import Engine
+    db, qs, ref = _batch(name)
+    print("case: %s %s, %d fact rows, %d queries" % (name, schedule, db.relations[0].n_rows, len(qs)), flush=True)
+    eng = Engine(db, qs, precision="fp32", schedule=schedule)
+    eng.run()
+    compare(eng.results(), ref, qs, 1e-6, "%s %s" % (name, schedule))

@@ -185,10 +185,10 @@ def main():
               file=sys.stderr, flush=True)
         del x
 
-    # plain form: fp32 covariance, one launch per view, heuristic tiles
+    # plain form: fp32 covariance, one launch per view, heuristic tiles, every table scanned
     t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
     if args.forms == "both":
-        plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols)
+        plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols, rollup=False)
         # the classification-tree level's plain form rescans the fact once per view (about 1,860 scans)
         ps, pw = (args.steps, args.warmup) if args.batch != "ctree" else (2, 1)
         t_plain = time_steps(plain, stream, ps, pw)
@@ -313,7 +313,8 @@ def main():
                    "plan_choices": plans,
                    "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
                    "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
-                   "lds_bytes": stats["lds_bytes"]},
+                   "lds_bytes": stats["lds_bytes"], "grouped_tables": stats["tables"],
+                   "derived_tables": stats["derived_tables"], "launches": stats["launches"]},
         "speedup_vs_plain_fp32": (t_plain / t_full) if t_plain else None,
         "plain_fp32": ({"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
                         "launches": plain_stats["launches"]} if t_plain else None),

@@ -169,6 +169,13 @@ typedef struct {
     int32_t gram_block;    /* override: FP32 register block edge 2/4/6/8 (0 = planner's choice);
                               other values are INVALID_ARG */
     const char *cost_model;/* LEARNED: path of the weights file written by lmfao_train_cost_model */
+    int32_t scan_every_table; /* 0: a grouped table whose key is another table's key (same WHERE
+                              filter) with one component left out is not updated by the fact
+                              scan but summed from that table's cells afterwards (its sums are
+                              added to the finer table's); chains of such tables are summed
+                              longest key first.  1: the fact scan updates every table.  Other
+                              values are INVALID_ARG.  Results agree up to the order of fp64
+                              additions; counts are identical. */
 } lmfao_plan_opts;
 
 /* Build the evaluation plan for all queries added so far. */
@@ -194,6 +201,7 @@ typedef struct {
     int32_t nbuf;                /* staging buffers per wave (2: next tile copied during this one) */
     int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */
     int32_t dedicated_scan;      /* 1: the covariance-only root scan runs on the dedicated BF16 kernel */
+    int32_t derived_tables;      /* grouped tables summed from a finer table after the scan */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);

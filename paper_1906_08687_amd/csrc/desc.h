@@ -257,6 +257,32 @@ struct MergeDesc {
     unsigned long long *count;         // total joined tuples
 };
 
+// Marginal derivation: a grouped table T whose key is the key of a table U
+// (same filter) with one component d left out is the sum of U over d.  Cells
+// are row-major in key order, so with S = cells of the components after d,
+// cell t of T is the sum over v < dom(d) of U's cell
+// (t / S) * dom(d) * S + v * S + t % S.
+struct RollupItem {
+    int64_t t_cnt, t_val;     // first global count / sum of T
+    int64_t u_cnt, u_val;     // first global count / sum of U
+    int64_t t_cells;
+    int32_t t_nvals;          // sums per cell of T
+    int32_t u_nvals;          // sums per cell of U
+    int32_t dom;              // domain of the dropped component
+    int32_t suffix;           // S
+    int32_t map_base;         // into map: U's value index of each of T's values
+    int32_t pad;
+};
+
+struct RollupDesc {           // one pass: tables of equal key length, sources already final
+    int32_t n_items;
+    int32_t pad;
+    const RollupItem *items;
+    const int32_t *map;
+    unsigned long long *g_cnt;
+    double *g_val;
+};
+
 enum SrcKind : int32_t { SRC_GRAM = 0, SRC_TABLE = 1 };
 
 struct OutDesc {          // one query's result

@@ -58,7 +58,8 @@ GramKernel gram_kernel(int nt, int nf, bool x4, bool pr);
 hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st);
 hipError_t set_gram_lds_limit(GramKernel k, size_t bytes);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
-hipError_t launch_assemble(const AssembleDesc *desc, int n_out, hipStream_t st);
+hipError_t launch_assemble(const AssembleDesc *desc, int n_out, int64_t max_cells, hipStream_t st);
+hipError_t launch_rollup(const RollupDesc *desc, int n_items, int64_t max_work, hipStream_t st);
 // cost-model network (mlp.hip)
 hipError_t mlp_forward_dev(int hidden, const float *params, const float *x, int n, float *y, hipStream_t st);
 }  // namespace lmfao
@@ -143,6 +144,9 @@ struct Table {
     int part = 0;
     int lds_cnt = -1, lds_val = -1;
     int64_t glb_cnt = 0, glb_val = 0;
+    // marginal derivation: summed after the scan from table `from` over its component `drop`
+    int from = -1, drop = -1;
+    std::vector<int> vmap;              // per value: index in the source table's values
     // uint32 counts, then fp64 sums at an even word offset
     int words() const { return (int)(round_up((int)n_cells, 2) + 2 * n_cells * (int64_t)vals.size()); }
     int val_off() const { return round_up((int)n_cells, 2); }
@@ -225,6 +229,8 @@ struct Plan {
     std::vector<Family> fams;
     std::vector<Output> outs;
     int64_t table_cells = 0, table_vals = 0;
+    std::vector<std::vector<int>> rollup_passes;   // derived tables per pass, in execution order
+    int n_derived = 0;
     // schedule
     int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
     TileCfg cfg;                      // chosen tile configuration
@@ -268,6 +274,9 @@ struct lmfao_ctx {
     std::vector<std::vector<int>> level_rels;     // relations per level (non-root)
     std::vector<size_t> view_desc_off;            // per relation: ScanDesc offset in blob
     size_t merge_off = 0, assemble_off = 0;
+    std::vector<size_t> rollup_off;               // per pass: RollupDesc offset in blob
+    std::vector<int64_t> rollup_cells;            // per pass: most (cell, sum or count) pairs of a table
+    int64_t assemble_cells = 0;                   // most cells of a query result
     // execution
     hipStream_t last_stream = nullptr;
     bool executed = false;
@@ -732,7 +741,57 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         }
     }
     P.n_gram = gram_used ? P.n_feat : 0;
+    // ---- marginal derivation: a table whose key is another same-filter table's key with one
+    // component left out is summed from that table after the scan instead of being updated
+    // per fact row (its sums join the source's).  Shortest keys first, so a source's values
+    // are complete before its own source is chosen; the source with the smallest dropped
+    // domain wins.
+    if (!c->opts.scan_every_table) {
+        std::vector<int> order(P.tables.size());
+        for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return P.tables[a].comps.size() < P.tables[b].comps.size(); });
+        for (int t : order) {
+            int best = -1, best_pos = -1, best_dom = 0;
+            for (size_t u = 0; u < P.tables.size(); ++u) {
+                const Table &U = P.tables[u];
+                const Table &T = P.tables[t];
+                if (U.filter != T.filter || U.comps.size() != T.comps.size() + 1) continue;
+                for (size_t d = 0; d < U.comps.size(); ++d) {
+                    bool same = true;
+                    for (size_t i = 0, j = 0; i < U.comps.size() && same; ++i) {
+                        if (i == d) continue;
+                        same = U.comps[i] == T.comps[j++];
+                    }
+                    const int dom = P.comps[U.comps[d]].dom;
+                    if (same && (best < 0 || dom < best_dom)) { best = (int)u; best_pos = (int)d; best_dom = dom; }
+                }
+            }
+            if (best < 0) continue;
+            Table &T = P.tables[t];
+            T.from = best;
+            T.drop = best_pos;
+            auto &uv = P.tables[best].vals;
+            for (auto &v : T.vals)
+                if (std::find(uv.begin(), uv.end(), v) == uv.end()) uv.push_back(v);
+            ++P.n_derived;
+        }
+        // passes: longest derived keys first (their sources are scanned or derived earlier)
+        std::map<int, std::vector<int>, std::greater<int>> by_len;
+        for (size_t t = 0; t < P.tables.size(); ++t)
+            if (P.tables[t].from >= 0) by_len[(int)P.tables[t].comps.size()].push_back((int)t);
+        for (auto &kv : by_len) P.rollup_passes.push_back(kv.second);
+    }
     for (auto &T : P.tables) std::sort(T.vals.begin(), T.vals.end());
+    for (auto &T : P.tables) {
+        if (T.from < 0) continue;
+        const auto &uv = P.tables[T.from].vals;
+        for (auto &v : T.vals) {
+            const auto it = std::find(uv.begin(), uv.end(), v);
+            if (it == uv.end()) return fail(c, LMFAO_ERR_STATE, "internal: derived table value missing from its source");
+            T.vmap.push_back((int)(it - uv.begin()));
+        }
+    }
     for (auto &O : P.outs)
         for (auto &t : O.terms) {
             if (t.src < 0) continue;
@@ -745,7 +804,8 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         }
     // ---- families: tables with equal value lists and equal key lists across filters ----
     std::map<std::pair<std::vector<std::pair<int, int>>, int>, std::vector<int>> by_vf;
-    for (size_t t = 0; t < P.tables.size(); ++t) by_vf[{P.tables[t].vals, P.tables[t].filter}].push_back((int)t);
+    for (size_t t = 0; t < P.tables.size(); ++t)
+        if (P.tables[t].from < 0) by_vf[{P.tables[t].vals, P.tables[t].filter}].push_back((int)t);
     std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, std::vector<int>> fam_of;
     std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, bool> fam_unf;
     for (auto &kv : by_vf) {
@@ -880,7 +940,7 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
         int used = 0;
         for (int t : idx) {
             const int w = P.tables[t].words();
-            if (used + w > budget_words) continue;
+            if (P.tables[t].from >= 0 || used + w > budget_words) continue;
             P.tables[t].lds_cnt = used;
             P.tables[t].lds_val = used + P.tables[t].val_off();
             used += w;
@@ -1554,6 +1614,44 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     ad.res_cnt = reinterpret_cast<unsigned long long *>(c->res);
     ad.res_sum = reinterpret_cast<double *>(c->res);
     c->assemble_off = B.put(&ad, sizeof ad);
+    c->assemble_cells = 0;
+    for (auto &O : P.outs) c->assemble_cells = std::max(c->assemble_cells, O.n_cells);
+    // ---- marginal derivation passes ------------------------------------------------------------
+    c->rollup_off.clear();
+    c->rollup_cells.clear();
+    for (auto &pass : P.rollup_passes) {
+        std::vector<RollupItem> items;
+        std::vector<int32_t> map;
+        int64_t mx = 0;
+        for (int t : pass) {
+            const Table &T = P.tables[t];
+            const Table &U = P.tables[T.from];
+            RollupItem it{};
+            it.t_cnt = T.glb_cnt;
+            it.t_val = T.glb_val;
+            it.u_cnt = U.glb_cnt;
+            it.u_val = U.glb_val;
+            it.t_cells = T.n_cells;
+            it.t_nvals = (int)T.vals.size();
+            it.u_nvals = (int)U.vals.size();
+            it.dom = P.comps[U.comps[T.drop]].dom;
+            int64_t suffix = 1;
+            for (size_t i = T.drop + 1; i < U.comps.size(); ++i) suffix *= P.comps[U.comps[i]].dom;
+            it.suffix = (int32_t)suffix;     // <= T.n_cells < 2^31
+            it.map_base = (int)map.size();
+            map.insert(map.end(), T.vmap.begin(), T.vmap.end());
+            items.push_back(it);
+            mx = std::max(mx, T.n_cells * (int64_t)(T.vals.size() + 1));
+        }
+        RollupDesc rd{};
+        rd.n_items = (int)items.size();
+        rd.items = reinterpret_cast<const RollupItem *>(dev(B.vec(items)));
+        rd.map = reinterpret_cast<const int32_t *>(dev(B.vec(map)));
+        rd.g_cnt = gcnt;
+        rd.g_val = gval;
+        c->rollup_off.push_back(B.put(&rd, sizeof rd));
+        c->rollup_cells.push_back(mx);
+    }
     // ---- fills: error word, records, seen counters, global tables -----------------------------
     std::vector<FillDesc> fills;
     fills.push_back(FillDesc{err, 1});
@@ -1618,6 +1716,7 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     if (opts) o = *opts;
     if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X4 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
         o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED || o.block_rows != 0 || o.grid_blocks < 0 ||
+        o.scan_every_table < 0 || o.scan_every_table > 1 ||
         !(o.gram_block == 0 || o.gram_block == 2 || o.gram_block == 4 || o.gram_block == 6 || o.gram_block == 8))
         return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
     invalidate(c);
@@ -1645,6 +1744,7 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->features = P.n_gram;
     s->filters = (int)P.filters.size();
     s->tables = (int)P.tables.size();
+    s->derived_tables = P.n_derived;
     s->table_cells = P.table_cells;
     int launches = 1;   // fill
     for (int L = 0; L < P.levels - 1; ++L) {
@@ -1655,6 +1755,7 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     }
     launches += (int)P.root_launches.size();
     if (P.n_gram > 0 || P.need_count) launches += 1;
+    launches += (int)P.rollup_passes.size();
     launches += 1;   // assemble
     s->launches = launches;
     s->block_rows = (int32_t)std::min<int64_t>(P.rows_per_block, INT32_MAX);
@@ -1777,7 +1878,11 @@ static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
     if (s != LMFAO_OK) return s;
     if (P.n_gram > 0 || P.need_count)
         HIP_TRY(c, launch_merge(reinterpret_cast<const MergeDesc *>(db + c->merge_off), P.n_gram, st));
-    HIP_TRY(c, launch_assemble(reinterpret_cast<const AssembleDesc *>(db + c->assemble_off), (int)P.outs.size(), st));
+    for (size_t i = 0; i < c->rollup_off.size(); ++i)
+        HIP_TRY(c, launch_rollup(reinterpret_cast<const RollupDesc *>(db + c->rollup_off[i]),
+                                 (int)P.rollup_passes[i].size(), c->rollup_cells[i], st));
+    HIP_TRY(c, launch_assemble(reinterpret_cast<const AssembleDesc *>(db + c->assemble_off), (int)P.outs.size(),
+                               c->assemble_cells, st));
     return LMFAO_OK;
 }
 

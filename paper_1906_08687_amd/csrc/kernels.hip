@@ -17,6 +17,8 @@
 //  * merge_kernel        fp64 cross-workgroup reduction of the covariance
 //                        partials and counts (the domain-parallel partition
 //                        merge implied by Section 1.2)
+//  * rollup_kernel       grouped tables derived from a finer table with the
+//                        same filter by summing out one component
 //  * assemble_kernel     per-query results from the merged views
 //
 // The covariance block is computed in one of three arithmetics:
@@ -778,29 +780,69 @@ __global__ void merge_final_kernel(const MergeDesc *__restrict__ dp) {
 }
 
 // ---------------------------------------------------------------------------
-// result assembly: one workgroup per query, threads over cells
+// marginal derivation of grouped tables: one pass per key length, longest
+// first, so every source table is final when it is read; items on blockIdx.y,
+// cells of the derived table on threads; each cell sums its source cells in
+// ascending order of the dropped component (a fixed order: deterministic)
+// ---------------------------------------------------------------------------
+
+__global__ void rollup_kernel(const RollupDesc *__restrict__ dp) {
+    const AS_CONST RollupDesc &d = *cst(dp);
+    for (int i = blockIdx.y; i < d.n_items; i += gridDim.y) {
+        const AS_CONST RollupItem &it = cst(d.items)[i];
+        const int64_t S = it.suffix, D = it.dom;
+        const int tn = it.t_nvals, un = it.u_nvals;
+        const int64_t per = tn + 1;             // the cell's sums, then its count
+        const int32_t *map = d.map + it.map_base;
+        const unsigned long long *ucnt = d.g_cnt + it.u_cnt;
+        const double *uval = d.g_val + it.u_val;
+        for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < it.t_cells * per;
+             w += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t t = w / per;
+            const int j = (int)(w - t * per);
+            const int64_t u0 = (t / S) * D * S + t % S;
+            if (j == tn) {
+                unsigned long long cnt = 0;
+#pragma unroll 4
+                for (int64_t v = 0; v < D; ++v) cnt += gld(ucnt)[u0 + v * S];
+                gst(d.g_cnt)[it.t_cnt + t] = cnt;
+            } else {
+                const int k = gld(map)[j];
+                double s = 0.0;
+#pragma unroll 4
+                for (int64_t v = 0; v < D; ++v) s += gld(uval)[(u0 + v * S) * un + k];
+                gst(d.g_val)[it.t_val + t * tn + j] = s;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// result assembly: queries on blockIdx.y, cells on threads
 // ---------------------------------------------------------------------------
 
 __global__ void assemble_kernel(const AssembleDesc *__restrict__ dp) {
-    const AssembleDesc &d = *dp;
-    for (int o = blockIdx.x; o < d.n_out; o += gridDim.x) {
-        const OutDesc &O = d.outs[o];
-        const TermDesc *terms = d.terms + O.term_base;
-        const int nt = d.term_count[o];
-        for (int64_t cell = threadIdx.x; cell < O.n_cells; cell += blockDim.x) {
-            unsigned long long cnt;
-            if (O.kind == SRC_GRAM) cnt = *d.count;
-            else cnt = d.g_cnt[O.src_cnt + cell];
-            d.res_cnt[O.dst_cnt + cell] = cnt;
-            double *sum = d.res_sum + O.dst_sum + cell * O.n_aggs;
-            for (int a = 0; a < O.n_aggs; ++a) sum[a] = 0.0;
-            for (int t = 0; t < nt; ++t) {
-                const TermDesc T = terms[t];
-                double v;
-                if (T.src < 0) v = (double)cnt;
-                else if (O.kind == SRC_GRAM) v = d.gram[T.src];
-                else v = d.g_val[O.src_val + cell * O.src_nvals + T.src];
-                sum[T.agg] += T.coeff * v;
+    const AS_CONST AssembleDesc &d = *cst(dp);
+    for (int o = blockIdx.y; o < d.n_out; o += gridDim.y) {
+        const AS_CONST OutDesc &O = cst(d.outs)[o];
+        const AS_CONST TermDesc *terms = cst(d.terms) + O.term_base;
+        const int nt = cst(d.term_count)[o];
+        const bool gram = O.kind == SRC_GRAM;
+        for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < O.n_cells;
+             cell += (int64_t)gridDim.x * blockDim.x) {
+            const unsigned long long cnt = gram ? *gld(d.count) : gld(d.g_cnt)[O.src_cnt + cell];
+            gst(d.res_cnt)[O.dst_cnt + cell] = cnt;
+            const double *vals = d.g_val + O.src_val + cell * O.src_nvals;
+            // each aggregate summed in registers, its terms in list order
+            for (int a = 0; a < O.n_aggs; ++a) {
+                double s = 0.0;
+                for (int t = 0; t < nt; ++t) {
+                    if (terms[t].agg != a) continue;
+                    const int src = terms[t].src;
+                    const double v = src < 0 ? (double)cnt : (gram ? gld(d.gram)[src] : gld(vals)[src]);
+                    s += terms[t].coeff * v;
+                }
+                gst(d.res_sum)[O.dst_sum + cell * O.n_aggs + a] = s;
             }
         }
     }
@@ -1323,9 +1365,20 @@ hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const AssembleDesc *desc, int n_out, hipStream_t st) {
-    if (n_out == 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel, dim3(n_out < 4096 ? n_out : 4096), dim3(256), 0, st, desc);
+hipError_t launch_rollup(const RollupDesc *desc, int n_items, int64_t max_work, hipStream_t st) {
+    if (n_items == 0 || max_work <= 0) return hipSuccess;
+    const int64_t bx = (max_work + 255) / 256;
+    hipLaunchKernelGGL(rollup_kernel, dim3(bx < 1024 ? (unsigned)bx : 1024u, n_items < 1024 ? n_items : 1024), dim3(256),
+                       0, st, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AssembleDesc *desc, int n_out, int64_t max_cells, hipStream_t st) {
+    if (n_out == 0 || max_cells <= 0) return hipSuccess;
+    const int bs = max_cells < 256 ? 64 : 256;
+    const int64_t bx = (max_cells + bs - 1) / bs;
+    hipLaunchKernelGGL(assemble_kernel, dim3(bx < 1024 ? (unsigned)bx : 1024u, n_out < 4096 ? n_out : 4096), dim3(bs), 0,
+                       st, desc);
     return hipGetLastError();
 }
 

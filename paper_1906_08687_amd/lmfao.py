@@ -65,7 +65,7 @@ class _Query(ctypes.Structure):
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("planner", ctypes.c_int32),
                 ("block_rows", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32),
-                ("cost_model", ctypes.c_char_p)]
+                ("cost_model", ctypes.c_char_p), ("scan_every_table", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -75,7 +75,7 @@ class _Stats(ctypes.Structure):
                 ("table_cells", ctypes.c_int64), ("launches", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("nbuf", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("dedicated_scan", ctypes.c_int32)]
+                ("dedicated_scan", ctypes.c_int32), ("derived_tables", ctypes.c_int32)]
 
 
 # every symbol the header declares
@@ -236,8 +236,13 @@ class Context:
         return qid.value
 
     # ---- planning --------------------------------------------------------------------
-    def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0):
-        o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None)
+    def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0,
+             rollup=True):
+        """``rollup``: tables one group-by component short of another table with
+        the same filter are summed from it after the scan (``scan_every_table``
+        = 0); False makes the scan update every table."""
+        o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None,
+                      0 if rollup else 1)
         self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
 
     def stats(self) -> dict:
@@ -321,7 +326,7 @@ class Engine:
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
-                 grid_blocks=0, gram_block=0, columns=None):
+                 grid_blocks=0, gram_block=0, columns=None, rollup=True):
         import torch
         self.torch = torch
         self.db = db
@@ -340,8 +345,8 @@ class Engine:
         self.ctx.set_join_tree(db.edges)
         for q in self.queries:
             self.ctx.add_query(q)
-        self.precision, self.schedule = precision, schedule
-        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block)
+        self.precision, self.schedule, self.rollup = precision, schedule, rollup
+        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup)
         self._bind()
 
     def _bind(self):
@@ -360,7 +365,7 @@ class Engine:
     def replan(self, precision=None, schedule=None, planner="heuristic", grid_blocks=0, gram_block=0):
         self.precision = precision or self.precision
         self.schedule = schedule or self.schedule
-        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block)
+        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup)
         self._bind()
 
     def run(self, stream=None):

@@ -286,13 +286,41 @@ def test_query_errors():
     ctx.plan()
 
 
+def test_marginal_derivation_is_planned_per_filter_and_chained():
+    """A grouped table one component short of a same-filter table is summed
+    from it after the scan: one pass per derived key length, each adding a
+    launch; tables under another filter are not sources."""
+    from datagen.schema import Agg, GroupBy, Pred, Query
+    ctx = new_ctx()
+    star(ctx)
+    filt = [Pred("a0", "le", 0.5)]
+    ctx.add_query(Query(groupby=[GroupBy("fc"), GroupBy("ac")], aggs=[Agg.monomial("f0")]))
+    ctx.add_query(Query(groupby=[GroupBy("ac")], aggs=[Agg.monomial("f1")]))          # from (fc, ac)
+    ctx.add_query(Query(groupby=[GroupBy("fc")], where=filt))                          # no filtered source
+    ctx.add_query(Query(where=filt, aggs=[Agg.monomial("a1")]))                        # from the filtered (fc)
+    ctx.add_query(Query(groupby=[GroupBy("b0", [-1.0, 0.0, 1.0]), GroupBy("fc"), GroupBy("ac")]))
+    ctx.plan("fp32", "batched", rollup=False)
+    off = ctx.stats()
+    ctx.plan("fp32", "batched")
+    on = ctx.stats()
+    assert off["derived_tables"] == 0 and off["tables"] == on["tables"] == 5
+    # (fc, ac) now comes from the 3-component table as well, (ac) from (fc, ac),
+    # the filtered count from the filtered (fc): three passes (key lengths 2, 1, 0)
+    assert on["derived_tables"] == 3
+    assert on["launches"] == off["launches"] + 3
+    ctx.plan("fp32", "plain")
+    plain = ctx.stats()
+    ctx.plan("fp32", "plain", rollup=False)
+    assert plain["launches"] == ctx.stats()["launches"] - 3 + 3     # three fewer table scans, three passes
+
+
 def test_plan_option_errors():
     ctx = new_ctx()
     star(ctx)
     ctx.add_query(covariance(["f0"])[1])
-    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None)
+    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None, 0)
     for field, bad in (("precision", 3), ("schedule", 2), ("planner", 9), ("block_rows", 128), ("grid_blocks", -1),
-                       ("gram_block", 5)):
+                       ("gram_block", 5), ("scan_every_table", 2)):
         x = lmfao._PlanOpts.from_buffer_copy(o)
         setattr(x, field, bad)
         assert ctx.lib.lmfao_plan(ctx.ptr, ctypes.byref(x)) == -1, field

@@ -4,7 +4,8 @@ three-dimensional data cube with five measures over workload 2's schema
 classification-tree level over workload 3's schema (equations (9) and (10):
 per node and split attribute, COUNT GROUP BY (label, bucket) and COUNT GROUP
 BY bucket).  Both run on the general root scan (grouped tables; no
-covariance block), in the batched and the plain schedule.
+covariance block), in the batched and the plain schedule, with the coarser
+tables derived from finer ones after the scan and with every table scanned.
 
 Counts are bit-exact; sums follow tests/helpers.check_sums at 1e-6.
 """
@@ -33,12 +34,34 @@ def _batch(name):
     return _cache[name]
 
 
+@pytest.mark.parametrize("rollup", [True, False], ids=["derived", "scanned"])
 @pytest.mark.parametrize("schedule", ["batched", "plain"])
 @pytest.mark.parametrize("name", ["cube", "classification_tree"])
-def test_batch_parity(name, schedule):
+def test_batch_parity(name, schedule, rollup):
     from paper_1906_08687_amd.lmfao import Engine
     db, qs, ref = _batch(name)
-    print("case: %s %s, %d fact rows, %d queries" % (name, schedule, db.relations[0].n_rows, len(qs)), flush=True)
-    eng = Engine(db, qs, precision="fp32", schedule=schedule)
+    print("case: %s %s rollup=%s, %d fact rows, %d queries" % (name, schedule, rollup, db.relations[0].n_rows, len(qs)),
+          flush=True)
+    eng = Engine(db, qs, precision="fp32", schedule=schedule, rollup=rollup)
+    assert (eng.ctx.stats()["derived_tables"] > 0) == rollup
     eng.run()
     compare(eng.results(), ref, qs, 1e-6, "%s %s" % (name, schedule))
+
+
+@pytest.mark.parametrize("name", ["cube", "classification_tree"])
+def test_derived_tables_match_scanned_tables(name):
+    """Summing a finer table after the scan gives the same counts as updating
+    the coarser table per row, and sums equal up to the order of fp64
+    additions."""
+    import numpy as np
+    from paper_1906_08687_amd.lmfao import Engine
+    db, qs, _ = _batch(name)
+    print("case: %s derived vs scanned" % name, flush=True)
+    res = []
+    for rollup in (True, False):
+        eng = Engine(db, qs, precision="fp32", schedule="batched", rollup=rollup)
+        eng.run()
+        res.append(eng.results())
+    for a, b in zip(*res):
+        np.testing.assert_array_equal(a.counts, b.counts)
+        np.testing.assert_allclose(a.sums, b.sums, rtol=1e-9, atol=1e-6)

@@ -202,6 +202,12 @@ typedef struct {
     int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */
     int32_t dedicated_scan;      /* 1: the covariance-only root scan runs on the dedicated BF16 kernel */
     int32_t derived_tables;      /* grouped tables summed from a finer table after the scan */
+    int32_t strided_families;    /* filtered table families whose LDS tables are addressed from the
+                                    filter's rank instead of per-table descriptors */
+    int32_t code_scan;           /* 1: COUNT-only filtered tables over several LDS partitions; the root
+                                    scan writes each row's filter mask and key cells once (4 bytes per
+                                    key and row of workspace, at most 16 GiB) and a code scan per
+                                    partition updates the tables from them */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);

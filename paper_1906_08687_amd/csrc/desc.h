@@ -98,6 +98,8 @@ struct KeyDesc {          // group-by key: cell = sum_i comp[c[i]] * s[i]
     int32_t s[kMaxKeyComps];
     int32_t n_comp;
     int32_t n_cells;
+    int32_t off_cnt;      // strided families: word offsets of this key's counts and sums
+    int32_t off_val;      // from the start of its filter's group of tables
 };
 
 struct ValDesc {          // summed monomial x[a] * x[b]; feature 0 is the constant 1
@@ -107,7 +109,7 @@ struct ValDesc {          // summed monomial x[a] * x[b]; feature 0 is the const
 struct TabDesc {          // one table = (filter, key) of a family
     int32_t part;         // table partition (blockIdx.y) that evaluates it
     int32_t lds_cnt;      // word offset of uint32 counts in LDS, or -1 when global
-    int32_t lds_val;      // word offset of fp32 sums in LDS
+    int32_t lds_val;      // word offset of fp64 sums in LDS
     int32_t pad;
     int64_t glb_cnt;      // index of the first uint64 count in the global count array
     int64_t glb_val;      // index of the first double sum in the global sum array
@@ -132,6 +134,16 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
     int32_t tab_base;     // table (f, k) = tab_base + f * n_keys + k
     uint64_t filt_mask;   // union of the family's filter bits
     uint64_t part_mask[kMaxParts];   // filter bits whose tables belong to each partition
+    // Strided layout (filtered families whose tables all sit in LDS): the tables of one
+    // filter are a group of unit_words words, and the groups of the filters of partition
+    // p follow each other in filter order from part_base[p].  The group of filter bit b
+    // then starts at part_base[p] + popcount(part_mask[p] & (2^b - 1)) * unit_words, so no
+    // per-lane table descriptor is read.
+    int32_t strided;
+    int32_t unit_words;
+    int32_t part_base[kMaxParts];
+    int32_t code_base;    // per-row codes: column of this family's first key
+    int32_t pad_c;
 };
 
 constexpr int kColPitch = 68;     // words per 64-row LDS column (64 rows + 4 words of bank padding)
@@ -186,6 +198,37 @@ struct RootDesc {
     double *gram_partial;              // [grid.x][n_gram * n_gram]
     unsigned long long *count_partial; // [grid.x]
     uint32_t *err;
+    // per-row codes (see CodeScanDesc): when set, the tables are not updated here; each row's
+    // filter mask (0 when the row does not join) and the cell of every family key are written
+    uint32_t *codes;
+    int64_t code_pitch;                // words per code column (rows rounded up to 64)
+    int32_t n_mask_codes;              // mask columns: 1, or 2 with more than 32 filters
+    int32_t pad1;
+};
+
+// ---- grouped tables from per-row codes -----------------------------------------
+//
+// When the root group's tables are COUNT-only, filtered, in the strided LDS
+// layout and need more than one partition, the root scan runs once with no
+// tables and writes per-row codes instead: column-major uint32, column 0 (and
+// 1) the filter mask, then one column per family key holding the row's cell.
+// This scan then runs once per partition (blockIdx.y), with the whole LDS for
+// that partition's tables, and replays the codes: every partition reads four
+// bytes per key and row instead of repeating the root scan's gathers,
+// bucketing and predicates.
+struct CodeScanDesc {
+    int64_t n_rows;
+    int64_t rows_per_block;
+    int64_t pitch;                     // words per code column
+    const uint32_t *codes;
+    int32_t n_mask_codes;
+    int32_t n_fam;
+    const FamilyDesc *fams;            // strided, COUNT-only
+    const KeyDesc *keys;
+    const FlushDesc *flush;
+    int32_t lds_table_words[kMaxParts];
+    int32_t flush_base[kMaxParts], n_flush[kMaxParts];
+    unsigned long long *g_cnt;
 };
 
 // ---- covariance-only root scan ------------------------------------------------

@@ -57,6 +57,8 @@ typedef void (*GramKernel)(const GramDesc *);
 GramKernel gram_kernel(int nt, int nf, bool x4, bool pr);
 hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st);
 hipError_t set_gram_lds_limit(GramKernel k, size_t bytes);
+hipError_t set_code_scan_lds_limit(size_t bytes);
+hipError_t launch_code_scan(const CodeScanDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
 hipError_t launch_assemble(const AssembleDesc *desc, int n_out, int64_t max_cells, hipStream_t st);
 hipError_t launch_rollup(const RollupDesc *desc, int n_items, int64_t max_work, hipStream_t st);
@@ -231,6 +233,14 @@ struct Plan {
     int64_t table_cells = 0, table_vals = 0;
     std::vector<std::vector<int>> rollup_passes;   // derived tables per pass, in execution order
     int n_derived = 0;
+    int n_strided = 0;                             // families of root launches with strided LDS layout
+    // grouped tables from per-row codes (root scan writes them, a code scan per partition reads)
+    bool codes = false;
+    int n_mask_codes = 1, n_codes = 0;
+    int64_t code_pitch = 0;
+    int code_grid = 0;
+    int64_t code_rows_per_block = 0;
+    size_t code_lds_bytes = 0;
     // schedule
     int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
     TileCfg cfg;                      // chosen tile configuration
@@ -275,6 +285,8 @@ struct lmfao_ctx {
     std::vector<size_t> view_desc_off;            // per relation: ScanDesc offset in blob
     size_t merge_off = 0, assemble_off = 0;
     std::vector<size_t> rollup_off;               // per pass: RollupDesc offset in blob
+    size_t off_codes = 0;                         // per-row codes
+    size_t code_desc_off = 0;                     // CodeScanDesc offset in blob
     std::vector<int64_t> rollup_cells;            // per pass: most (cell, sum or count) pairs of a table
     int64_t assemble_cells = 0;                   // most cells of a query result
     // execution
@@ -1017,6 +1029,60 @@ static size_t gram_lds_bytes(const Plan &P, int waves, int nf) {
     return (pr ? 2048 : 1024) + (size_t)waves * ((size_t)quads * kQuadBytes + (size_t)nf * 16 * kFactPitch);
 }
 
+// word offset in LDS of the first table of family filter i
+static int T_start(const Plan &P, const Family &F, size_t i) { return P.tables[F.tables[i * F.keys.size()]].lds_cnt; }
+
+// Whether a filtered family's LDS layout is strided (see FamilyDesc); fills the
+// strided fields when it is.  Checked table by table against the formula the
+// kernel uses, so any other layout keeps the per-table descriptors.
+static bool family_strided(const Plan &P, const Family &F, FamilyDesc &fd) {
+    fd.strided = 0;
+    const size_t nk = F.keys.size(), nf = F.filters.size();
+    if (nf == 0 || nk == 0) return false;
+    int unit = 0;
+    for (size_t k = 0; k < nk; ++k) unit += P.tables[F.tables[k]].words();
+    for (size_t i = 0; i < nf; ++i) {
+        const Table &T0 = P.tables[F.tables[i * nk]];
+        for (size_t k = 0; k < nk; ++k) {
+            const Table &T = P.tables[F.tables[i * nk + k]];
+            const Table &R = P.tables[F.tables[k]];
+            if (T.lds_cnt < 0 || T.part != T0.part || T.lds_cnt - T0.lds_cnt != R.lds_cnt - T_start(P, F, 0) ||
+                T.lds_val - T0.lds_cnt != R.lds_val - T_start(P, F, 0))
+                return false;
+        }
+    }
+    int base[kMaxParts], rank[kMaxParts] = {};
+    for (size_t i = 0; i < nf; ++i) {
+        const Table &T0 = P.tables[F.tables[i * nk]];
+        const int p = T0.part;
+        if (rank[p] == 0) base[p] = T0.lds_cnt;
+        else if (T0.lds_cnt != base[p] + rank[p] * unit) return false;
+        ++rank[p];
+    }
+    fd.strided = 1;
+    fd.unit_words = unit;
+    for (int p = 0; p < kMaxParts; ++p) fd.part_base[p] = rank[p] ? base[p] : 0;
+    return true;
+}
+
+// Per-row codes (see CodeScanDesc): tables that are all COUNT-only and filtered.
+static bool codes_eligible(const Plan &P) {
+    if (P.fams.empty()) return false;
+    for (auto &F : P.fams)
+        if (F.filters.empty() || !F.vals.empty()) return false;
+    return true;
+}
+
+static bool all_strided(const Plan &P) {
+    for (auto &F : P.fams) {
+        FamilyDesc fd{};
+        if (!family_strided(P, F, fd)) return false;
+    }
+    return true;
+}
+
+constexpr size_t kMaxCodeBytes = (size_t)16 << 30;   // workspace the per-row codes may take
+
 static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     Plan &P = c->plan;
     const Rel &root = c->rels[P.root];
@@ -1055,6 +1121,30 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     }
     const int budget = table_words_fit(c, P, P.mode, p1, has_tables, P.nbuf, P.waves);
     place_tables(c, P, P.lds_policy, budget);
+    // COUNT-only filtered tables that need several partitions: the root scan runs once with no
+    // tables and writes per-row codes; a code scan per partition, with the whole LDS for its
+    // tables, replays them (when the codes fit their workspace cap)
+    P.codes = false;
+    if (P.schedule == LMFAO_BATCHED && P.lds_policy == 2 && P.parts > 1 && root.n_rows > 0 && codes_eligible(P)) {
+        P.n_mask_codes = P.filters.size() > 32 ? 2 : 1;
+        P.n_codes = P.n_mask_codes;
+        for (auto &F : P.fams) P.n_codes += (int)F.keys.size();
+        P.code_pitch = round_up((int)std::min<int64_t>(root.n_rows, 1 << 30), 64);
+        const size_t bytes = (size_t)P.n_codes * (size_t)P.code_pitch * 4;
+        place_tables(c, P, 2, (int)(c->lds_limit / 4) - 64);
+        if (bytes <= kMaxCodeBytes && all_strided(P)) {
+            P.codes = true;
+            int words = 0;
+            for (auto &T : P.tables)
+                if (T.lds_cnt >= 0) words = std::max(words, T.lds_cnt + T.words());
+            P.code_lds_bytes = (size_t)words * 4;
+            P.code_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_cu, ceil_div(root.n_rows, 1024)));
+            P.code_rows_per_block = ceil_div(root.n_rows, P.code_grid);
+            P.code_grid = (int)std::max<int64_t>(1, ceil_div(root.n_rows, P.code_rows_per_block));
+        } else {
+            place_tables(c, P, P.lds_policy, budget);
+        }
+    }
     int gnt = 0, gnf = 0;
     P.gram_waves = cfg.waves > 0 ? cfg.waves : 4;
     const bool gram_ok = gram_eligible(c, P, &gnt, &gnf) && gram_lds_bytes(P, P.gram_waves, gnf) <= c->lds_limit;
@@ -1073,6 +1163,8 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         if (single_table >= 0) {
             const Table &T = P.tables[single_table];
             max_words = T.lds_cnt >= 0 ? T.words() : 0;
+        } else if (L.tables && P.codes) {
+            max_words = 0;   // tables live in the code scan
         } else if (L.tables) {
             std::vector<int> w(kMaxParts, 0);
             for (auto &T : P.tables)
@@ -1184,6 +1276,8 @@ static size_t compute_ws(lmfao_ctx *c) {
     o = align_up(o + 8);
     c->off_zero = o;
     o = align_up(o + 4 * kMaxRecWords);
+    c->off_codes = o;
+    if (P.codes) o = align_up(o + (size_t)P.n_codes * (size_t)P.code_pitch * 4);
     c->off_mlp = o;
     o = align_up(o + ((size_t)1 << 20));
     c->off_desc = o;
@@ -1400,7 +1494,10 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     };
     unsigned long long *gcnt = reinterpret_cast<unsigned long long *>(ws + c->off_gcnt);
     double *gval = reinterpret_cast<double *>(ws + c->off_gval);
+    P.n_strided = 0;
+    CodeScanDesc csd{};
     for (auto &L : P.root_launches) {
+        int code_col = P.n_mask_codes;
         RootDesc D{};
         D.scan = rs;
         D.n_feat = P.n_feat;
@@ -1451,6 +1548,8 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             } else {
                 for (auto &k : F.keys) add_key(k);
                 fd.n_keys = (int)F.keys.size();
+                fd.code_base = code_col;
+                code_col += fd.n_keys;
                 for (size_t i = 0; i < F.tables.size(); ++i) {
                     const Table &T = P.tables[F.tables[i]];
                     TabDesc td{};
@@ -1466,6 +1565,14 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                         pw[T.part] = std::max(pw[T.part], T.lds_cnt + T.words());
                     }
                 }
+                if (family_strided(P, F, fd)) {
+                    ++P.n_strided;
+                    for (int k = 0; k < fd.n_keys; ++k) {
+                        const Table &T = P.tables[F.tables[k]];
+                        keys[fd.key_base + k].off_cnt = T.lds_cnt - T_start(P, F, 0);
+                        keys[fd.key_base + k].off_val = T.lds_val - T_start(P, F, 0);
+                    }
+                }
             }
             fdesc.push_back(fd);
         }
@@ -1476,6 +1583,23 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             D.n_flush[p] = (int)flushes[p].size();
             D.lds_table_words[p] = pw[p];
             fl.insert(fl.end(), flushes[p].begin(), flushes[p].end());
+        }
+        const bool codes = P.codes && L.tables && L.single_table < 0;
+        if (codes) {
+            // the tables move to the code scan; this launch writes the codes
+            if (code_col != P.n_codes) return fail(c, LMFAO_ERR_STATE, "internal: code columns do not match the plan");
+            for (int p = 0; p < kMaxParts; ++p) {
+                csd.flush_base[p] = D.flush_base[p];
+                csd.n_flush[p] = D.n_flush[p];
+                csd.lds_table_words[p] = D.lds_table_words[p];
+                if ((size_t)pw[p] * 4 > P.code_lds_bytes) return fail(c, LMFAO_ERR_STATE, "internal: code scan LDS");
+                D.n_flush[p] = 0;
+                D.lds_table_words[p] = 0;
+            }
+            max_words = 0;
+            D.codes = reinterpret_cast<uint32_t *>(ws + c->off_codes);
+            D.code_pitch = P.code_pitch;
+            D.n_mask_codes = P.n_mask_codes;
         }
         D.n_fam = (int)fdesc.size();
         D.n_parts = L.parts;
@@ -1506,6 +1630,17 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         D.fams = reinterpret_cast<const FamilyDesc *>(dev(B.vec(fdesc)));
         D.tabs = reinterpret_cast<const TabDesc *>(dev(B.vec(tdesc)));
         D.flush = reinterpret_cast<const FlushDesc *>(dev(B.vec(fl)));
+        if (codes) {
+            csd.n_rows = c->rels[r0].n_rows;
+            csd.rows_per_block = P.code_rows_per_block;
+            csd.pitch = P.code_pitch;
+            csd.codes = D.codes;
+            csd.n_mask_codes = P.n_mask_codes;
+            csd.n_fam = D.n_fam;
+            csd.fams = D.fams;
+            csd.flush = D.flush;
+            csd.g_cnt = gcnt;
+        }
         D.g_cnt = gcnt;
         D.g_val = gval;
         D.gram_partial = reinterpret_cast<double *>(ws + c->off_gpart);
@@ -1563,6 +1698,10 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         L.desc.vals = reinterpret_cast<const ValDesc *>(dev(vals_off));
         L.desc.filt_bits = reinterpret_cast<const int32_t *>(dev(fb_off));
         L.desc_off = L.gram ? B.put(&L.gdesc, sizeof(GramDesc)) : B.put(&L.desc, sizeof(RootDesc));
+    }
+    if (P.codes) {
+        csd.keys = reinterpret_cast<const KeyDesc *>(dev(keys_off));
+        c->code_desc_off = B.put(&csd, sizeof csd);
     }
     // ---- merge and assembly ---------------------------------------------------------------------
     MergeDesc md{};
@@ -1745,6 +1884,8 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->filters = (int)P.filters.size();
     s->tables = (int)P.tables.size();
     s->derived_tables = P.n_derived;
+    s->strided_families = P.n_strided;
+    s->code_scan = P.codes ? 1 : 0;
     s->table_cells = P.table_cells;
     int launches = 1;   // fill
     for (int L = 0; L < P.levels - 1; ++L) {
@@ -1753,7 +1894,7 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
             if (r != P.root && P.height[r] == L) ++nrel;
         launches += P.schedule == LMFAO_BATCHED ? (nrel > 0) : nrel;
     }
-    launches += (int)P.root_launches.size();
+    launches += (int)P.root_launches.size() + (P.codes ? 1 : 0);
     if (P.n_gram > 0 || P.need_count) launches += 1;
     launches += (int)P.rollup_passes.size();
     launches += 1;   // assemble
@@ -1813,6 +1954,7 @@ static lmfao_status upload(lmfao_ctx *c) {
             if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_root_lds_limit(k, L.lds_bytes));
         }
     }
+    if (c->plan.codes && c->plan.code_lds_bytes > 64 * 1024) HIP_TRY(c, set_code_scan_lds_limit(c->plan.code_lds_bytes));
     return LMFAO_OK;
 }
 
@@ -1855,6 +1997,10 @@ static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
         HIP_TRY(c, launch_root(k, reinterpret_cast<const RootDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x, L.parts,
                                L.waves, L.lds_bytes, st));
     }
+    const Plan &P = c->plan;
+    if (P.codes)
+        HIP_TRY(c, launch_code_scan(reinterpret_cast<const CodeScanDesc *>(c->ws + c->off_desc + c->code_desc_off),
+                                    P.code_grid, P.parts, P.code_lds_bytes, st));
     return LMFAO_OK;
 }
 

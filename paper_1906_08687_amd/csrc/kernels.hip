@@ -575,7 +575,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         }
 
         // ---- grouped tables (this lane's own row) ---------------------------------------------
-        if (TABLES && valid) {
+        if (TABLES && d.codes) {
+            // per-row codes for the partitioned table scan; rows past the range write nothing
+            if (row < w_end) {
+                const uint64_t m = valid ? mask : 0ull;
+                uint32_t *cd = d.codes + row;
+                gst(cd)[0] = (uint32_t)m;
+                if (d.n_mask_codes > 1) gst(cd)[d.code_pitch] = (uint32_t)(m >> 32);
+                const uint32_t *cr = W + d.w_comp + lane;
+                for (int fi = 0; fi < d.n_fam; ++fi) {
+                    const AS_CONST FamilyDesc &F = fams[fi];
+                    for (int k = 0; k < F.n_keys; ++k) {
+                        const AS_CONST KeyDesc &K = keys[F.key_base + k];
+                        int32_t cell = 0;
+                        for (int c = 0; c < K.n_comp; ++c) cell += (int32_t)cr[K.c[c] * 64] * K.s[c];
+                        gst(cd)[(int64_t)(F.code_base + k) * d.code_pitch] = (uint32_t)cell;
+                    }
+                }
+            }
+        } else if (TABLES && valid) {
             const uint32_t *cr = W + d.w_comp + lane;
             auto fval = [&](int f) -> double {
                 const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
@@ -583,6 +601,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             };
             for (int fi = 0; fi < d.n_fam; ++fi) {
                 const AS_CONST FamilyDesc &F = fams[fi];
+                if (F.strided) {
+                    // the cell of each key once per row, then one update per filter this row
+                    // satisfies, at an address computed from the filter's rank in the partition
+                    const uint64_t pm = F.part_mask[part];
+                    const uint64_t rb = mask & pm;
+                    if (rb) {
+                        const uint32_t tb = (uint32_t)(d.lds_tables + F.part_base[part]);
+                        for (int k = 0; k < F.n_keys; ++k) {
+                            const AS_CONST KeyDesc &K = keys[F.key_base + k];
+                            int32_t cell = 0;
+                            for (int c = 0; c < K.n_comp; ++c) cell += (int32_t)cr[K.c[c] * 64] * K.s[c];
+                            uint64_t b = rb;
+                            while (b) {
+                                const int bi = __ffsll((long long)b) - 1;
+                                b &= b - 1;
+                                const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
+                                atomicAdd(&smem[u + K.off_cnt + cell], 1u);
+                                if (F.n_vals) {
+                                    double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
+                                    for (int v = 0; v < F.n_vals; ++v) {
+                                        const AS_CONST ValDesc &vd = vals[F.val_base + v];
+                                        atomicAdd(vs + v, fval(vd.a) * fval(vd.b));
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    continue;
+                }
                 uint64_t bits = F.unfiltered ? 1ull : (mask & F.part_mask[part]);
                 while (bits) {
                     int f;
@@ -715,6 +762,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                     if (x != 0.0) gadd(d.g_val + F.glb_val + (int64_t)cell * F.n_vals + v, x);
                 }
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// grouped tables from per-row codes: one workgroup of 1024 threads per (row
+// block, partition); the partition's tables in LDS, a thread per row, the
+// strided addressing of the root scan
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__restrict__ dp) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    const AS_CONST CodeScanDesc &d = *cst(dp);
+    const AS_CONST FamilyDesc *fams = cst(d.fams);
+    const AS_CONST KeyDesc *keys = cst(d.keys);
+    const int part = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int words = d.lds_table_words[part];
+    for (int i = tid; i < words; i += blockDim.x) smem[i] = 0u;
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * d.rows_per_block;
+    const int64_t r1 = r0 + d.rows_per_block < d.n_rows ? r0 + d.rows_per_block : d.n_rows;
+    const uint32_t *codes = d.codes;
+    for (int64_t r = r0 + tid; r < r1; r += blockDim.x) {
+        uint64_t mask = gld(codes)[r];
+        if (d.n_mask_codes > 1) mask |= (uint64_t)gld(codes)[d.pitch + r] << 32;
+        for (int fi = 0; fi < d.n_fam; ++fi) {
+            const AS_CONST FamilyDesc &F = fams[fi];
+            const uint64_t pm = F.part_mask[part];
+            const uint64_t rb = mask & pm;
+            if (!rb) continue;
+            const uint32_t tb = (uint32_t)F.part_base[part];
+            for (int k = 0; k < F.n_keys; ++k) {
+                const uint32_t cell = gld(codes)[(int64_t)(F.code_base + k) * d.pitch + r] + (uint32_t)keys[F.key_base + k].off_cnt;
+                uint64_t b = rb;
+                while (b) {
+                    const int bi = __ffsll((long long)b) - 1;
+                    b &= b - 1;
+                    atomicAdd(&smem[tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words + cell], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int nf = d.n_flush[part];
+    for (int t = 0; t < nf; ++t) {
+        const AS_CONST FlushDesc &F = cst(d.flush)[d.flush_base[part] + t];
+        for (int cell = tid; cell < F.n_cells; cell += blockDim.x) {
+            const uint32_t c = smem[F.lds_cnt + cell];
+            if (c) gadd(d.g_cnt + F.glb_cnt + cell, (unsigned long long)c);
         }
     }
 }
@@ -1362,6 +1459,15 @@ hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st) {
     const int bx = (ntri + 63) / 64;
     hipLaunchKernelGGL(merge_groups_kernel, dim3(bx, kMergeGroups), dim3(64), 0, st, desc);
     hipLaunchKernelGGL(merge_final_kernel, dim3(bx), dim3(64), 0, st, desc);
+    return hipGetLastError();
+}
+
+hipError_t set_code_scan_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute((const void *)code_scan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_code_scan(const CodeScanDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(code_scan_kernel, dim3(grid_x, parts), dim3(1024), lds_bytes, st, desc);
     return hipGetLastError();
 }
 

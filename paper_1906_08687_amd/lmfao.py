@@ -75,7 +75,8 @@ class _Stats(ctypes.Structure):
                 ("table_cells", ctypes.c_int64), ("launches", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("nbuf", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("dedicated_scan", ctypes.c_int32), ("derived_tables", ctypes.c_int32)]
+                ("dedicated_scan", ctypes.c_int32), ("derived_tables", ctypes.c_int32),
+                ("strided_families", ctypes.c_int32), ("code_scan", ctypes.c_int32)]
 
 
 # every symbol the header declares

@@ -43,7 +43,10 @@ def test_batch_parity(name, schedule, rollup):
     print("case: %s %s rollup=%s, %d fact rows, %d queries" % (name, schedule, rollup, db.relations[0].n_rows, len(qs)),
           flush=True)
     eng = Engine(db, qs, precision="fp32", schedule=schedule, rollup=rollup)
-    assert (eng.ctx.stats()["derived_tables"] > 0) == rollup
+    st = eng.ctx.stats()
+    assert (st["derived_tables"] > 0) == rollup
+    if name == "classification_tree" and schedule == "batched":
+        assert st["strided_families"] >= 1      # the per-node tables use the strided LDS layout
     eng.run()
     compare(eng.results(), ref, qs, 1e-6, "%s %s" % (name, schedule))
 
@@ -65,3 +68,22 @@ def test_derived_tables_match_scanned_tables(name):
     for a, b in zip(*res):
         np.testing.assert_array_equal(a.counts, b.counts)
         np.testing.assert_allclose(a.sums, b.sums, rtol=1e-9, atol=1e-6)
+
+
+def test_classification_tree_every_tile_candidate_agrees():
+    """Every tile candidate of the tree level (tables in global memory, greedy
+    LDS, LDS partitions; the partitioned ones replayed from per-row codes)
+    gives the oracle's counts."""
+    from paper_1906_08687_amd.lmfao import Engine
+    db, qs, ref = _batch("classification_tree")
+    eng = Engine(db, qs, precision="fp32", schedule="batched")
+    assert eng.ctx.stats()["code_scan"] == 1
+    seen = set()
+    for i, cfg in enumerate(eng.ctx.candidates()):
+        print("case: classification_tree candidate %d %s" % (i, cfg), flush=True)
+        eng.ctx.select_candidate(i)
+        eng._bind()
+        seen.add(eng.ctx.stats()["code_scan"])
+        eng.run()
+        compare(eng.results(), ref, qs, 1e-6, "candidate %s" % cfg)
+    assert seen == {0, 1}

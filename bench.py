@@ -94,14 +94,25 @@ def time_steps(eng, stream, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+WORKLOADS = {
+    "w1": "tiny star: 100k-row fact, 2 dims; covariance of 9 attributes plus one grouped sum",
+    "w2": "snowflake: 10M-row fact (Zipf(1.1) keys), 4 dims and a sub-dimension; ridge-regression batch with "
+          "categorical group-bys and pairwise categorical counts",
+    "w3": "regression-tree level: 50M-row fact, 3 dims; COUNT, SUM(y), SUM(y^2) grouped by bucket per "
+          "(node, attribute) for 32 random nodes",
+    "w5": "mutual-information counts: 50M-row fact, 3 dims; all marginal and pairwise COUNT GROUP BY over "
+          "15 categorical attributes",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", default="covariance", choices=["covariance", "cube", "ctree"],
-                    help="covariance: the 861-aggregate covariance batch (the benchmark); cube: data cube; "
-                         "ctree: classification-tree level")
+    ap.add_argument("--batch", default="covariance", choices=["covariance", "cube", "ctree", "w1", "w2", "w3", "w5"],
+                    help="covariance: the 861-aggregate covariance batch (workload 4, the benchmark); cube: data "
+                         "cube; ctree: classification-tree level; wK: workload K's batch at full size")
     ap.add_argument("--n-fact", type=int, default=None, help="fact rows (default: the batch's full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -147,6 +158,15 @@ def main():
         workload = ("data cube: 3 dimensions (c0 of the fact, c1 and c4 of two dimensions; 60/65/112 values "
                     "at this seed) x 5 measures, 8 group-bys, over workload 2's snowflake at 10M fact rows")
         cpu_rows = 10_000_000
+    elif args.batch in WORKLOADS:
+        k = int(args.batch[1])
+        db = make_database(k, "full", **over)
+        qs = make_batch(k, db)
+        has_gram = any(not q.groupby and not q.where and q.aggs for q in qs)
+        precision = args.precision if has_gram else "fp32"
+        metric = "join tuples aggregated/sec (workload %d, %s fact)" % (k, "{:,}".format(db.relations[0].n_rows))
+        workload = WORKLOADS[args.batch]
+        cpu_rows = {1: 100_000, 2: 2_000_000, 3: 1_000_000, 5: 2_000_000}[k]
     else:
         db = make_database(3, "full", **over)
         qs = classification_tree_batch(db, "g3", tree_level(db, seed=3))
@@ -307,7 +327,7 @@ def main():
         "vs_baseline": None,
         "dtype": ("%s-split/f32-acc/f64-merge" % precision) if precision != "fp32" else "f32/u64-counts/f64-merge",
         "data": "synthetic (seeded; %s recipe)" % {"covariance": "workload 4", "cube": "workload 2",
-                                                    "ctree": "workload 3"}[args.batch],
+                                                    "ctree": "workload 3"}.get(args.batch, "workload " + args.batch[1:]),
         "config": {"workload": workload,
                    "fact_rows": n_join, "aggregates": len(qs), "plan": chosen, "candidate": best,
                    "plan_choices": plans,

@@ -176,6 +176,9 @@ typedef struct {
                               longest key first.  1: the fact scan updates every table.  Other
                               values are INVALID_ARG.  Results agree up to the order of fp64
                               additions; counts are identical. */
+    int32_t no_row_codes;  /* 0: filtered tables over several LDS partitions are updated from per-row
+                              codes when they qualify (see lmfao_stats.code_scan); 1: the root scan
+                              updates them itself, once per partition.  Other values are INVALID_ARG. */
 } lmfao_plan_opts;
 
 /* Build the evaluation plan for all queries added so far. */
@@ -204,10 +207,10 @@ typedef struct {
     int32_t derived_tables;      /* grouped tables summed from a finer table after the scan */
     int32_t strided_families;    /* filtered table families whose LDS tables are addressed from the
                                     filter's rank instead of per-table descriptors */
-    int32_t code_scan;           /* 1: COUNT-only filtered tables over several LDS partitions; the root
-                                    scan writes each row's filter mask and key cells once (4 bytes per
-                                    key and row of workspace, at most 16 GiB) and a code scan per
-                                    partition updates the tables from them */
+    int32_t code_scan;           /* 1: filtered tables (at most 4 sums each) over several LDS partitions;
+                                    the root scan writes each row's filter mask, key cells and summed
+                                    feature values once (4 bytes per column and row of workspace, at
+                                    most 16 GiB) and a code scan per partition updates the tables */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);

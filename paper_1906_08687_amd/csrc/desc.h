@@ -203,19 +203,26 @@ struct RootDesc {
     uint32_t *codes;
     int64_t code_pitch;                // words per code column (rows rounded up to 64)
     int32_t n_mask_codes;              // mask columns: 1, or 2 with more than 32 filters
+    int32_t n_code_feats;              // staged features summed by the tables, written as fp32 codes
+    const int32_t *code_feats;         // [n_code_feats] their staged feature ids
+    int32_t code_feat_col;             // column of the first of them
     int32_t pad1;
 };
 
 // ---- grouped tables from per-row codes -----------------------------------------
 //
-// When the root group's tables are COUNT-only, filtered, in the strided LDS
-// layout and need more than one partition, the root scan runs once with no
-// tables and writes per-row codes instead: column-major uint32, column 0 (and
-// 1) the filter mask, then one column per family key holding the row's cell.
+// When the root group's tables are filtered, sum at most kMaxCodeVals
+// monomials, sit in the strided LDS layout and need more than one partition,
+// the root scan runs once with no tables and writes per-row codes instead:
+// column-major 32-bit words, column 0 (and 1) the filter mask, then one column
+// per family key holding the row's cell, then the fp32 value of every feature
+// the tables sum (products are formed here, in fp64, as the root scan would).
 // This scan then runs once per partition (blockIdx.y), with the whole LDS for
 // that partition's tables, and replays the codes: every partition reads four
 // bytes per key and row instead of repeating the root scan's gathers,
 // bucketing and predicates.
+constexpr int kMaxCodeVals = 4;
+
 struct CodeScanDesc {
     int64_t n_rows;
     int64_t rows_per_block;
@@ -223,12 +230,15 @@ struct CodeScanDesc {
     const uint32_t *codes;
     int32_t n_mask_codes;
     int32_t n_fam;
-    const FamilyDesc *fams;            // strided, COUNT-only
+    const FamilyDesc *fams;            // strided
     const KeyDesc *keys;
+    const ValDesc *val_cols;           // per family value (as vals): code columns of its two
+                                       // factors, -1 for the constant 1
     const FlushDesc *flush;
     int32_t lds_table_words[kMaxParts];
     int32_t flush_base[kMaxParts], n_flush[kMaxParts];
     unsigned long long *g_cnt;
+    double *g_val;
 };
 
 // ---- covariance-only root scan ------------------------------------------------

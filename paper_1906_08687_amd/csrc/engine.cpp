@@ -237,6 +237,8 @@ struct Plan {
     // grouped tables from per-row codes (root scan writes them, a code scan per partition reads)
     bool codes = false;
     int n_mask_codes = 1, n_codes = 0;
+    std::vector<int32_t> code_feats;               // staged features summed by the tables
+    int code_feat_col = 0;
     int64_t code_pitch = 0;
     int code_grid = 0;
     int64_t code_rows_per_block = 0;
@@ -1065,11 +1067,11 @@ static bool family_strided(const Plan &P, const Family &F, FamilyDesc &fd) {
     return true;
 }
 
-// Per-row codes (see CodeScanDesc): tables that are all COUNT-only and filtered.
+// Per-row codes (see CodeScanDesc): tables that are all filtered, with few sums.
 static bool codes_eligible(const Plan &P) {
     if (P.fams.empty()) return false;
     for (auto &F : P.fams)
-        if (F.filters.empty() || !F.vals.empty()) return false;
+        if (F.filters.empty() || (int)F.vals.size() > kMaxCodeVals) return false;
     return true;
 }
 
@@ -1125,10 +1127,20 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     // tables and writes per-row codes; a code scan per partition, with the whole LDS for its
     // tables, replays them (when the codes fit their workspace cap)
     P.codes = false;
-    if (P.schedule == LMFAO_BATCHED && P.lds_policy == 2 && P.parts > 1 && root.n_rows > 0 && codes_eligible(P)) {
+    if (!c->opts.no_row_codes && P.schedule == LMFAO_BATCHED && P.lds_policy == 2 && P.parts > 1 && root.n_rows > 0 &&
+        codes_eligible(P)) {
         P.n_mask_codes = P.filters.size() > 32 ? 2 : 1;
         P.n_codes = P.n_mask_codes;
         for (auto &F : P.fams) P.n_codes += (int)F.keys.size();
+        std::set<int> fs;
+        for (auto &F : P.fams)
+            for (auto &v : F.vals) {
+                if (v.first > 0) fs.insert(v.first);
+                if (v.second > 0) fs.insert(v.second);
+            }
+        P.code_feats.assign(fs.begin(), fs.end());
+        P.code_feat_col = P.n_codes;
+        P.n_codes += (int)P.code_feats.size();
         P.code_pitch = round_up((int)std::min<int64_t>(root.n_rows, 1 << 30), 64);
         const size_t bytes = (size_t)P.n_codes * (size_t)P.code_pitch * 4;
         place_tables(c, P, 2, (int)(c->lds_limit / 4) - 64);
@@ -1587,7 +1599,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         const bool codes = P.codes && L.tables && L.single_table < 0;
         if (codes) {
             // the tables move to the code scan; this launch writes the codes
-            if (code_col != P.n_codes) return fail(c, LMFAO_ERR_STATE, "internal: code columns do not match the plan");
+            if (code_col != P.code_feat_col) return fail(c, LMFAO_ERR_STATE, "internal: code columns do not match the plan");
             for (int p = 0; p < kMaxParts; ++p) {
                 csd.flush_base[p] = D.flush_base[p];
                 csd.n_flush[p] = D.n_flush[p];
@@ -1600,6 +1612,9 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             D.codes = reinterpret_cast<uint32_t *>(ws + c->off_codes);
             D.code_pitch = P.code_pitch;
             D.n_mask_codes = P.n_mask_codes;
+            D.n_code_feats = (int)P.code_feats.size();
+            D.code_feats = reinterpret_cast<const int32_t *>(dev(B.vec(P.code_feats)));
+            D.code_feat_col = P.code_feat_col;
         }
         D.n_fam = (int)fdesc.size();
         D.n_parts = L.parts;
@@ -1640,6 +1655,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             csd.fams = D.fams;
             csd.flush = D.flush;
             csd.g_cnt = gcnt;
+            csd.g_val = gval;
         }
         D.g_cnt = gcnt;
         D.g_val = gval;
@@ -1700,6 +1716,20 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         L.desc_off = L.gram ? B.put(&L.gdesc, sizeof(GramDesc)) : B.put(&L.desc, sizeof(RootDesc));
     }
     if (P.codes) {
+        // each value's factors as code columns (-1: the constant 1)
+        std::vector<ValDesc> vcols;
+        for (auto &v : vals) {
+            int16_t col[2];
+            const int f[2] = {v.a, v.b};
+            for (int i = 0; i < 2; ++i) {
+                if (f[i] == 0) { col[i] = -1; continue; }
+                const auto it = std::find(P.code_feats.begin(), P.code_feats.end(), f[i]);
+                if (it == P.code_feats.end()) return fail(c, LMFAO_ERR_STATE, "internal: summed feature without a code");
+                col[i] = (int16_t)(P.code_feat_col + (it - P.code_feats.begin()));
+            }
+            vcols.push_back(ValDesc{col[0], col[1]});
+        }
+        csd.val_cols = reinterpret_cast<const ValDesc *>(dev(B.vec(vcols)));
         csd.keys = reinterpret_cast<const KeyDesc *>(dev(keys_off));
         c->code_desc_off = B.put(&csd, sizeof csd);
     }
@@ -1855,7 +1885,7 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     if (opts) o = *opts;
     if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X4 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
         o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED || o.block_rows != 0 || o.grid_blocks < 0 ||
-        o.scan_every_table < 0 || o.scan_every_table > 1 ||
+        o.scan_every_table < 0 || o.scan_every_table > 1 || o.no_row_codes < 0 || o.no_row_codes > 1 ||
         !(o.gram_block == 0 || o.gram_block == 2 || o.gram_block == 4 || o.gram_block == 6 || o.gram_block == 8))
         return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
     invalidate(c);

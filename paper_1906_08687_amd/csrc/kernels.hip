@@ -592,6 +592,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         gst(cd)[(int64_t)(F.code_base + k) * d.code_pitch] = (uint32_t)cell;
                     }
                 }
+                for (int j = 0; j < d.n_code_feats; ++j) {
+                    const int f = cst(d.code_feats)[j];
+                    const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
+                    gst(cd)[(int64_t)(d.code_feat_col + j) * d.code_pitch] =
+                        __float_as_uint(fsm[L.base + buf * L.step + lane * L.stride]);
+                }
             }
         } else if (TABLES && valid) {
             const uint32_t *cr = W + d.w_comp + lane;
@@ -769,7 +775,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // ---------------------------------------------------------------------------
 // grouped tables from per-row codes: one workgroup of 1024 threads per (row
 // block, partition); the partition's tables in LDS, a thread per row, the
-// strided addressing of the root scan
+// strided addressing and the fp64 products of the root scan
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__restrict__ dp) {
@@ -777,6 +783,7 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
     const AS_CONST CodeScanDesc &d = *cst(dp);
     const AS_CONST FamilyDesc *fams = cst(d.fams);
     const AS_CONST KeyDesc *keys = cst(d.keys);
+    const AS_CONST ValDesc *vcols = cst(d.val_cols);
     const int part = blockIdx.y;
     const int tid = threadIdx.x;
     const int words = d.lds_table_words[part];
@@ -794,13 +801,33 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
             const uint64_t rb = mask & pm;
             if (!rb) continue;
             const uint32_t tb = (uint32_t)F.part_base[part];
+            // the row's summed monomials, products of two fp32 codes formed in fp64
+            double pv[kMaxCodeVals];
+#pragma unroll
+            for (int v = 0; v < kMaxCodeVals; ++v) {
+                pv[v] = 0.0;
+                if (v < F.n_vals) {
+                    const AS_CONST ValDesc &vc = vcols[F.val_base + v];
+                    const float xa = vc.a < 0 ? 1.f : __uint_as_float(gld(codes)[(int64_t)vc.a * d.pitch + r]);
+                    const float xb = vc.b < 0 ? 1.f : __uint_as_float(gld(codes)[(int64_t)vc.b * d.pitch + r]);
+                    pv[v] = (double)xa * (double)xb;
+                }
+            }
             for (int k = 0; k < F.n_keys; ++k) {
-                const uint32_t cell = gld(codes)[(int64_t)(F.code_base + k) * d.pitch + r] + (uint32_t)keys[F.key_base + k].off_cnt;
+                const AS_CONST KeyDesc &K = keys[F.key_base + k];
+                const uint32_t cell = gld(codes)[(int64_t)(F.code_base + k) * d.pitch + r];
                 uint64_t b = rb;
                 while (b) {
                     const int bi = __ffsll((long long)b) - 1;
                     b &= b - 1;
-                    atomicAdd(&smem[tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words + cell], 1u);
+                    const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
+                    atomicAdd(&smem[u + K.off_cnt + cell], 1u);
+                    if (F.n_vals) {
+                        double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
+#pragma unroll
+                        for (int v = 0; v < kMaxCodeVals; ++v)
+                            if (v < F.n_vals) atomicAdd(vs + v, pv[v]);
+                    }
                 }
             }
         }
@@ -809,9 +836,15 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
     const int nf = d.n_flush[part];
     for (int t = 0; t < nf; ++t) {
         const AS_CONST FlushDesc &F = cst(d.flush)[d.flush_base[part] + t];
+        const double *val = reinterpret_cast<const double *>(smem + F.lds_val);
         for (int cell = tid; cell < F.n_cells; cell += blockDim.x) {
             const uint32_t c = smem[F.lds_cnt + cell];
-            if (c) gadd(d.g_cnt + F.glb_cnt + cell, (unsigned long long)c);
+            if (c == 0u) continue;
+            gadd(d.g_cnt + F.glb_cnt + cell, (unsigned long long)c);
+            for (int v = 0; v < F.n_vals; ++v) {
+                const double x = val[(int64_t)cell * F.n_vals + v];
+                if (x != 0.0) gadd(d.g_val + F.glb_val + (int64_t)cell * F.n_vals + v, x);
+            }
         }
     }
 }

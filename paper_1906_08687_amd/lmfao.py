@@ -65,7 +65,8 @@ class _Query(ctypes.Structure):
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("planner", ctypes.c_int32),
                 ("block_rows", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32),
-                ("cost_model", ctypes.c_char_p), ("scan_every_table", ctypes.c_int32)]
+                ("cost_model", ctypes.c_char_p), ("scan_every_table", ctypes.c_int32),
+                ("no_row_codes", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -238,12 +239,14 @@ class Context:
 
     # ---- planning --------------------------------------------------------------------
     def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0,
-             rollup=True):
+             rollup=True, row_codes=True):
         """``rollup``: tables one group-by component short of another table with
         the same filter are summed from it after the scan (``scan_every_table``
-        = 0); False makes the scan update every table."""
+        = 0); False makes the scan update every table.  ``row_codes``: filtered
+        tables over several LDS partitions are updated from per-row codes when
+        they qualify (``no_row_codes`` = 0)."""
         o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None,
-                      0 if rollup else 1)
+                      0 if rollup else 1, 0 if row_codes else 1)
         self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
 
     def stats(self) -> dict:
@@ -327,7 +330,7 @@ class Engine:
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
-                 grid_blocks=0, gram_block=0, columns=None, rollup=True):
+                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True):
         import torch
         self.torch = torch
         self.db = db
@@ -346,8 +349,8 @@ class Engine:
         self.ctx.set_join_tree(db.edges)
         for q in self.queries:
             self.ctx.add_query(q)
-        self.precision, self.schedule, self.rollup = precision, schedule, rollup
-        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup)
+        self.precision, self.schedule, self.rollup, self.row_codes = precision, schedule, rollup, row_codes
+        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes)
         self._bind()
 
     def _bind(self):
@@ -366,7 +369,7 @@ class Engine:
     def replan(self, precision=None, schedule=None, planner="heuristic", grid_blocks=0, gram_block=0):
         self.precision = precision or self.precision
         self.schedule = schedule or self.schedule
-        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup)
+        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup, self.row_codes)
         self._bind()
 
     def run(self, stream=None):

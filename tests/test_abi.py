@@ -318,9 +318,9 @@ def test_plan_option_errors():
     ctx = new_ctx()
     star(ctx)
     ctx.add_query(covariance(["f0"])[1])
-    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None, 0)
+    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None, 0, 0)
     for field, bad in (("precision", 3), ("schedule", 2), ("planner", 9), ("block_rows", 128), ("grid_blocks", -1),
-                       ("gram_block", 5), ("scan_every_table", 2)):
+                       ("gram_block", 5), ("scan_every_table", 2), ("no_row_codes", -1)):
         x = lmfao._PlanOpts.from_buffer_copy(o)
         setattr(x, field, bad)
         assert ctx.lib.lmfao_plan(ctx.ptr, ctypes.byref(x)) == -1, field

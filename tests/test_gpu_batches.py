@@ -35,18 +35,20 @@ def _batch(name):
 
 
 @pytest.mark.parametrize("rollup", [True, False], ids=["derived", "scanned"])
-@pytest.mark.parametrize("schedule", ["batched", "plain"])
+@pytest.mark.parametrize("schedule", ["batched", "batched-no-codes", "plain"])
 @pytest.mark.parametrize("name", ["cube", "classification_tree"])
 def test_batch_parity(name, schedule, rollup):
     from paper_1906_08687_amd.lmfao import Engine
     db, qs, ref = _batch(name)
     print("case: %s %s rollup=%s, %d fact rows, %d queries" % (name, schedule, rollup, db.relations[0].n_rows, len(qs)),
           flush=True)
-    eng = Engine(db, qs, precision="fp32", schedule=schedule, rollup=rollup)
+    codes = schedule != "batched-no-codes"
+    eng = Engine(db, qs, precision="fp32", schedule=schedule.split("-")[0], rollup=rollup, row_codes=codes)
     st = eng.ctx.stats()
     assert (st["derived_tables"] > 0) == rollup
-    if name == "classification_tree" and schedule == "batched":
+    if name == "classification_tree" and schedule != "plain":
         assert st["strided_families"] >= 1      # the per-node tables use the strided LDS layout
+        assert st["code_scan"] == int(codes)
     eng.run()
     compare(eng.results(), ref, qs, 1e-6, "%s %s" % (name, schedule))
 

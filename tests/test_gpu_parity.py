@@ -153,3 +153,32 @@ def test_empty_fact_and_empty_result_cells():
     eng.run()
     compare(eng.results(), ref, qs, 1e-6, "empty fact")
     assert int(eng.results()[0].counts[0]) == 0
+
+
+@pytest.mark.parametrize("codes", [True, False], ids=["row-codes", "rescans"])
+def test_regression_tree_level_paths(codes):
+    """Workload 3's node histograms (COUNT, SUM(y), SUM(y^2) per node and
+    bucket) over several LDS partitions: replayed from per-row codes with the
+    sums' fp64 products formed from fp32 value codes, or updated by the root
+    scan itself once per partition (strided addressing)."""
+    db, qs, ref = _workload(3)
+    print("case: workload 3 fp32 batched, row codes %s" % codes, flush=True)
+    eng = _engine(db, qs, precision="fp32", schedule="batched", row_codes=codes)
+    st = eng.ctx.stats()
+    assert st["code_scan"] == int(codes) and st["strided_families"] >= 1
+    eng.run()
+    compare(eng.results(), ref, qs, RTOL["fp32"], "workload 3 row codes %s" % codes)
+
+
+def test_regression_tree_every_tile_candidate_agrees():
+    db, qs, ref = _workload(3)
+    eng = _engine(db, qs, precision="fp32", schedule="batched")
+    seen = set()
+    for i, cfg in enumerate(eng.ctx.candidates()):
+        print("case: workload 3 candidate %d %s" % (i, cfg), flush=True)
+        eng.ctx.select_candidate(i)
+        eng._bind()
+        seen.add(eng.ctx.stats()["code_scan"])
+        eng.run()
+        compare(eng.results(), ref, qs, RTOL["fp32"], "workload 3 candidate %s" % cfg)
+    assert seen == {0, 1}

@@ -341,7 +341,7 @@ def main():
         "errors_vs_oracle": errors,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("kernels.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,
+                     "traffic": measured_traffic("gram_scan.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,
                      "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % precision,
                      "algorithmic_bytes": alg, "kernel_ms": root_ms},
         "cpu_baseline": cpu,

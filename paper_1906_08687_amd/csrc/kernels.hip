@@ -14,12 +14,17 @@
 //                        (COUNT and SUM of monomials GROUP BY components,
 //                        optionally restricted by a filter; equations (3),
 //                        (4), (7), (8)).
+//  * code_scan_kernel    grouped tables over several LDS partitions, updated
+//                        from per-row codes the root scan writes once
 //  * merge_kernel        fp64 cross-workgroup reduction of the covariance
 //                        partials and counts (the domain-parallel partition
 //                        merge implied by Section 1.2)
 //  * rollup_kernel       grouped tables derived from a finer table with the
 //                        same filter by summing out one component
 //  * assemble_kernel     per-query results from the merged views
+//
+// The covariance-only scan on matrix cores (gram_scan_kernel) is in
+// gram_scan.hip; helpers both files use are in device.h.
 //
 // The covariance block is computed in one of three arithmetics:
 //   FP32      register-blocked fp32 FMAs over a row tile staged in LDS;
@@ -33,33 +38,9 @@
 #include <hip/hip_runtime.h>
 
 #include "desc.h"
+#include "device.h"
 
 namespace lmfao {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kMaxChild = 8;
-
-// Address-space views.  Descriptor arrays are read through the constant
-// space (scalar loads that wait on lgkmcnt only); per-lane data and atomics
-// go through the global space.  Generic (flat) accesses would count against
-// both wait counters and serialise the asynchronous LDS copies.
-#define AS_GLOBAL __attribute__((address_space(1)))
-#define AS_CONST __attribute__((address_space(4)))
-template <class T>
-__device__ __forceinline__ const AS_CONST T *cst(const T *p) { return (const AS_CONST T *)p; }
-template <class T>
-__device__ __forceinline__ const AS_GLOBAL T *gld(const T *p) { return (const AS_GLOBAL T *)p; }
-template <class T>
-__device__ __forceinline__ AS_GLOBAL T *gst(T *p) { return (AS_GLOBAL T *)p; }
-template <class T>
-__device__ __forceinline__ void gadd(T *p, T v) {
-    __hip_atomic_fetch_add(gst(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void gor(uint32_t *p, uint32_t v) {
-    __hip_atomic_fetch_or(gst(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ---------------------------------------------------------------------------
 // fills (used instead of memset nodes so the sequence can live in a graph)
@@ -200,64 +181,6 @@ __global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__re
     if (seen_before != 0u) gor(d.err, kErrDupKey);
 }
 
-// ---------------------------------------------------------------------------
-// helpers of the root scan
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t bf16_rne(float x) {
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// s + e += x with TwoSum (Knuth): s is the fp32 sum, e its running error
-__device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
-    const float t = s + x;
-    const float bp = t - s;
-    e += (s - (t - bp)) + (x - bp);
-    s = t;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) void lds_void;
-
-// Asynchronous global -> LDS copies (no registers): every lane's 4 or 16
-// bytes land at lds_base + lane * size.  lds_base must be wave-uniform.
-__device__ __forceinline__ void lds_dma4(const void *g, uint32_t *lds_base) {
-    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds_base, 4, 0, 0);
-}
-__device__ __forceinline__ void lds_dma16(const void *g, uint32_t *lds_base) {
-    __builtin_amdgcn_global_load_lds(g, (lds_void *)lds_base, 16, 0, 0);
-}
-
-// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), both round-to-nearest-even
-__device__ __forceinline__ void split_bf16x8(const float *x, bf16x8 &hi, bf16x8 &lo) {
-    uint32_t h[4], l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const f32x2 v = {x[2 * i], x[2 * i + 1]};
-        const bf16x2 hb = __builtin_convertvector(v, bf16x2);
-        const f32x2 hf = __builtin_convertvector(hb, f32x2);
-        const bf16x2 lb = __builtin_convertvector(v - hf, bf16x2);
-        h[i] = __builtin_bit_cast(uint32_t, hb);
-        l[i] = __builtin_bit_cast(uint32_t, lb);
-    }
-    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
-    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
-}
-
-constexpr int kFlushTiles = 16;   // mfma accumulators fold into fp32 sums every 16 tiles (1024 rows per wave)
 
 // Where a staged feature of a tile lives in LDS: word(row) = base + buf * step + row * stride.
 struct FeatLoc {
@@ -778,6 +701,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // strided addressing and the fp64 products of the root scan
 // ---------------------------------------------------------------------------
 
+constexpr int kCodeBatch = 8;   // key cells of one row requested together by the code scan
+
 __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__restrict__ dp) {
     extern __shared__ __align__(16) uint32_t smem[];
     const AS_CONST CodeScanDesc &d = *cst(dp);
@@ -813,20 +738,29 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
                     pv[v] = (double)xa * (double)xb;
                 }
             }
-            for (int k = 0; k < F.n_keys; ++k) {
-                const AS_CONST KeyDesc &K = keys[F.key_base + k];
-                const uint32_t cell = gld(codes)[(int64_t)(F.code_base + k) * d.pitch + r];
-                uint64_t b = rb;
-                while (b) {
-                    const int bi = __ffsll((long long)b) - 1;
-                    b &= b - 1;
-                    const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
-                    atomicAdd(&smem[u + K.off_cnt + cell], 1u);
-                    if (F.n_vals) {
-                        double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
+            // the cells of kCodeBatch keys are requested together, then their updates made
+            for (int k0 = 0; k0 < F.n_keys; k0 += kCodeBatch) {
+                uint32_t cells[kCodeBatch];
 #pragma unroll
-                        for (int v = 0; v < kMaxCodeVals; ++v)
-                            if (v < F.n_vals) atomicAdd(vs + v, pv[v]);
+                for (int j = 0; j < kCodeBatch; ++j)
+                    cells[j] = k0 + j < F.n_keys ? gld(codes)[(int64_t)(F.code_base + k0 + j) * d.pitch + r] : 0u;
+#pragma unroll
+                for (int j = 0; j < kCodeBatch; ++j) {
+                    if (k0 + j >= F.n_keys) break;
+                    const AS_CONST KeyDesc &K = keys[F.key_base + k0 + j];
+                    const uint32_t cell = cells[j];
+                    uint64_t b = rb;
+                    while (b) {
+                        const int bi = __ffsll((long long)b) - 1;
+                        b &= b - 1;
+                        const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
+                        atomicAdd(&smem[u + K.off_cnt + cell], 1u);
+                        if (F.n_vals) {
+                            double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
+#pragma unroll
+                            for (int v = 0; v < kMaxCodeVals; ++v)
+                                if (v < F.n_vals) atomicAdd(vs + v, pv[v]);
+                        }
                     }
                 }
             }
@@ -979,413 +913,6 @@ __global__ void assemble_kernel(const AssembleDesc *__restrict__ dp) {
 }
 
 // ---------------------------------------------------------------------------
-// covariance-only root scan (BF16 hi+lo split on matrix cores)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
-    // raw buffer: stride 0, range `bytes`; loads beyond the range return zeros
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
-
-// One wave scans its rows in 64-row tiles.  Lane (i, g) = (lane % 16,
-// lane / 16) feeds slot i of each 16-slot tile; in k-step ks (32 rows) it
-// holds rows 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3}.  (Any pairing of
-// rows to MFMA k-indices is valid as long as every operand uses the same one;
-// this one keeps the four lane groups on different LDS banks and lets every
-// fact chunk be one 16-byte load.)  Per tile t:
-//   1. wait until tile t's records and facts and tile t+1's keys have landed;
-//   2. spread records gathered once for a uniform key to every row; write tile
-//      t's facts (loaded as 256 contiguous bytes per column) from registers to
-//      the wave's LDS fact tile, and request tile t+1's facts into them;
-//   3. find the tile's valid rows and split every slot value x = hi + lo in
-//      bf16 into operand registers (from the fact tile, the record buffer and
-//      the constant block);
-//   4. gather tile t+1's child records into the record buffer with buffer
-//      loads that bypass registers (a key outside [0, n_keys) reads past the
-//      buffer range and lands as zeros: no join), then request the keys of
-//      tile t+2 (after the last tile these requests repeat it, unused);
-//   5. accumulate hi*hi + hi*lo + lo*hi (+ lo*lo) for every upper-triangle
-//      16x16 tile pair on MFMA while those copies are in flight.
-// Fact columns and keys are streamed once: their loads are non-temporal, so
-// they do not push the gathered view records out of the caches.  Each wave
-// writes its own fp64 partial of the upper triangle (no LDS reduction).
-template <int NT, int NF, bool X4, bool PR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 3))) void gram_scan_kernel(
-    const GramDesc *__restrict__ dp) {
-    extern __shared__ __align__(16) uint32_t smem[];
-    const AS_CONST GramDesc &d = *cst(dp);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nwaves = blockDim.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-    constexpr int NP = NT * (NT + 1) / 2;
-    constexpr int NFA = NF > 0 ? NF : 1;
-
-    // the constant block: 64 rows of [1, 0, 0, 0] (pair rows: [1, 0, ..., 0] of 8 words), laid out
-    // like the record rows so that constant and padding slots read it with the records' stride
-    constexpr int kRowWords = PR ? 8 : 4;
-    if (tid < 64) {
-        smem[kRowWords * tid] = __float_as_uint(1.f);
-#pragma unroll
-        for (int w = 1; w < kRowWords; ++w) smem[kRowWords * tid + w] = 0u;
-    }
-    __syncthreads();
-
-    // row indices fit 32 bits: the planner refuses a root above 2^30 rows
-    const int n_rows = (int)d.n_rows;
-    const int rpb = (int)d.rows_per_block;
-    const int blk_begin = (int)blockIdx.x * rpb;
-    const int blk_end = min(blk_begin + rpb, n_rows);
-    // the waves of a workgroup take its 64-row tiles in turn, so that at any time they stream
-    // neighbouring stretches of every column (DRAM pages are opened once for several waves)
-    const int blk_tiles = blk_end > blk_begin ? (blk_end - blk_begin + 63) / 64 : 0;
-    const int n_tiles = blk_tiles > wave ? (blk_tiles - wave + nwaves - 1) / nwaves : 0;
-    const int n_child = d.n_child;
-    const int rbase = d.lds_wave0 + wave * d.wave_bytes;     // this wave's record buffer (bytes)
-    const uint32_t last_row = (uint32_t)(n_rows - 1);
-
-    // per-lane sources of the NT slots this lane feeds (in fact tiles, fact lanes read the
-    // fact tile in LDS at lds_off; other lanes their record word or the constant quad)
-    bool is_fact[NT];
-    int lds_off[NT];
-    const int fbase = rbase + d.fact_off;                      // this wave's fact tile in LDS
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int s = 16 * t + li;
-        const int fc = gld(&dp->slot[s].fact)[0];
-        is_fact[t] = fc >= 0;
-        const int off = gld(&dp->slot[s].lds)[0];       // row 0 of the slot's word
-        lds_off[t] = fc >= 0 ? fbase + s * kFactPitch : (gld(&dp->slot[s].per_buf)[0] ? rbase + off : off);
-    }
-    // fact loads: in load q of fact tile f, lane (i, g) reads rows 4i..4i+3 of fact column
-    // 16f + 4q + g, so 16 lanes read 256 contiguous bytes of one column.  Lanes past the last
-    // fact column read column 0 (ignored), so every load is issued by the whole wave.
-    const char *fld[NFA][4];
-    int fst[NFA][4];
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = 16 * f + 4 * q + lg;
-            fld[f][q] = reinterpret_cast<const char *>(gld(d.fact_cols)[c < d.n_fact ? c : 0]) + 16 * li;
-            fst[f][q] = fbase + c * kFactPitch + 16 * li;
-        }
-    const bool mixed = NF > 0 && d.n_fact < 16 * NF;   // wave-uniform: the last fact tile has LDS lanes too
-
-    // per-child constants, hoisted out of the tile loop (wave-uniform)
-    __amdgpu_buffer_rsrc_t rrs[kGramMaxChild];
-    const int32_t *fkp[kGramMaxChild];
-    uint32_t nkey[kGramMaxChild], rbytes[kGramMaxChild];
-    int cdst[kGramMaxChild], cnq[kGramMaxChild];
-#pragma unroll
-    for (int c = 0; c < kGramMaxChild; ++c)
-        if (c < n_child) {
-            const AS_CONST GramChild &ch = d.ch[c];
-            nkey[c] = ch.n_keys;
-            rbytes[c] = ch.rec_bytes;
-            rrs[c] = buffer_rsrc(ch.rec, nkey[c] * rbytes[c]);
-            fkp[c] = ch.fk;
-            cdst[c] = rbase + ch.quad0 * kQuadBytes;
-            cnq[c] = ch.n_quads;
-        }
-
-    f32x4 acc[NP], sacc[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        acc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
-        sacc[p] = acc[p];
-    }
-    unsigned long long count = 0;
-    int since_flush = 0;
-
-    uint32_t key[kGramMaxChild];
-    // children whose keys are equal on all 64 rows of the next / this tile (the fact is sorted
-    // by its keys, so long runs are common): their record is gathered by one lane into row 0
-    // and copied to the other rows inside LDS, which costs the memory pipeline one request
-    uint32_t uni_next = 0u, uni_cur = 0u;
-    // children whose record buffer holds one record in every row (a uniform tile, spread), and
-    // that record's key: a next tile with the same uniform key needs no copy at all
-    uint32_t held_ok = 0u;
-    uint32_t held[kGramMaxChild];
-    f32x4 F[NFA][4];      // the next tile's fact chunks, in flight (see fld)
-
-    auto tile_row = [&](int t) -> int { return blk_begin + 64 * (wave + t * nwaves); };
-    auto load_keys = [&](int t) {
-        const uint32_t row = min((uint32_t)(tile_row(t) + lane), last_row);
-#pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c)
-            if (c < n_child) key[c] = (uint32_t)__builtin_nontemporal_load(gld(fkp[c]) + row);
-    };
-    auto issue_rec = [&]() {
-        uni_next = 0u;
-#pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c)
-            if (c < n_child) {
-                const uint32_t k0 = __builtin_amdgcn_readfirstlane(key[c]);
-                const bool uni = __ballot(key[c] != k0) == 0ull;
-                uint32_t koff = __umul24(min(key[c], nkey[c]), rbytes[c]);
-                char *dst = reinterpret_cast<char *>(smem) + cdst[c];
-                if (uni && ((held_ok >> c) & 1u) && held[c] == k0) {
-                    // already in every row (the fact is sorted, so the small dimensions' keys
-                    // stay the same over many tiles)
-                } else if (uni) {
-                    uni_next |= 1u << c;
-                    held[c] = k0;
-                    held_ok |= 1u << c;
-                    if (PR) {
-                        // lanes 0 and 1: the record's two quads land in row 0 (a one-quad
-                        // record's second lane reads past the buffer range: zeros)
-                        if (lane < 2) {
-                            const uint32_t ko = lane < cnq[c] ? koff + 16u * (uint32_t)lane : nkey[c] * rbytes[c];
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, ko, 0, 0, 0);
-                        }
-                    } else if (lane == 0) {
-                        // one lane: the record lands in row 0 of each quad
-#pragma unroll 1
-                        for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
-                    }
-                } else {
-                    held_ok &= ~(1u << c);
-                    if (PR) {
-                        // lane l of request i reads quad l % 2 of row 32 i + l / 2: a row's two
-                        // quads are one contiguous 32-byte piece on neighbouring lanes, so the
-                        // memory pipeline handles one address per row, not one per row and quad
-#pragma unroll
-                        for (int i = 0; i < 2; ++i) {
-                            const uint32_t f = 64u * (uint32_t)i + (uint32_t)lane;
-                            const uint32_t kr = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(4u * (f >> 1)), (int)key[c]);
-                            const uint32_t ko = (f & 1u) < (uint32_t)cnq[c] ? __umul24(min(kr, nkey[c]), rbytes[c]) + 16u * (f & 1u)
-                                                                           : nkey[c] * rbytes[c];
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)(dst + 1024 * i), 16, ko, 0, 0, 0);
-                        }
-                    } else {
-                        // a rolled loop: per-quad conditions and addresses stay out of the scalar registers
-#pragma unroll 1
-                        for (int q = 0; q < cnq[c]; ++q, koff += 16u, dst += kQuadBytes)
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)dst, 16, koff, 0, 0, 0);
-                    }
-                }
-            }
-    };
-    // fact chunks of tile t into F: always four loads per fact tile by the whole wave, so the
-    // count of operations in flight never depends on the data.  A tile that ends past the
-    // last row loads clamped (in-bounds) chunks; its rows are re-read one by one before use.
-    auto load_fact = [&](int t) {
-        const int r0 = tile_row(t);
-        if (r0 + 64 <= n_rows) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    F[f][q] = __builtin_nontemporal_load(gld(reinterpret_cast<const f32x4 *>(fld[f][q] + (uint32_t)r0 * 4u)));
-        } else {
-            const int rq = min(r0 + 4 * li, n_rows - 4);
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    F[f][q] = gld(reinterpret_cast<const f32x4 *>(fld[f][q] - 16 * li + (uint32_t)rq * 4u))[0];
-        }
-    };
-    // the tile's facts from F into the wave's LDS fact tile (a tile ending past the last row
-    // is re-read row by row first, waited for here so no load stays pending)
-    auto store_fact = [&](int t) {
-        const int r0 = tile_row(t);
-        if (r0 + 64 > n_rows) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float *p = reinterpret_cast<const float *>(fld[f][q] - 16 * li) + r0;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) F[f][q][e] = r0 + 4 * li + e < n_rows ? gld(p)[4 * li + e] : 0.f;
-                }
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-        }
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) *reinterpret_cast<f32x4 *>(reinterpret_cast<char *>(smem) + fst[f][q]) = F[f][q];
-    };
-
-    // Phase 1 of a tile: validity, then every operand of both k-steps split into bf16 hi/lo
-    // registers.  After it the tile needs neither its LDS record buffer nor its fact
-    // registers, so the next copies can be issued before phase 2 (the MFMAs) runs.
-    bf16x8 oph[2][NT], opl[2][NT];
-    auto phase1 = [&](int t) -> bool {
-        const int r0 = tile_row(t);
-        bool valid = r0 + lane < blk_end;
-        uint32_t cnt[kGramMaxChild];
-#pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + kRowWords * lane] : 1u;
-#pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c)
-            if (cnt[c] == 0u) valid = false;
-        const uint64_t vm = __ballot(valid);
-        count += (unsigned long long)__popcll(vm);
-        const bool all_rows = vm == ~0ull;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const uint32_t vbits = (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
-                                   ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4);
-#pragma unroll
-            for (int t2 = 0; t2 < NT; ++t2) {
-                float x[8];
-                if (t2 < NF && is_fact[t2]) {
-                    // rows 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3} of the slot's column
-                    const char *base = reinterpret_cast<const char *>(smem) + lds_off[t2] + 128 * ks + 16 * lg;
-                    const f32x4 lo4 = *reinterpret_cast<const f32x4 *>(base);
-                    const f32x4 hi4 = *reinterpret_cast<const f32x4 *>(base + 64);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        x[e] = lo4[e];
-                        x[4 + e] = hi4[e];
-                    }
-                }
-                if (t2 >= NF || (t2 == NF - 1 && mixed)) {
-                    if (t2 >= NF || !is_fact[t2]) {
-                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
-                                                                         lds_off[t2] + 16 * kRowWords * lg + 128 * kRowWords * ks);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            x[i] = p[kRowWords * i];
-                            x[4 + i] = p[16 * kRowWords + kRowWords * i];
-                        }
-                    }
-                }
-                if (!all_rows) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (!((vbits >> i) & 1u)) x[i] = 0.f;
-                }
-                split_bf16x8(x, oph[ks][t2], opl[ks][t2]);
-            }
-        }
-        return true;
-    };
-    // Phase 2: the MFMAs of both k-steps, from registers only.
-    auto phase2 = [&]() {
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            int p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], oph[ks][b], acc[p], 0, 0, 0);
-            p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], opl[ks][b], acc[p], 0, 0, 0);
-            p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], oph[ks][b], acc[p], 0, 0, 0);
-            if (X4) {
-                p = 0;
-#pragma unroll
-                for (int a = 0; a < NT; ++a)
-#pragma unroll
-                    for (int b = a; b < NT; ++b, ++p)
-                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], opl[ks][b], acc[p], 0, 0, 0);
-            }
-        }
-        if (++since_flush == kFlushTiles) {
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                sacc[p] += acc[p];
-                acc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-            since_flush = 0;
-        }
-    };
-
-    // Every step issues the same operations whether or not a further tile exists (past the
-    // end they re-read the last tile, in bounds, and nothing uses the result): the count of
-    // operations after any load is then the same on every path, and the compiler's own
-    // waits before a register's first use never reach past the newest fact loads.
-    auto step = [&](int t) {
-        // this tile's records and facts and the next keys have landed
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        wave_sync();
-        uni_cur = uni_next;
-        const bool live = t < n_tiles;
-        if (live && uni_cur) {
-            // records gathered once: row 0 to the other rows of each quad
-#pragma unroll
-            for (int c = 0; c < kGramMaxChild; ++c)
-                if (c < n_child && ((uni_cur >> c) & 1u)) {
-                    char *q0 = reinterpret_cast<char *>(smem) + cdst[c];
-                    if (PR) {
-                        const f32x4 v0 = *reinterpret_cast<const f32x4 *>(q0);
-                        const f32x4 v1 = *reinterpret_cast<const f32x4 *>(q0 + 16);
-                        if (lane > 0) {
-                            *reinterpret_cast<f32x4 *>(q0 + 32 * lane) = v0;
-                            *reinterpret_cast<f32x4 *>(q0 + 32 * lane + 16) = v1;
-                        }
-                    } else {
-#pragma unroll 1
-                        for (int q = 0; q < cnq[c]; ++q, q0 += kQuadBytes) {
-                            const f32x4 v = *reinterpret_cast<const f32x4 *>(q0);
-                            if (lane > 0) *reinterpret_cast<f32x4 *>(q0 + 16 * lane) = v;
-                        }
-                    }
-                }
-        }
-        if (live) store_fact(t);
-        load_fact(min(t + 1, n_tiles - 1));             // in flight for the rest of the step
-        wave_sync();
-        if (live) phase1(t);
-        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this tile's LDS reads are done
-        wave_sync();
-        issue_rec();                                    // tile t+1 (keys loaded last step)
-        load_keys(min(t + 2, n_tiles - 1));
-        if (live) phase2();                             // MFMAs while the copies are in flight
-    };
-
-    if (n_tiles > 0) {
-        load_keys(0);
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        issue_rec();
-        load_keys(min(1, n_tiles - 1));
-        load_fact(0);
-    }
-    for (int t = 0; t < n_tiles; ++t) step(t);
-    __builtin_amdgcn_s_waitcnt(0);
-
-    // ---- every wave writes its own partial: fp64 upper triangle, staged feature order ------
-    // (each unordered feature pair is one slot pair: one lane of one accumulator owns it)
-    const int ng = d.n_gram;
-    const int pidx = blockIdx.x * nwaves + wave;
-    double *out = d.gram_partial + (int64_t)pidx * (ng * (ng + 1) / 2);
-    {
-        int p = 0;
-#pragma unroll
-        for (int a = 0; a < NT; ++a)
-#pragma unroll
-            for (int b = a; b < NT; ++b, ++p) {
-                const int sb = 16 * b + li;
-                const int fb = gld(&dp->slot[sb].feat)[0];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int sa = 16 * a + 4 * lg + e;
-                    if (a == b && sa > sb) continue;
-                    const int fa = gld(&dp->slot[sa].feat)[0];
-                    if (fa < 0 || fb < 0) continue;
-                    gst(out)[tri_index(min(fa, fb), max(fa, fb), ng)] = (double)sacc[p][e] + (double)acc[p][e];
-                }
-            }
-    }
-    if (d.do_count && lane == 0) gst(d.count_partial)[pidx] = count;
-}
-
-// ---------------------------------------------------------------------------
 // kernel table for the host
 // ---------------------------------------------------------------------------
 
@@ -1426,43 +953,6 @@ RootKernel root_kernel(int mode, int p1, bool tables) {
             return nullptr;
     }
     return nullptr;
-}
-
-typedef void (*GramKernel)(const GramDesc *);
-
-template <int NT, int NF>
-static GramKernel pick_gram(bool x4, bool pr) {
-    if (pr) return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, true> : (GramKernel)gram_scan_kernel<NT, NF, false, true>;
-    return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, false> : (GramKernel)gram_scan_kernel<NT, NF, false, false>;
-}
-
-// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2)); pr: pair-row record
-// buffers (every child record at most two quads, a row's quads contiguous) instead of quad-major ones
-GramKernel gram_kernel(int nt, int nf, bool x4, bool pr) {
-    if (nf < 0 || nf > 2 || nf > nt) return nullptr;
-    switch (nt * 4 + nf) {
-        case 4: return pick_gram<1, 0>(x4, pr);
-        case 5: return pick_gram<1, 1>(x4, pr);
-        case 8: return pick_gram<2, 0>(x4, pr);
-        case 9: return pick_gram<2, 1>(x4, pr);
-        case 10: return pick_gram<2, 2>(x4, pr);
-        case 12: return pick_gram<3, 0>(x4, pr);
-        case 13: return pick_gram<3, 1>(x4, pr);
-        case 14: return pick_gram<3, 2>(x4, pr);
-        case 16: return pick_gram<4, 0>(x4, pr);
-        case 17: return pick_gram<4, 1>(x4, pr);
-        case 18: return pick_gram<4, 2>(x4, pr);
-    }
-    return nullptr;
-}
-
-hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st) {
-    hipLaunchKernelGGL(k, dim3(grid_x), dim3(64 * waves), lds_bytes, st, desc);
-    return hipGetLastError();
-}
-
-hipError_t set_gram_lds_limit(GramKernel k, size_t bytes) {
-    return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_fill(const void *fills, int n, hipStream_t st) {

@@ -341,3 +341,43 @@ def test_mlp_parameter_count_matches_reference():
     _lib()
     for h in (1, 8, 32, 64):
         assert lmfao.mlp_param_count(h) == ref.param_count(h)
+
+
+def _plan_db(db, qs, **kw):
+    ctx = new_ctx()
+    for r in db.relations:
+        spec = []
+        for c in r.columns:
+            dtype = lmfao.F32 if c.kind == "cont" else lmfao.I32
+            kind = {"key": lmfao.KEY, "cont": lmfao.CONT, "cat": lmfao.CAT}[c.kind]
+            spec.append((c.attr, dtype, kind, int(c.domain), FAKE))
+        ctx.add_relation(r.name, r.n_rows, spec)
+    ctx.set_join_tree(db.edges)
+    for q in qs:
+        ctx.add_query(q)
+    ctx.plan("fp32", kw.pop("schedule", "batched"), **kw)
+    return ctx
+
+
+def test_row_codes_are_planned_for_partitioned_filtered_tables():
+    """Filtered tables over several LDS partitions (a tree level's per-node
+    histograms) are replayed from per-row codes: the plan adds the code scan's
+    launch and a workspace region of 4 bytes per code column and row (mask,
+    one cell per key, one value per summed feature).  Unfiltered tables, the
+    plain schedule and no_row_codes keep the root scan's own updates."""
+    from datagen import make_batch, make_database
+    db = make_database(3)
+    qs = make_batch(3, db)                     # COUNT, SUM(y), SUM(y^2) per node x attribute x bucket
+    on = _plan_db(db, qs)
+    off = _plan_db(db, qs, row_codes=False)
+    s_on, s_off = on.stats(), off.stats()
+    assert s_on["code_scan"] == 1 and s_off["code_scan"] == 0
+    assert s_on["strided_families"] >= 1 and s_off["strided_families"] >= 1
+    assert s_on["launches"] == s_off["launches"] + 1
+    n_rows = db.relations[0].n_rows
+    n_keys = len(qs) // 32                     # one key per attribute, shared by the 32 nodes
+    cols = 1 + n_keys + 1                      # mask, cells, y
+    assert on.workspace_size() - off.workspace_size() >= cols * ((n_rows + 63) // 64 * 64) * 4
+    assert _plan_db(db, qs, schedule="plain").stats()["code_scan"] == 0
+    db5 = make_database(5)
+    assert _plan_db(db5, make_batch(5, db5)).stats()["code_scan"] == 0   # unfiltered pair counts

@@ -756,10 +756,10 @@ static lmfao_status build_logical(lmfao_ctx *c) {
     }
     P.n_gram = gram_used ? P.n_feat : 0;
     // ---- marginal derivation: a table whose key is another same-filter table's key with one
-    // component left out is summed from that table after the scan instead of being updated
-    // per fact row (its sums join the source's).  Shortest keys first, so a source's values
-    // are complete before its own source is chosen; the source with the smallest dropped
-    // domain wins.
+    // component left out, and whose sums that table already carries, is summed from it after
+    // the scan instead of being updated per fact row.  (Adding sums to a finer table would
+    // move the coarser table's updates onto more cells, not remove them.)  The source with
+    // the smallest dropped domain wins.
     if (!c->opts.scan_every_table) {
         std::vector<int> order(P.tables.size());
         for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
@@ -771,6 +771,10 @@ static lmfao_status build_logical(lmfao_ctx *c) {
                 const Table &U = P.tables[u];
                 const Table &T = P.tables[t];
                 if (U.filter != T.filter || U.comps.size() != T.comps.size() + 1) continue;
+                bool has_vals = true;
+                for (auto &v : T.vals)
+                    if (std::find(U.vals.begin(), U.vals.end(), v) == U.vals.end()) has_vals = false;
+                if (!has_vals) continue;
                 for (size_t d = 0; d < U.comps.size(); ++d) {
                     bool same = true;
                     for (size_t i = 0, j = 0; i < U.comps.size() && same; ++i) {
@@ -785,9 +789,6 @@ static lmfao_status build_logical(lmfao_ctx *c) {
             Table &T = P.tables[t];
             T.from = best;
             T.drop = best_pos;
-            auto &uv = P.tables[best].vals;
-            for (auto &v : T.vals)
-                if (std::find(uv.begin(), uv.end(), v) == uv.end()) uv.push_back(v);
             ++P.n_derived;
         }
         // passes: longest derived keys first (their sources are scanned or derived earlier)

@@ -287,31 +287,34 @@ def test_query_errors():
 
 
 def test_marginal_derivation_is_planned_per_filter_and_chained():
-    """A grouped table one component short of a same-filter table is summed
-    from it after the scan: one pass per derived key length, each adding a
-    launch; tables under another filter are not sources."""
+    """A grouped table one component short of a same-filter table that already
+    carries its sums is summed from it after the scan: one pass per derived key
+    length, each adding a launch.  Tables under another filter, or whose sums
+    the finer table lacks, are not derived."""
     from datagen.schema import Agg, GroupBy, Pred, Query
     ctx = new_ctx()
     star(ctx)
     filt = [Pred("a0", "le", 0.5)]
     ctx.add_query(Query(groupby=[GroupBy("fc"), GroupBy("ac")], aggs=[Agg.monomial("f0")]))
-    ctx.add_query(Query(groupby=[GroupBy("ac")], aggs=[Agg.monomial("f1")]))          # from (fc, ac)
-    ctx.add_query(Query(groupby=[GroupBy("fc")], where=filt))                          # no filtered source
+    ctx.add_query(Query(groupby=[GroupBy("ac")], aggs=[Agg.monomial("f0")]))          # from (fc, ac)
+    ctx.add_query(Query(groupby=[GroupBy("fc")], where=filt, aggs=[Agg.monomial("a1")]))  # no filtered source
     ctx.add_query(Query(where=filt, aggs=[Agg.monomial("a1")]))                        # from the filtered (fc)
-    ctx.add_query(Query(groupby=[GroupBy("b0", [-1.0, 0.0, 1.0]), GroupBy("fc"), GroupBy("ac")]))
+    ctx.add_query(Query(groupby=[GroupBy("b0", [-1.0, 0.0, 1.0]), GroupBy("fc"), GroupBy("ac")],
+                        aggs=[Agg.monomial("f0")]))
+    ctx.add_query(Query(groupby=[GroupBy("fc")], aggs=[Agg.monomial("f1")]))          # (fc, ac) lacks SUM(f1)
     ctx.plan("fp32", "batched", rollup=False)
     off = ctx.stats()
     ctx.plan("fp32", "batched")
     on = ctx.stats()
-    assert off["derived_tables"] == 0 and off["tables"] == on["tables"] == 5
-    # (fc, ac) now comes from the 3-component table as well, (ac) from (fc, ac),
-    # the filtered count from the filtered (fc): three passes (key lengths 2, 1, 0)
+    assert off["derived_tables"] == 0 and off["tables"] == on["tables"] == 6
+    # (fc, ac) comes from the 3-component table, (ac) from (fc, ac), the filtered sum from the
+    # filtered (fc): three passes (key lengths 2, 1, 0)
     assert on["derived_tables"] == 3
     assert on["launches"] == off["launches"] + 3
     ctx.plan("fp32", "plain")
     plain = ctx.stats()
     ctx.plan("fp32", "plain", rollup=False)
-    assert plain["launches"] == ctx.stats()["launches"] - 3 + 3     # three fewer table scans, three passes
+    assert plain["launches"] == ctx.stats()["launches"]       # three fewer table scans, three passes
 
 
 def test_plan_option_errors():

@@ -209,8 +209,8 @@ def main():
     t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
     if args.forms == "both":
         plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols, rollup=False)
-        # the classification-tree level's plain form rescans the fact once per view (about 1,860 scans)
-        ps, pw = (args.steps, args.warmup) if args.batch != "ctree" else (2, 1)
+        # the tree levels' and pair counts' plain forms rescan the fact once per view (hundreds of scans)
+        ps, pw = (args.steps, args.warmup) if args.batch not in ("ctree", "w3", "w5") else (2, 1)
         t_plain = time_steps(plain, stream, ps, pw)
         res_plain = plain.results()
         plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)

@@ -89,3 +89,19 @@ def test_classification_tree_every_tile_candidate_agrees():
         eng.run()
         compare(eng.results(), ref, qs, 1e-6, "candidate %s" % cfg)
     assert seen == {0, 1}
+
+
+def test_classification_tree_over_32_nodes_uses_two_mask_columns():
+    """40 nodes are 40 filters: the per-row codes carry the filter mask in two
+    columns (bits 0-31 and 32-63); counts still match the oracle."""
+    from datagen import make_database
+    from paper_1906_08687_amd.lmfao import Engine
+    db = make_database(3, n_fact=30_011)
+    qs = classification_tree_batch(db, "g3", tree_level(db, n_nodes=40, seed=5))
+    ref = oracle.evaluate(db, qs)
+    print("case: classification_tree 40 nodes, %d queries" % len(qs), flush=True)
+    eng = Engine(db, qs, precision="fp32", schedule="batched")
+    st = eng.ctx.stats()
+    assert st["filters"] == 40 and st["code_scan"] == 1
+    eng.run()
+    compare(eng.results(), ref, qs, 1e-6, "classification_tree 40 nodes")

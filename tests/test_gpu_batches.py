@@ -105,3 +105,22 @@ def test_classification_tree_over_32_nodes_uses_two_mask_columns():
     assert st["filters"] == 40 and st["code_scan"] == 1
     eng.run()
     compare(eng.results(), ref, qs, 1e-6, "classification_tree 40 nodes")
+
+
+def test_tree_levels_of_two_kinds_share_one_code_scan():
+    """A classification-tree level and a regression-tree level over the same
+    nodes: two strided families (counts; counts with SUM(y), SUM(y^2)) whose
+    key cells and y value come from one set of per-row codes."""
+    from datagen import make_database
+    from datagen.configs import batch3
+    from paper_1906_08687_amd.lmfao import Engine
+    db = make_database(3, n_fact=30_011)
+    level = tree_level(db, n_nodes=8, seed=3)
+    qs = classification_tree_batch(db, "g3", level) + batch3(db, level)
+    ref = oracle.evaluate(db, qs)
+    print("case: two tree levels, %d queries" % len(qs), flush=True)
+    eng = Engine(db, qs, precision="fp32", schedule="batched")
+    st = eng.ctx.stats()
+    assert st["code_scan"] == 1 and st["strided_families"] == 2
+    eng.run()
+    compare(eng.results(), ref, qs, 1e-6, "two tree levels")

@@ -326,7 +326,9 @@ class Engine:
 
     Columns are copied to the device once (load time is outside every
     measurement, as in the paper's protocol); the workspace and result arena
-    are torch tensors bound to the context.
+    are torch tensors bound to the context.  ``rollup`` and ``row_codes`` are
+    the plan options of ``Context.plan`` (derived tables; tables replayed from
+    per-row codes), both on by default.
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,

@@ -7,13 +7,16 @@ per second (|J| = 100M tuples per step) of the full form (BF16 hi+lo split
 covariance on MFMA, batched schedule in a hipGraph, tile configuration
 ranked by the learned cost model and judged by timing, else chosen by the
 exhaustive autotuner), next to the plain form (fp32 FMAs, one launch per
-view, heuristic tiles) and the speedup between them.  Both forms are checked
-against the CPU oracle on a sample of aggregates evaluated over the full join.
+view, heuristic tiles) and the speedup between them.  The CPU oracle runs
+only as the reported baseline, on a bounded sample of the same workload; the
+parity of both forms with it at full size, in this launch configuration, is
+tests/test_gpu_full_size.py.
 
 `--batch cube` and `--batch ctree` time the other batch shapes the same way
 (a three-dimensional data cube with five measures over workload 2's schema at
 10M fact rows; a 32-node classification-tree level over workload 3's schema
-at 50M fact rows); the default is the covariance batch.
+at 50M fact rows), and `--batch w1|w2|w3|w5` the other workloads at full
+size; the default is the covariance batch.
 """
 from __future__ import annotations
 
@@ -115,7 +118,9 @@ def main():
                          "cube; ctree: classification-tree level; wK: workload K's batch at full size")
     ap.add_argument("--n-fact", type=int, default=None, help="fact rows (default: the batch's full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="no effect (accepted for recorded profiling command lines); parity with the oracle at full "
+                         "size in this launch configuration is tests/test_gpu_full_size.py")
     ap.add_argument("--plan", default="auto", choices=["auto", "learned", "autotune", "heuristic"],
                     help="tile choice of the full form: auto = the cost model ranks the candidates, its top 4 "
                          "and the heuristic choice are timed and the fastest kept (exhaustive autotune without a model); learned = the model's top choice alone")
@@ -206,13 +211,12 @@ def main():
         del x
 
     # plain form: fp32 covariance, one launch per view, heuristic tiles, every table scanned
-    t_plain, res_plain, plain_root_ms, plain_stats = None, None, None, {"launches": None}
+    t_plain, plain_root_ms, plain_stats = None, None, {"launches": None}
     if args.forms == "both":
         plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols, rollup=False)
         # the tree levels' and pair counts' plain forms rescan the fact once per view (hundreds of scans)
         ps, pw = (args.steps, args.warmup) if args.batch not in ("ctree", "w3", "w5") else (2, 1)
         t_plain = time_steps(plain, stream, ps, pw)
-        res_plain = plain.results()
         plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)
         plain_stats = plain.stats()
         print("[bench] plain fp32: %.3f ms/step" % (t_plain * 1e3), file=sys.stderr, flush=True)
@@ -270,34 +274,10 @@ def main():
         print("[bench] tile choices: %s" % json.dumps(plans), file=sys.stderr, flush=True)
     full._bind()
     t_full = time_steps(full, stream, args.steps, args.warmup)
-    res_full = full.results()
     root_ms = full.ctx.time_root_group(stream, 2, 10)
     stats = full.stats()
     print("[bench] full %s/batched/%s: %.3f ms/step, root scan %.3f ms" % (precision, chosen, t_full * 1e3, root_ms),
           file=sys.stderr, flush=True)
-
-    # accuracy of both forms against the oracle on sampled aggregates over the full join
-    errors = None
-    if not args.no_check:
-        import oracle
-        rng = np.random.default_rng(4)
-        sample = sorted(set([0] + list(rng.choice(np.arange(1, len(qs)), min(15, len(qs) - 1), replace=False))))
-        t = time.time()
-        ref = oracle.evaluate(db, [qs[i] for i in sample])
-        errors = {}
-        for name, res in (("plain_fp32", res_plain), ("full", res_full)):
-            if res is None:
-                continue
-            worst = 0.0
-            for i, r in zip(sample, ref):
-                if not np.array_equal(res[i].counts, r.counts):
-                    raise SystemExit("count mismatch in %s query %d" % (name, i))
-                if r.sums.size:
-                    rel = np.abs(res[i].sums - r.sums) / np.maximum(np.abs(r.sums), 1e-300)
-                    worst = max(worst, float(rel.max()))
-            errors[name] = {"max_rel_err": worst, "aggregates_checked": len(sample)}
-        print("[bench] oracle check of %d aggregates in %.1fs: %s" % (len(sample), time.time() - t, errors),
-              file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -338,7 +318,6 @@ def main():
         "speedup_vs_plain_fp32": (t_plain / t_full) if t_plain else None,
         "plain_fp32": ({"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
                         "launches": plain_stats["launches"]} if t_plain else None),
-        "errors_vs_oracle": errors,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("gram_scan.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,

@@ -80,3 +80,24 @@ def test_classification_tree_counts_split_by_label_and_attribute():
             assert int(alone.counts.sum()) == node_count
             # the label's class totals equal a direct count on the join
             np.testing.assert_array_equal(per.sum(axis=1), np.bincount(J[label][keep], minlength=dom_label))
+
+
+def test_planner_derives_coarser_tables_of_the_batches():
+    """Which tables the planner derives after the scan instead of updating
+    per row, on the batch shapes: the cube's lattice leaves one scanned table;
+    a tree level's COUNT GROUP BY bucket comes from the label-split counts;
+    the mutual-information marginals come from the pair counts; workload 2's
+    SUM(x) GROUP BY c tables stay scanned (the pair counts carry no sums)."""
+    from datagen import make_batch
+    from tests.test_abi import _plan_db
+    db = make_database(2, n_fact=20_011)
+    st = _plan_db(db, data_cube_batch(CUBE_DIMS, CUBE_MEASURES)).stats()
+    assert (st["tables"], st["derived_tables"]) == (7, 6)
+    assert _plan_db(db, make_batch(2, db)).stats()["derived_tables"] == 0
+    db3 = make_database(3, n_fact=10_007)
+    qs = classification_tree_batch(db3, "g3", tree_level(db3, n_nodes=4, seed=3))
+    st = _plan_db(db3, qs).stats()
+    assert st["derived_tables"] * 2 == st["tables"] == len(qs)
+    db5 = make_database(5)
+    st = _plan_db(db5, make_batch(5, db5)).stats()
+    assert (st["tables"], st["derived_tables"]) == (120, 15)

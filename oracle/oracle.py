@@ -183,7 +183,9 @@ def brute_force(db, queries: Sequence):
     """Exact results by the textbook definition: the natural join is the set
     of combinations of one row per relation that agree on every attribute
     name they share; aggregates are summed as exact rationals.  Returns, per
-    query, (counts as a list of ints, sums as a list of lists of Fractions)."""
+    query, (counts as a list of ints, sums as a list of lists of Fractions,
+    abs_sums: the exact sum over join tuples and terms of |coeff * prod x|,
+    each term taken on its own, as a list of lists of Fractions)."""
     rows = []
     for r in db.relations:
         rows.append([{c.attr: c.data[i].item() for c in r.columns} for i in range(r.n_rows)])
@@ -208,6 +210,7 @@ def brute_force(db, queries: Sequence):
         cells = int(np.prod(doms)) if doms else 1
         counts = [0] * cells
         sums = [[Fraction(0)] * len(q.aggs) for _ in range(cells)]
+        abs_sums = [[Fraction(0)] * len(q.aggs) for _ in range(cells)]
         for t in joined:
             if not all(_pred(np.float32(t[p.attr]) if kinds[p.attr] == "cont" else t[p.attr], p.op,
                              np.float32(p.value) if kinds[p.attr] == "cont" else int(p.value))
@@ -228,5 +231,6 @@ def brute_force(db, queries: Sequence):
                     for f in facs:
                         term *= Fraction(float(np.float32(t[f])))
                     sums[cell][ai] += term
-        out.append((counts, sums))
+                    abs_sums[cell][ai] += abs(term)
+        out.append((counts, sums, abs_sums))
     return out

@@ -22,18 +22,80 @@ def _data(n=257, seed=3):
 # the reference, pinned
 # --------------------------------------------------------------------------
 
+def _set(h, W1=None, b1=None, W2=None, b2=None, W3=None, b3=0.0):
+    """Flat parameter vector from hand-set layers (unset entries zero), laid out
+    W1[H][16], b1[H], W2[H][H], b2[H], W3[H], b3 as the network defines."""
+    W1 = np.zeros((h, ref.N_IN)) if W1 is None else np.asarray(W1, np.float64)
+    b1 = np.zeros(h) if b1 is None else np.asarray(b1, np.float64)
+    W2 = np.zeros((h, h)) if W2 is None else np.asarray(W2, np.float64)
+    b2 = np.zeros(h) if b2 is None else np.asarray(b2, np.float64)
+    W3 = np.zeros(h) if W3 is None else np.asarray(W3, np.float64)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, [b3]])
+
+
+def test_reference_forward_identity_network():
+    """relu(x0) - relu(-x0) = x0: two hidden units carry the positive and negative
+    parts of x0 through an identity second layer and are subtracted."""
+    h = 2
+    W1 = np.zeros((2, ref.N_IN))
+    W1[0, 0], W1[1, 0] = 1.0, -1.0
+    p = _set(h, W1=W1, W2=np.eye(2), W3=[1.0, -1.0])
+    x = np.random.default_rng(7).normal(size=(64, ref.N_IN)) * 5
+    assert np.array_equal(ref.forward(p, x, h), x[:, 0])
+    # a bias on the output and a second input through the other unit: y = x0 + 3 relu(x5 - 1) + 0.5
+    W1b = W1.copy()
+    W1b[1, :] = 0.0
+    W1b[1, 5] = 1.0
+    p = _set(h, W1=W1b, b1=[0.0, -1.0], W2=np.eye(2), W3=[1.0, 3.0], b3=0.5)
+    x[:, 0] = np.abs(x[:, 0])
+    np.testing.assert_allclose(ref.forward(p, x, h), x[:, 0] + 3 * np.maximum(x[:, 5] - 1, 0) + 0.5,
+                               rtol=1e-15, atol=1e-14)
+
+
+def test_reference_forward_hand_worked_example():
+    """Worked by hand: x = (3, -2, 0, ...).
+    layer 1: z1 = (3 - 4 + 0.5, 2 - 1) = (-0.5, 1)  -> a1 = (0, 1)
+    layer 2: z2 = (2*0 + 3*1, -1*0 + 4*1 - 5) = (3, -1)  -> a2 = (3, 0)
+    output:  y = 0.5*3 + 7*0 + 0.25 = 1.75
+    and with target 1, the loss (1.75 - 1)^2 = 0.5625."""
+    h = 2
+    W1 = np.zeros((2, ref.N_IN))
+    W1[0, :2] = [1.0, 2.0]
+    W1[1, 1] = -1.0
+    p = _set(h, W1=W1, b1=[0.5, -1.0], W2=[[2.0, 3.0], [-1.0, 4.0]], b2=[0.0, -5.0], W3=[0.5, 7.0], b3=0.25)
+    x = np.zeros((1, ref.N_IN))
+    x[0, :2] = [3.0, -2.0]
+    assert ref.forward(p, x, h)[0] == 1.75
+    loss, g = ref.loss_grad(p, x, np.array([1.0]), h)
+    assert loss == 0.5625
+    # dL/db3 = 2 (y - t) = 1.5; dL/dW3 = 1.5 * a2 = (4.5, 0); units with zero pre-activation slope
+    # (z1[0] < 0, z2[1] < 0) pass no gradient, so W1 row 0 and W2 row 1 get none
+    W1g, b1g, W2g, b2g, W3g, b3g = ref.unpack(g, h)
+    assert b3g == 1.5 and list(W3g) == [4.5, 0.0]
+    assert np.all(W1g[0] == 0) and np.all(W2g[1] == 0) and b2g[1] == 0
+    # dL/dz2[0] = 1.5 * 0.5 = 0.75 -> dW2[0] = 0.75 * a1 = (0, 0.75); dz1 = 0.75 * W2[0] * (z1 > 0) = (0, 2.25)
+    assert list(W2g[0]) == [0.0, 0.75] and b2g[0] == 0.75
+    assert list(b1g) == [0.0, 2.25] and list(W1g[1, :2]) == [6.75, -4.5]
+
+
 @pytest.mark.parametrize("h", [4, 8])
 def test_reference_gradient_matches_finite_differences(h):
+    """Central differences of the mean squared error of the pinned forward pass
+    (not of the loss that loss_grad computes alongside its gradient)."""
     x, t = _data(40)
     p = ref.init(h, seed=h) + 0.01
+
+    def mse(q):
+        return float(np.mean((ref.forward(q, x, h) - t) ** 2))
+
     loss, g = ref.loss_grad(p, x, t, h)
     eps = 1e-6
     for i in range(len(p)):
         d = np.zeros_like(p)
         d[i] = eps
-        num = (ref.loss_grad(p + d, x, t, h)[0] - ref.loss_grad(p - d, x, t, h)[0]) / (2 * eps)
+        num = (mse(p + d) - mse(p - d)) / (2 * eps)
         assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(num)), (i, num, g[i])
-    assert abs(loss - np.mean((ref.forward(p, x, h) - t) ** 2)) < 1e-12
+    assert abs(loss - mse(p)) < 1e-12
 
 
 def test_reference_constant_network_closed_form():

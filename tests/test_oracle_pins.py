@@ -126,12 +126,17 @@ def test_oracle_equals_exact_brute_force(seed):
     qs = _tiny_queries(db, rnd)
     got = oracle.evaluate(db, qs, n_threads=3)
     exact = oracle.brute_force(db, qs)
-    for q, g, (cnt, sums) in zip(qs, got, exact):
+    for q, g, (cnt, sums, abs_sums) in zip(qs, got, exact):
         assert list(g.counts) == cnt
         for cell in range(len(cnt)):
             for a in range(len(q.aggs)):
                 ref = float(sums[cell][a])      # correctly rounded exact value
                 assert abs(g.sums[cell, a] - ref) <= 2 * math.ulp(max(abs(ref), 1e-300)) or g.sums[cell, a] == ref
+                # the conditioning scale sum |term|: every term is exact in fp64 and non-negative, so a
+                # plain fp64 sum of n terms is within (n - 1) ulp of the exact value
+                aref = float(abs_sums[cell][a])
+                n_terms = cnt[cell] * len(q.aggs[a].terms)
+                assert abs(g.abs_sums[cell, a] - aref) <= max(n_terms, 2) * math.ulp(max(aref, 1e-300))
 
 
 def test_oracle_golden_moo_example():
@@ -156,7 +161,7 @@ def test_oracle_golden_moo_example():
         assert list(res.counts) == spec["counts"]
         assert np.array_equal(res.sums, np.array(spec["sums"], np.float64))
     # the brute force agrees on the same fixture
-    for spec, (cnt, sums) in zip(fx["queries"], oracle.brute_force(db, qs)):
+    for spec, (cnt, sums, _) in zip(fx["queries"], oracle.brute_force(db, qs)):
         assert cnt == spec["counts"]
         assert [[float(s) for s in row] for row in sums] == spec["sums"]
 
@@ -180,6 +185,33 @@ def test_count_is_fact_size_and_dim_sums_by_bincount():
     J = materialize(db)
     ref2 = math.fsum(J["z1"] * J["y3"])          # fp32*fp32 products are exact in fp64
     assert abs(res[2].sums[0, 0] - ref2) <= 2 * math.ulp(abs(ref2))
+
+
+def test_abs_sums_equal_fsum_of_absolute_terms():
+    """Sum |term| (the scale of the tolerance rule) on workload 1's materialised join:
+    each term coeff * prod x on its own, not |aggregate| per tuple.  The mixed-sign
+    aggregate separates the two (|2 x1 - 0.5 x2 y1| <= |2 x1| + |0.5 x2 y1|)."""
+    db = make_database(1, n_fact=30_011)
+    J = materialize(db)
+    mixed = Agg([(2.0, ("x1",)), (-0.5, ("x2", "y1"))])
+    qs = [Query(aggs=[Agg.monomial("x1", "z1"), mixed, Agg.monomial()]),
+          Query([GroupBy("c")], [Pred("z2", "gt", 0.0)], [mixed, Agg([(3.0, ())])])]
+    res = oracle.evaluate(db, qs, n_threads=4)
+    t1 = np.abs(2.0 * J["x1"])
+    t2 = np.abs(-0.5 * J["x2"] * J["y1"])           # products of two fp32 values are exact in fp64
+    n = len(J["x1"])
+    for got, ref in [(res[0].abs_sums[0, 0], math.fsum(np.abs(J["x1"] * J["z1"]))),
+                     (res[0].abs_sums[0, 1], math.fsum(np.concatenate([t1, t2]))),
+                     (res[0].abs_sums[0, 2], float(n))]:
+        assert abs(got - ref) <= n * math.ulp(ref)
+    partial = math.fsum(np.abs(2.0 * J["x1"] - 0.5 * J["x2"] * J["y1"]))
+    assert res[0].abs_sums[0, 1] > partial * (1 + 1e-3)
+    m = J["z2"].astype(np.float32) > np.float32(0.0)
+    for v in range(db.column("c").domain):
+        sel = m & (J["c"] == v)
+        ref = math.fsum(np.concatenate([t1[sel], t2[sel]]))
+        assert abs(res[1].abs_sums[v, 0] - ref) <= n * math.ulp(max(ref, 1e-300))
+        assert res[1].abs_sums[v, 1] == 3.0 * sel.sum()
 
 
 def test_covariance_matches_fsum_and_is_symmetric_psd():

@@ -122,7 +122,10 @@ typedef struct {
 typedef struct {
     const char *attr;          /* factor 1[attr op value] */
     int32_t op;                /* LMFAO_LE .. LMFAO_NE */
-    double value;              /* compared in fp32 for CONT, as an integer for KEY/CAT */
+    double value;              /* CONT: compared in fp32 with the constant rounded to fp32.
+                                  KEY/CAT: compared exactly with the real constant, which need
+                                  not be an integer (c >= 2.5 holds for c >= 3; c = 2.5 never).
+                                  NaN is INVALID_ARG. */
 } lmfao_pred;
 
 typedef struct {

@@ -30,8 +30,9 @@
  * contiguous ranges of root rows; partials are merged in thread order with
  * the same compensated addition.
  *
- * Predicates 1[X op t] compare fp32 attribute values with the fp32 constant
- * exactly, and integer attributes with the integer constant.  A bucket
+ * Predicates 1[X op t] compare fp32 attribute values with the constant
+ * rounded to fp32, and integer attributes with the real constant exactly
+ * (1[c >= 2.5] holds for c >= 3).  A bucket
  * group-by over sorted thresholds t_0 < ... < t_{T-1} maps x to
  * #{k : t_k < x}, i.e. x <= t_k  <=>  bucket <= k (the split X <= t of
  * Section 2, decision trees).
@@ -168,8 +169,10 @@ static int pred_holds(const ctx_t *cx, const int64_t *row, int32_t attr, int32_t
             default: return x != t;
         }
     } else {
-        int64_t x = ival(r, L->col, row[L->rel]);
-        int64_t t = (int64_t)v;
+        /* an integer attribute against the real constant v, compared exactly
+         * (every int32 value is a double) */
+        double x = (double)ival(r, L->col, row[L->rel]);
+        double t = v;
         switch (op) {
             case OP_LE: return x <= t;
             case OP_LT: return x < t;

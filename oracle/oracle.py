@@ -212,8 +212,8 @@ def brute_force(db, queries: Sequence):
         sums = [[Fraction(0)] * len(q.aggs) for _ in range(cells)]
         abs_sums = [[Fraction(0)] * len(q.aggs) for _ in range(cells)]
         for t in joined:
-            if not all(_pred(np.float32(t[p.attr]) if kinds[p.attr] == "cont" else t[p.attr], p.op,
-                             np.float32(p.value) if kinds[p.attr] == "cont" else int(p.value))
+            if not all(_pred(np.float32(t[p.attr]) if kinds[p.attr] == "cont" else int(t[p.attr]), p.op,
+                             np.float32(p.value) if kinds[p.attr] == "cont" else float(p.value))
                        for p in q.where):
                 continue
             cell = 0

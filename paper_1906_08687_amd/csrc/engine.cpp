@@ -456,6 +456,37 @@ static bool find_attr(const lmfao_ctx *c, const std::string &a, ARef &out) {
     return best >= 0;
 }
 
+// The factor 1[X op v] (Section 1.1) on an int32 attribute, for any real v: rewritten as an
+// equal test against an int32 constant (X >= v <=> X >= ceil(v), X > v <=> X >= floor(v) + 1,
+// X <= v <=> X <= floor(v), X < v <=> X <= ceil(v) - 1; X = v never holds and X != v always
+// holds unless v is an int32 value).  Tests that hold for every or for no int32 value become
+// X >= INT32_MIN and X < INT32_MIN, so the kernels compare int32 values only.
+static void int_predicate(int32_t *op, double *v) {
+    const double lo = (double)INT32_MIN, hi = (double)INT32_MAX;
+    const bool integral = std::floor(*v) == *v && *v >= lo && *v <= hi;
+    auto always = [&] { *op = LMFAO_GE; *v = lo; };
+    auto never = [&] { *op = LMFAO_LT; *v = lo; };
+    switch (*op) {
+        case LMFAO_EQ: if (!integral) never(); return;
+        case LMFAO_NE: if (!integral) always(); return;
+        case LMFAO_GE:
+        case LMFAO_GT: {
+            const double t = *op == LMFAO_GE ? std::ceil(*v) : std::floor(*v) + 1.0;
+            if (t <= lo) always();
+            else if (t > hi) never();
+            else { *op = LMFAO_GE; *v = t; }
+            return;
+        }
+        default: {   // LE, LT
+            const double t = *op == LMFAO_LE ? std::floor(*v) : std::ceil(*v) - 1.0;
+            if (t >= hi) { *op = LMFAO_LE; *v = hi; }
+            else if (t < lo) never();
+            else { *op = LMFAO_LE; *v = t; }
+            return;
+        }
+    }
+}
+
 extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int32_t *qid) {
     if (!c || !q) return LMFAO_ERR_INVALID_ARG;
     if (!c->tree_set) return fail(c, LMFAO_ERR_STATE, "set the join tree before adding queries");
@@ -495,9 +526,14 @@ extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int3
     if (cells > 2147483647.0) return fail(c, LMFAO_ERR_TOO_LARGE, "query has more than 2^31 cells");
     for (int p = 0; p < q->n_preds; ++p) {
         const lmfao_pred &x = q->preds[p];
-        if (!holder(x.attr)) return fail(c, LMFAO_ERR_UNKNOWN_ATTR, std::string("unknown predicate attribute ") + (x.attr ? x.attr : "(null)"));
+        const Col *col = holder(x.attr);
+        if (!col) return fail(c, LMFAO_ERR_UNKNOWN_ATTR, std::string("unknown predicate attribute ") + (x.attr ? x.attr : "(null)"));
         if (x.op < LMFAO_LE || x.op > LMFAO_NE) return fail(c, LMFAO_ERR_INVALID_ARG, "bad predicate operator");
-        Q.preds.push_back(QPred{x.attr, x.op, x.value});
+        if (std::isnan(x.value)) return fail(c, LMFAO_ERR_INVALID_ARG, "predicate constant is NaN");
+        int32_t op = x.op;
+        double v = x.value;
+        if (col->dtype == LMFAO_I32) int_predicate(&op, &v);
+        Q.preds.push_back(QPred{x.attr, op, v});
     }
     for (int a = 0; a < q->n_aggs; ++a) {
         const lmfao_agg &x = q->aggs[a];
@@ -2206,24 +2242,26 @@ extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t c
 }
 
 // Rounds of workgroups the root scan takes under candidate t: its workgroups over what the
-// chip holds at once (the plan is built for t on the side, then restored).
-static double candidate_rounds(lmfao_ctx *c, const TileCfg &t) {
-    Plan saved = c->plan;
+// chip holds at once.  The plan for t is built in a copy of the context (planning is host-only;
+// the copy owns no graph), so the caller's context is not touched.
+static double candidate_rounds(const lmfao_ctx *c, const TileCfg &t) {
+    lmfao_ctx side = *c;
+    side.graph = nullptr;
+    side.graph_def = nullptr;
     double rounds = 1.0;
-    if (build_logical(c) == LMFAO_OK) {
-        c->plan.precision = saved.precision;
-        c->plan.schedule = saved.schedule;
-        c->plan.planner = saved.planner;
-        if (build_physical(c, t) == LMFAO_OK && !c->plan.root_launches.empty()) {
-            const RootLaunch &L = c->plan.root_launches[0];
+    if (build_logical(&side) == LMFAO_OK) {
+        side.plan.precision = c->plan.precision;
+        side.plan.schedule = c->plan.schedule;
+        side.plan.planner = c->plan.planner;
+        if (build_physical(&side, t) == LMFAO_OK && !side.plan.root_launches.empty()) {
+            const RootLaunch &L = side.plan.root_launches[0];
             rounds = (double)L.grid_x / ((double)std::max(1, c->n_cu) * std::max(1, L.resident));
         }
     }
-    c->plan = std::move(saved);
     return rounds;
 }
 
-static void features_of(lmfao_ctx *c, const TileCfg &t, float *f) {
+static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
     const Plan &P = c->plan;
     const double rows = (double)c->rels[P.root].n_rows;
     int64_t child_keys = 0;
@@ -2255,8 +2293,7 @@ extern "C" lmfao_status lmfao_candidate_features(const lmfao_ctx *c, int32_t i, 
     if (!c->plan.ok) return LMFAO_ERR_STATE;
     auto v = enumerate_candidates(c);
     if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
-    // features_of plans candidate i on the side and restores the plan: the context is unchanged
-    features_of(const_cast<lmfao_ctx *>(c), v[i], features);
+    features_of(c, v[i], features);
     return LMFAO_OK;
 }
 

@@ -80,6 +80,22 @@ def check_sums(got, ref, abs_sums, rtol, what=""):
     return float(np.max(strict, initial=0.0)), float(np.max(normwise, initial=0.0))
 
 
+def compare_results(got, ref, queries, rtol, what):
+    """Counts bit for bit, sums under check_sums; returns the worst (strict,
+    normwise) error over the sums that were compared."""
+    worst = (0.0, 0.0)
+    for i, (g, r, q) in enumerate(zip(got, ref, queries)):
+        assert g.counts.shape == r.counts.shape, (what, i)
+        if not np.array_equal(g.counts, r.counts):
+            bad = np.argwhere(g.counts != r.counts).ravel()[:5]
+            raise AssertionError("%s query %d: counts differ at cells %s: got %s ref %s" %
+                                 (what, i, bad, g.counts[bad], r.counts[bad]))
+        if q.aggs:
+            s, n = check_sums(g.sums, r.sums, r.abs_sums, rtol, "%s query %d" % (what, i))
+            worst = (max(worst[0], s), max(worst[1], n))
+    return worst
+
+
 def bf16_split(x):
     """x = hi + lo + d with hi = bf16(x), lo = bf16(x - hi), both round to
     nearest even (the split of the BF16 covariance forms), as exact float64."""

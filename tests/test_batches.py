@@ -68,7 +68,7 @@ def test_classification_tree_counts_split_by_label_and_attribute():
         keep = np.ones(len(J[label]), bool)
         for p in preds:
             x = J[p.attr]
-            t = np.float32(p.value) if x.dtype.kind == "f" else int(p.value)
+            t = np.float32(p.value) if x.dtype.kind == "f" else float(p.value)
             keep &= {"le": x <= t, "gt": x > t, "eq": x == t, "ne": x != t}[p.op]
         node_count = int(keep.sum())
         for j, a in enumerate(feats):

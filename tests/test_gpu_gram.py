@@ -9,13 +9,14 @@ at most two quads (facts-only-tile, whole-tiles, distinct-keys, whose first
 dimension has one-quad records), quad-major otherwise.
 
 Counts are bit-exact.  Sums are checked twice:
-  * against the oracle's exact sums within the split's own error bound,
-    eps * sum|terms| with eps = 3 * 2^-16 (three products) or 2 * 2^-16
-    (four) plus fp32 accumulation (tests/test_split_bounds.py derives it;
-    these shapes put much of a sum on a few repeated dimension values,
-    where the bound is approached);
-  * against the same split computed exactly (tests/helpers.split_gram),
-    where only the fp32 accumulation differs: within 5e-6 * sum|terms|.
+  * against the oracle under the tolerance rule of tests/helpers.check_sums
+    at 1e-5, the bound for the bf16 split forms (these shapes put much of a
+    sum on a few repeated dimension values, where the split's per-product
+    error averages out least: the worst measured is 8.6e-6 for three
+    products, 5.1e-6 for four);
+  * against the same split computed exactly (tests/helpers.split_gram), a
+    check of the kernel's fp32 accumulation alone, not of parity: within
+    5e-6 * sum|terms|.
 """
 import numpy as np
 import pytest
@@ -23,11 +24,11 @@ import pytest
 import oracle
 from datagen.configs import AttrSpec, RelSpec, build_database, covariance_queries, cont_attrs
 from datagen.schema import Database, Relation
-from tests.helpers import materialize, split_gram
+from tests.helpers import check_sums, materialize, split_gram
 
 pytestmark = pytest.mark.gpu
 
-EPS = {"bf16x3": 3 * 2.0 ** -16 + 4e-6, "bf16x4": 2 * 2.0 ** -16 + 4e-6}
+RTOL = 1e-5
 ACC = 5e-6
 
 # (name, fact rows, fact features, [(dimension rows, features)], Zipf exponent of the keys)
@@ -66,7 +67,7 @@ def _check(db, qs, eng, precision, what, emulate=True):
     for i, (g, r) in enumerate(zip(got, ref)):
         assert np.array_equal(g.counts, r.counts), "%s query %d: counts differ" % (what, i)
         if qs[i].aggs:
-            _normwise(g.sums, r.sums, r.abs_sums, EPS[precision], "%s query %d vs exact" % (what, i))
+            check_sums(g.sums, r.sums, r.abs_sums, RTOL, "%s query %d vs oracle" % (what, i))
     if emulate:
         conts = cont_attrs(db)
         J = materialize(db)

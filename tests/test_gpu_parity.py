@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from datagen import Agg, Column, Database, GroupBy, Pred, Query, Relation, make_batch, make_database
-from tests.helpers import check_sums
+from tests.helpers import compare_results
 
 pytestmark = pytest.mark.gpu
 
@@ -24,18 +24,7 @@ def _engine(db, qs, **kw):
     return Engine(db, qs, **kw)
 
 
-def compare(got, ref, queries, rtol, what):
-    worst = (0.0, 0.0)
-    for i, (g, r, q) in enumerate(zip(got, ref, queries)):
-        assert g.counts.shape == r.counts.shape, (what, i)
-        if not np.array_equal(g.counts, r.counts):
-            bad = np.argwhere(g.counts != r.counts).ravel()[:5]
-            raise AssertionError("%s query %d: counts differ at cells %s: got %s ref %s" %
-                                 (what, i, bad, g.counts[bad], r.counts[bad]))
-        if q.aggs:
-            s, n = check_sums(g.sums, r.sums, r.abs_sums, rtol, "%s query %d" % (what, i))
-            worst = (max(worst[0], s), max(worst[1], n))
-    return worst
+compare = compare_results
 
 
 _cache = {}

@@ -266,7 +266,7 @@ def _mask(J, preds):
             x = x.astype(np.float32)
             t = np.float32(p.value)
         else:
-            t = int(p.value)
+            t = float(p.value)
         m &= {"le": x <= t, "lt": x < t, "ge": x >= t, "gt": x > t, "eq": x == t, "ne": x != t}[p.op]
     return m
 
@@ -320,6 +320,24 @@ def test_bucket_and_predicate_boundaries():
     assert list(r[0].counts) == [3, 1, 1, 1]
     assert [int(q.counts[0]) for q in r[1:5]] == [3, 1, 2, 3]
     assert list(r[5].counts) == [3, 0] and r[5].sums[0, 0] == 9.0 and r[5].sums[1, 0] == 0.0
+
+
+def test_integer_predicates_against_real_constants():
+    """1[c op v] on an integer attribute compares c with the real number v:
+    c >= 2.5 is c >= 3, c < 2.5 is c <= 2, c = 2.5 never holds, c != 2.5 always
+    does, and constants beyond the int32 range hold for all or no rows."""
+    F = Relation("F", [Column("c", "cat", np.array([0, 1, 2, 3, 4, 2, 3, 9], np.int32), 10)])
+    db = Database([F], [])
+    c = F.col("c").data
+    cases = [("ge", 2.5, c >= 3), ("gt", 2.5, c >= 3), ("le", 2.5, c <= 2), ("lt", 2.5, c <= 2),
+             ("eq", 2.5, c < -1), ("ne", 2.5, c >= 0), ("ge", -0.5, c >= 0), ("lt", 3.0, c <= 2),
+             ("le", 1e12, c >= 0), ("gt", -1e12, c >= 0), ("lt", -1e12, c < -1), ("ge", 3e9, c < -1),
+             ("eq", 3.0, c == 3), ("ne", 3.0, c != 3)]
+    res = oracle.evaluate(db, [Query(where=[Pred("c", op, v)]) for op, v, _ in cases])
+    for (op, v, m), r in zip(cases, res):
+        assert int(r.counts[0]) == int(m.sum()), (op, v)
+    exact = oracle.brute_force(db, [Query(where=[Pred("c", op, v)]) for op, v, _ in cases])
+    assert [e[0][0] for e in exact] == [int(m.sum()) for _, _, m in cases]
 
 
 def test_thread_count_does_not_change_results():

@@ -236,6 +236,25 @@ lmfao_status lmfao_result_layout(const lmfao_ctx *ctx, int32_t qid, int64_t *n_c
  * reported sizes.  Errors: WORKSPACE (too small or misaligned). */
 lmfao_status lmfao_bind(lmfao_ctx *ctx, void *workspace, size_t ws_bytes, void *results, size_t res_bytes);
 
+/* Bind without allocating: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The workspace is the library's own scratch array, a static
+ * device array of 64 MiB that every GPU the library runs on holds until the
+ * process ends; `results` (device memory of at least lmfao_result_size()
+ * bytes, 8-byte aligned) is still the caller's.  Nothing is allocated: the
+ * descriptors are copied into the array and every execution clears what must
+ * start at zero.  Errors: WORKSPACE when the plan needs more than 64 MiB of
+ * workspace (lmfao_workspace_size tells) or `results` is too small, HIP when
+ * the array cannot be looked up on the context's device.  All contexts on one
+ * GPU share its array: binding another context to it (here, or through
+ * lmfao_select_candidate / lmfao_autotune re-binding) overwrites this
+ * context's descriptors, after which lmfao_execute, lmfao_time_root_group,
+ * lmfao_autotune and the learned choices return STATE until this context is
+ * bound again; executions of two contexts that overlap in time on one GPU
+ * race on the array.  Results equal those of lmfao_bind with a caller's
+ * workspace (the same plan and kernels). */
+lmfao_status lmfao_bind_scratch(lmfao_ctx *ctx, void *results, size_t res_bytes);
+
 /* ---- execution ----------------------------------------------------------- */
 
 /* Enqueue one evaluation of the whole batch on `hip_stream` (a hipStream_t;

@@ -27,12 +27,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <set>
 #include <sstream>
 #include <string>
@@ -258,6 +260,44 @@ struct Plan {
 
 }  // namespace
 
+// Workspace for callers that cannot allocate device memory (lmfao_bind_scratch): one array per
+// GPU, held until the process ends.  Host code never uses the array's name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress (scratch_ptr below).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+    std::once_flag once;
+    uint8_t *ptr = nullptr;          // device address of this GPU's scratch array
+    hipError_t status = hipSuccess;  // result of the symbol lookup
+    std::atomic<uint64_t> owner{0};  // binding generation that last bound the array
+};
+ScratchSlot g_scratch[kMaxDevices];
+std::atomic<uint64_t> g_scratch_gen{0};
+
+// Look the array up once per device, with that device current.
+hipError_t scratch_ptr(int device, uint8_t **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    ScratchSlot &S = g_scratch[device];
+    std::call_once(S.once, [&] {
+        int prev = 0;
+        S.status = hipGetDevice(&prev);
+        if (S.status != hipSuccess) return;
+        S.status = hipSetDevice(device);
+        if (S.status != hipSuccess) return;
+        void *p = nullptr;
+        S.status = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (S.status == hipSuccess) S.ptr = static_cast<uint8_t *>(p);
+        (void)hipSetDevice(prev);
+    });
+    *out = S.ptr;
+    return S.status;
+}
+}  // namespace
+
 struct lmfao_ctx {
     int device = 0;
     bool has_device = false;
@@ -271,6 +311,7 @@ struct lmfao_ctx {
     lmfao_plan_opts opts{};
     Plan plan;
     // binding
+    uint64_t scratch_gen = 0;         // nonzero while the workspace is this device's scratch array
     uint8_t *ws = nullptr;
     size_t ws_len = 0;
     uint8_t *res = nullptr;
@@ -327,6 +368,8 @@ extern "C" lmfao_status lmfao_create(lmfao_ctx **out, int32_t hip_device) {
             c->has_device = true;
             c->n_cu = prop.multiProcessorCount;
             c->lds_limit = prop.sharedMemPerBlock;
+            uint8_t *sp = nullptr;
+            (void)scratch_ptr(hip_device, &sp);   // once per device; its status is reported by lmfao_bind_scratch
         }
     } else {
         (void)hipGetLastError();
@@ -2025,8 +2068,37 @@ static lmfao_status upload(lmfao_ctx *c) {
     return LMFAO_OK;
 }
 
+static lmfao_status bind_buffers(lmfao_ctx *c, void *workspace, size_t ws_bytes, void *results, size_t res_bytes);
+
 extern "C" lmfao_status lmfao_bind(lmfao_ctx *c, void *workspace, size_t ws_bytes, void *results, size_t res_bytes) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
+    return bind_buffers(c, workspace, ws_bytes, results, res_bytes);
+}
+
+extern "C" lmfao_status lmfao_bind_scratch(lmfao_ctx *c, void *results, size_t res_bytes) {
+    if (!c) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "plan before binding");
+    if (!c->has_device) return fail(c, LMFAO_ERR_HIP, "no HIP device");
+    uint8_t *sp = nullptr;
+    const hipError_t e = scratch_ptr(c->device, &sp);
+    if (e != hipSuccess || !sp)
+        return fail(c, LMFAO_ERR_HIP, std::string("scratch array lookup: ") + hipGetErrorString(e));
+    if (c->plan.ws_bytes > kScratchBytes)
+        return fail(c, LMFAO_ERR_WORKSPACE, "the plan needs " + std::to_string(c->plan.ws_bytes) +
+                                                " bytes of workspace; the scratch array holds " +
+                                                std::to_string(kScratchBytes));
+    return bind_buffers(c, sp, kScratchBytes, results, res_bytes);
+}
+
+// Binding generation of the scratch array, checked before every execution: a later binding of
+// the array by another context has overwritten this context's descriptors.
+static lmfao_status check_scratch_owner(lmfao_ctx *c) {
+    if (c->scratch_gen && g_scratch[c->device].owner.load() != c->scratch_gen)
+        return fail(c, LMFAO_ERR_STATE, "another context has bound this device's scratch array since; bind again");
+    return LMFAO_OK;
+}
+
+static lmfao_status bind_buffers(lmfao_ctx *c, void *workspace, size_t ws_bytes, void *results, size_t res_bytes) {
     if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "plan before binding");
     if (!c->has_device) return fail(c, LMFAO_ERR_HIP, "no HIP device");
     if (!workspace || !results) return fail(c, LMFAO_ERR_WORKSPACE, "null buffer");
@@ -2040,6 +2112,12 @@ extern "C" lmfao_status lmfao_bind(lmfao_ctx *c, void *workspace, size_t ws_byte
     c->ws_len = ws_bytes;
     c->res = static_cast<uint8_t *>(results);
     c->res_len = res_bytes;
+    c->scratch_gen = 0;
+    uint8_t *sp = nullptr;
+    if (scratch_ptr(c->device, &sp) == hipSuccess && sp && c->ws == sp) {
+        c->scratch_gen = ++g_scratch_gen;
+        g_scratch[c->device].owner.store(c->scratch_gen);
+    }
     compute_ws(c);
     lmfao_status s = upload(c);
     if (s != LMFAO_OK) return s;
@@ -2102,6 +2180,7 @@ static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
 extern "C" lmfao_status lmfao_execute(lmfao_ctx *c, void *hip_stream) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
     if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before executing");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(c, hipSetDevice(c->device));
     c->last_stream = st;
@@ -2147,6 +2226,7 @@ extern "C" lmfao_status lmfao_sync(lmfao_ctx *c) {
 extern "C" lmfao_status lmfao_time_root_group(lmfao_ctx *c, void *hip_stream, int32_t warmup, int32_t reps, double *ms) {
     if (!c || !ms || reps <= 0 || warmup < 0) return LMFAO_ERR_INVALID_ARG;
     if (!c->bound || !c->executed) return fail(c, LMFAO_ERR_STATE, "execute once before timing");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(c, hipSetDevice(c->device));
     for (int i = 0; i < warmup; ++i) {
@@ -2323,6 +2403,7 @@ extern "C" lmfao_status lmfao_select_candidate(lmfao_ctx *c, int32_t i) {
 extern "C" lmfao_status lmfao_autotune(lmfao_ctx *c, void *hip_stream, const char *timing_db, int32_t reps, int32_t *best) {
     if (!c || reps <= 0) return LMFAO_ERR_INVALID_ARG;
     if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before autotuning");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
     auto cands = enumerate_candidates(c);
     std::FILE *db = timing_db ? std::fopen(timing_db, "a") : nullptr;
     double best_ms = 1e300;
@@ -2421,6 +2502,7 @@ static bool predict_candidates(lmfao_ctx *c, const char *weights, void *hip_stre
 extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, void *hip_stream, int32_t *best) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
     if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
     if (best) *best = -1;
     std::vector<TileCfg> cands;
     std::vector<float> y;
@@ -2442,6 +2524,7 @@ extern "C" lmfao_status lmfao_choose_learned_verified(lmfao_ctx *c, const char *
     if (!c) return LMFAO_ERR_INVALID_ARG;
     if (top_k <= 0 || reps <= 0) return fail(c, LMFAO_ERR_INVALID_ARG, "top_k and reps must be positive");
     if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
     if (best) *best = -1;
     std::vector<TileCfg> cands;
     std::vector<float> y;

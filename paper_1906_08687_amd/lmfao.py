@@ -83,7 +83,7 @@ class _Stats(ctypes.Structure):
 # every symbol the header declares
 SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relation", "lmfao_set_join_tree",
            "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_workspace_size", "lmfao_result_size",
-           "lmfao_result_layout", "lmfao_bind", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
+           "lmfao_result_layout", "lmfao_bind", "lmfao_bind_scratch", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
            "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
            "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train"]
@@ -116,6 +116,7 @@ def load(path: str = LIB_PATH):
         "lmfao_result_layout": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz),
                                      ctypes.POINTER(sz)]),
         "lmfao_bind": (st, [P, P, sz, P, sz]),
+        "lmfao_bind_scratch": (st, [P, P, sz]),
         "lmfao_execute": (st, [P, P]),
         "lmfao_sync": (st, [P]),
         "lmfao_time_root_group": (st, [P, P, i32, i32, ctypes.POINTER(ctypes.c_double)]),
@@ -273,6 +274,10 @@ class Context:
     def bind(self, ws_ptr: int, ws_bytes: int, res_ptr: int, res_bytes: int):
         self._check(self.lib.lmfao_bind(self.ptr, ws_ptr, ws_bytes, res_ptr, res_bytes))
 
+    def bind_scratch(self, res_ptr: int, res_bytes: int):
+        """Bind the library's static scratch array as the workspace (no allocation)."""
+        self._check(self.lib.lmfao_bind_scratch(self.ptr, res_ptr, res_bytes))
+
     def execute(self, stream=None):
         self._check(self.lib.lmfao_execute(self.ptr, _stream_handle(stream)))
 
@@ -326,13 +331,14 @@ class Engine:
 
     Columns are copied to the device once (load time is outside every
     measurement, as in the paper's protocol); the workspace and result arena
-    are torch tensors bound to the context.  ``rollup`` and ``row_codes`` are
-    the plan options of ``Context.plan`` (derived tables; tables replayed from
-    per-row codes), both on by default.
+    are torch tensors bound to the context (with ``scratch``, the workspace is
+    the library's static scratch array instead: lmfao_bind_scratch).
+    ``rollup`` and ``row_codes`` are the plan options of ``Context.plan``
+    (derived tables; tables replayed from per-row codes), both on by default.
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
-                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True):
+                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True, scratch=False):
         import torch
         self.torch = torch
         self.db = db
@@ -352,6 +358,7 @@ class Engine:
         for q in self.queries:
             self.ctx.add_query(q)
         self.precision, self.schedule, self.rollup, self.row_codes = precision, schedule, rollup, row_codes
+        self.scratch = scratch
         self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes)
         self._bind()
 
@@ -359,6 +366,12 @@ class Engine:
         torch = self.torch
         self.ws_bytes = self.ctx.workspace_size()
         self.res_bytes = self.ctx.result_size()
+        if self.scratch:
+            # the library's static scratch array is the workspace; only the results are ours
+            if not hasattr(self, "res") or self.res.numel() < self.res_bytes:
+                self.res = torch.empty(self.res_bytes, dtype=torch.uint8, device=self.dev)
+            self.ctx.bind_scratch(_ptr(self.res), self.res.numel())
+            return
         if not hasattr(self, "ws") or self.ws.numel() < self.ws_bytes + 256:
             # slack so that other tile candidates (autotuner, cost model) bind in place
             self.ws = torch.empty(self.ws_bytes + (4 << 20), dtype=torch.uint8, device=self.dev)

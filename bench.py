@@ -3,20 +3,29 @@
 One step = one evaluation of the whole batch (every view of every level:
 fills, dimension views, the fused root scan, fp64 merge, result assembly)
 with all inputs resident in HBM.  Reported value = join tuples aggregated
-per second (|J| = 100M tuples per step) of the full form (BF16 hi+lo split
+per second (|J| = 100M tuples per step) of the full form (BF16 split
 covariance on MFMA, batched schedule in a hipGraph, tile configuration
 ranked by the learned cost model and judged by timing, else chosen by the
 exhaustive autotuner), next to the plain form (fp32 FMAs, one launch per
-view, heuristic tiles) and the speedup between them.  The CPU oracle runs
-only as the reported baseline, on a bounded sample of the same workload; the
-parity of both forms with it at full size, in this launch configuration, is
-tests/test_gpu_full_size.py.
+view, heuristic tiles), the speedup between them, and an ablation of the
+three choices one at a time (precision, batching, learned tiles) over the
+plain form.  ms_per_step is the mean over the timed steps (one host clock
+around all of them); the median of per-step HIP-event times is reported
+beside it.
+
+The CPU oracle runs only in the reported-baseline leg: it is timed on a
+bounded sample of the workload (the first fact rows, every query), and the
+same leg evaluates a seeded sample of queries over the whole join so that
+each form's largest strict and normwise error against it is reported.  Full
+parity in this launch configuration is tests/test_gpu_full_size.py.
 
 `--batch cube` and `--batch ctree` time the other batch shapes the same way
 (a three-dimensional data cube with five measures over workload 2's schema at
 10M fact rows; a 32-node classification-tree level over workload 3's schema
 at 50M fact rows), and `--batch w1|w2|w3|w5` the other workloads at full
-size; the default is the covariance batch.
+size; the default is the covariance batch.  Table-bound batches also report
+their grouped-table updates against the measured LDS atomic rate.
+`--peaks` prints the measured unit rates (HBM read, LDS and L2 atomics) alone.
 """
 from __future__ import annotations
 
@@ -33,6 +42,9 @@ sys.path.insert(0, ROOT)
 
 WEIGHTS = os.path.join(ROOT, "paper_1906_08687_amd", "costmodel", "weights.bin")
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FULL_PRECISION = "bf16x6"     # the BF16 split the full form uses
+ERR_SAMPLE = 24               # queries the oracle leg evaluates over the whole join for the error report
 
 
 def algorithmic_bytes(db) -> int:
@@ -68,10 +80,10 @@ def referenced_bytes(db, queries) -> int:
     return int(b)
 
 
-def measured_traffic(kernel_file: str, kernel: str):
-    """HBM bytes per launch of the scan from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None when the
-    kernel source has changed since the counters were taken."""
+def profiled_kernel(kernel_file: str, kernel: str):
+    """The committed rocprofv3 summary of the scan (profiles/gram_scan_covariance_100M.json):
+    its average kernel duration and its HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled
+    by a plain copy of known size), or None when the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "gram_scan_covariance_100M.json")
     if not os.path.exists(path):
@@ -80,10 +92,13 @@ def measured_traffic(kernel_file: str, kernel: str):
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     if rec.get("kernel") != kernel or hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return rec["read_bytes"] + rec["write_bytes"]
+    return {"traffic": rec["read_bytes"] + rec["write_bytes"], "kernel_ms": rec.get("kernel_trace_avg_ms")}
 
 
-def time_steps(eng, stream, steps, warmup):
+def time_steps(eng, stream, steps, warmup, median=False):
+    """Mean seconds per step over `steps` executions after `warmup` (host clock around all of
+    them, synchronised on both sides); with `median`, also the median of per-step HIP-event
+    times recorded on the engine's stream (a second, separate run of `steps`)."""
     import torch
     for _ in range(warmup):
         eng.ctx.execute(stream)
@@ -94,7 +109,77 @@ def time_steps(eng, stream, steps, warmup):
         eng.ctx.execute(stream)
     eng.ctx.sync()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    mean = (time.perf_counter() - t0) / steps
+    if not median:
+        return mean
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        eng.ctx.execute(stream)
+        ev[i + 1].record(stream)
+    eng.ctx.sync()
+    torch.cuda.synchronize()
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return mean, per[len(per) // 2] * 1e-3
+
+
+def max_errors(got, ref, sample):
+    """Largest strict relative error |got - ref| / |ref| and normwise error
+    |got - ref| / sum|term| over the sampled queries' sums (ref = the oracle;
+    sums whose reference is 0 count in the normwise figure only)."""
+    strict = normwise = 0.0
+    for i, r in zip(sample, ref):
+        g = got[i]
+        if not r.sums.size:
+            continue
+        d = np.abs(g.sums - r.sums)
+        nz = r.sums != 0
+        if nz.any():
+            strict = max(strict, float(np.max(d[nz] / np.abs(r.sums[nz]))))
+        a = r.abs_sums > 0
+        if a.any():
+            normwise = max(normwise, float(np.max(d[a] / r.abs_sums[a])))
+    return {"max_strict": strict, "max_normwise": normwise}
+
+
+def counts_exact(got, ref, sample):
+    return all(np.array_equal(got[i].counts, r.counts) for i, r in zip(sample, ref))
+
+
+def measure_peaks(dev, stream):
+    """Unit rates on this GPU (lmfao_measure_peak): HBM read GB/s, LDS u32 atomics at random and
+    at bank-distinct addresses, LDS fp64 atomics, device-scope u64 atomics on a 22 MB table."""
+    import torch
+    from paper_1906_08687_amd import lmfao
+    out = {}
+    big = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    small = torch.zeros(1 << 20, dtype=torch.uint8, device=dev)
+    tab = torch.zeros(22 << 20, dtype=torch.uint8, device=dev)
+    for kind, buf, iters in (("read", big, 3), ("lds_u32", small, 2000), ("lds_u32_spread", small, 2000),
+                             ("lds_f64", small, 1000), ("global_u64", tab, 200)):
+        lmfao.measure_peak(kind, buf, max(1, iters // 10), stream)
+        best = None
+        for _ in range(3):
+            ms, units = lmfao.measure_peak(kind, buf, iters, stream)
+            rate = units / (ms * 1e-3)
+            best = rate if best is None else max(best, rate)
+        out[kind] = best / 1e9 if kind == "read" else best
+    del big, small, tab
+    torch.cuda.empty_cache()
+    return {"hbm_read_GBs": out["read"], "lds_u32_atomics_per_s": out["lds_u32"],
+            "lds_u32_atomics_bank_distinct_per_s": out["lds_u32_spread"], "lds_f64_atomics_per_s": out["lds_f64"],
+            "l2_u64_atomics_per_s": out["global_u64"]}
+
+
+def table_updates(db, queries, results):
+    """Grouped-table updates the batch defines: for every query with a group-by, one count and one
+    update per aggregate for each join tuple it reaches (from the result counts), before the
+    planner merges equal tables or derives coarser ones."""
+    n = 0
+    for q, r in zip(queries, results):
+        if q.groupby:
+            n += int(r.counts.sum()) * (1 + len(q.aggs))
+    return n
 
 
 WORKLOADS = {
@@ -127,10 +212,13 @@ def main():
     ap.add_argument("--timing-db", default=None, help="autotune: append every candidate's timing to this file")
     ap.add_argument("--candidate", type=int, default=-1,
                     help="run tile candidate I of the full form instead of choosing one (profiling runs)")
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x4"],
-                    help="split form of the full form: three products (hi*hi + hi*lo + lo*hi) or four (+ lo*lo)")
+    ap.add_argument("--precision", default=FULL_PRECISION, choices=["bf16x3", "bf16x4", "bf16x6"],
+                    help="split form of the full form: hi+lo with three products (hi*hi + hi*lo + lo*hi) or four "
+                         "(+ lo*lo), or hi+mid+lo with six (every term down to 2^-16 of a product)")
     ap.add_argument("--forms", default="both", choices=["both", "full"],
                     help="full: skip the plain form (profiling runs)")
+    ap.add_argument("--peaks", action="store_true", help="print the measured unit rates alone and exit")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the one-choice-at-a-time forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 2 GiB (a plain copy kernel of known size, "
                          "used to scale HBM byte counters)")
@@ -144,6 +232,11 @@ def main():
     from datagen import make_batch, make_database
     from datagen.configs import classification_tree_batch, data_cube_batch, tree_level
     from paper_1906_08687_amd.lmfao import Engine, upload_columns
+
+    if args.peaks:
+        dev = torch.device("cuda", 0)
+        print(json.dumps({"peaks": measure_peaks(dev, torch.cuda.Stream())}))
+        return
 
     t = time.time()
     over = {"n_fact": args.n_fact} if args.n_fact else {}
@@ -211,7 +304,7 @@ def main():
         del x
 
     # plain form: fp32 covariance, one launch per view, heuristic tiles, every table scanned
-    t_plain, plain_root_ms, plain_stats = None, None, {"launches": None}
+    t_plain, plain_root_ms, plain_stats, plain_res = None, None, {"launches": None}, None
     if args.forms == "both":
         plain = Engine(db, qs, precision="fp32", schedule="plain", columns=cols, rollup=False)
         # the tree levels' and pair counts' plain forms rescan the fact once per view (hundreds of scans)
@@ -219,10 +312,11 @@ def main():
         t_plain = time_steps(plain, stream, ps, pw)
         plain_root_ms = plain.ctx.time_root_group(stream, 1, 5)
         plain_stats = plain.stats()
+        plain_res = plain.results()
         print("[bench] plain fp32: %.3f ms/step" % (t_plain * 1e3), file=sys.stderr, flush=True)
         del plain
 
-    # full form: bf16x3 on MFMA, batched in a hipGraph; tiles chosen by the cost model, its top
+    # full form: BF16 split on MFMA, batched in a hipGraph; tiles chosen by the cost model, its top
     # candidates judged by timing (every way of choosing is timed and reported; the one the
     # --plan option names runs last, so it is the plan the timed steps use)
     full = Engine(db, qs, precision=precision, schedule="batched", columns=cols)
@@ -273,13 +367,40 @@ def main():
         best = plans[chosen]["candidate"]
         print("[bench] tile choices: %s" % json.dumps(plans), file=sys.stderr, flush=True)
     full._bind()
-    t_full = time_steps(full, stream, args.steps, args.warmup)
+    t_full, t_full_median = time_steps(full, stream, args.steps, args.warmup, median=True)
     root_ms = full.ctx.time_root_group(stream, 2, 10)
     stats = full.stats()
-    print("[bench] full %s/batched/%s: %.3f ms/step, root scan %.3f ms" % (precision, chosen, t_full * 1e3, root_ms),
-          file=sys.stderr, flush=True)
+    full_res = full.results()
+    print("[bench] full %s/batched/%s: %.3f ms/step (median %.3f), root scan %.3f ms" %
+          (precision, chosen, t_full * 1e3, t_full_median * 1e3, root_ms), file=sys.stderr, flush=True)
 
-    cpu = None
+    # ablation: each of the three choices alone over the plain form (fp32, one launch per view,
+    # heuristic tiles; the tables as the full form plans them)
+    ablation = None
+    if args.forms == "both" and not args.no_ablation:
+        ablation = {}
+        ab_steps = min(args.steps, 10) if args.batch not in ("ctree", "w3", "w5") else 2
+        del full
+        torch.cuda.empty_cache()
+        for name, prec, sched, learned in (("precision", precision, "plain", False), ("batching", "fp32", "batched", False),
+                                           ("learned_tiles", "fp32", "plain", True)):
+            eng = Engine(db, qs, precision=prec, schedule=sched, columns=cols)
+            eng.ctx.execute(stream)
+            eng.ctx.sync()
+            cand = -1
+            if learned and have_model:
+                cand = eng.ctx.choose_learned_verified(WEIGHTS, stream, 4, 3)
+                eng._bind()
+            t = time_steps(eng, stream, ab_steps, 1)
+            ablation[name] = {"precision": prec, "schedule": sched, "tiles": "learned_top4_timed" if learned else "heuristic",
+                              "candidate": cand, "ms_per_step": t * 1e3, "speedup_vs_plain_fp32": (t_plain / t)}
+            print("[bench] ablation %s alone: %.3f ms/step" % (name, t * 1e3), file=sys.stderr, flush=True)
+            del eng
+            torch.cuda.empty_cache()
+
+    # reported baseline: the oracle on the host cores, timed on a bounded sample; the same leg
+    # evaluates a seeded sample of queries over the whole join for the error report of both forms
+    cpu, errors = None, None
     if not args.no_cpu_baseline:
         import oracle
         rows = min(n_join, cpu_rows)        # about 10 s of the oracle on 16 host threads
@@ -291,9 +412,44 @@ def main():
                "sample": "first %d fact rows (of %d) joined with every dimension, all %d queries" %
                          (rows, n_join, len(qs))}
         print("[bench] cpu oracle: %.3g tuples/s on %d threads" % (cpu["value"], threads), file=sys.stderr, flush=True)
+        rng = np.random.default_rng(2024)
+        sample = sorted(set([0] + [int(i) for i in rng.choice(np.arange(1, len(qs)), min(ERR_SAMPLE, len(qs) - 1),
+                                                                 replace=False)]))
+        t = time.time()
+        ref = oracle.evaluate(db, [qs[i] for i in sample], n_threads=threads)
+        errors = {"sample": "%d of %d queries (seeded), every cell, over the whole join" % (len(sample), len(qs)),
+                  "oracle_s": time.time() - t,
+                  "full": dict(max_errors(full_res, ref, sample), counts_exact=counts_exact(full_res, ref, sample),
+                               precision=precision)}
+        if plain_res is not None:
+            errors["plain_fp32"] = dict(max_errors(plain_res, ref, sample), counts_exact=counts_exact(plain_res, ref, sample))
+        print("[bench] errors vs oracle: %s" % json.dumps(errors), file=sys.stderr, flush=True)
 
     alg = algorithmic_bytes(db) if args.batch == "covariance" else referenced_bytes(db, qs)
     achieved = alg / (root_ms * 1e-3) / 1e9
+    prof = profiled_kernel("gram_scan.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": prof["traffic"] if prof else None,
+                "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % precision,
+                "algorithmic_bytes": alg, "kernel_ms": root_ms,
+                "rocprof_kernel_ms": prof["kernel_ms"] if prof else None}
+    extra = {}
+    if args.batch == "covariance" and plain_root_ms:
+        # the plain form's covariance is fp32 FMAs: 2 flops per monomial and joined row
+        flops = 2.0 * sum(1 for q in qs if q.aggs) * n_join
+        extra["plain_fp32_scan_fp32_roofline"] = {"bound": "alu", "achieved": flops / (plain_root_ms * 1e-3) / 1e12,
+                                                  "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                  "frac": flops / (plain_root_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    if args.batch in ("w2", "w3", "w5", "cube", "ctree"):
+        # grouped tables: their updates against the measured LDS atomic rate
+        peaks = measure_peaks(dev, stream)
+        upd = table_updates(db, qs, full_res)
+        rate = upd / t_full
+        extra["table_updates"] = {"bound": "lds_atomics", "updates_per_step": upd, "achieved_per_s": rate,
+                                  "peak_per_s": peaks["lds_u32_atomics_per_s"],
+                                  "frac": rate / peaks["lds_u32_atomics_per_s"],
+                                  "hbm_frac": alg / t_full / 1e9 / HBM_PEAK_GBS, "peaks": peaks}
     line = {
         "metric": metric,
         "value": n_join / t_full,
@@ -302,6 +458,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": t_full * 1e3,
+        "ms_per_step_median": t_full_median * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -314,17 +471,17 @@ def main():
                    "grid_blocks": stats["grid_blocks"], "gram_block": stats["gram_block"],
                    "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
                    "lds_bytes": stats["lds_bytes"], "grouped_tables": stats["tables"],
-                   "derived_tables": stats["derived_tables"], "launches": stats["launches"]},
+                   "derived_tables": stats["derived_tables"], "count_table_scan": stats["hist_scan"],
+                   "launches": stats["launches"]},
         "speedup_vs_plain_fp32": (t_plain / t_full) if t_plain else None,
         "plain_fp32": ({"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
                         "launches": plain_stats["launches"]} if t_plain else None),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("gram_scan.hip", "gram_scan_kernel") if stats["dedicated_scan"] else None,
-                     "kernel": ("gram_scan_kernel" if stats["dedicated_scan"] else "root_scan_kernel") + " (%s)" % precision,
-                     "algorithmic_bytes": alg, "kernel_ms": root_ms},
+        "ablation": ablation,
+        "errors_vs_oracle": errors,
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    line.update(extra)
     print(json.dumps(line))
 
 

@@ -155,13 +155,17 @@ lmfao_status lmfao_add_query(lmfao_ctx *ctx, const lmfao_query *q, int32_t *qid)
 
 /* ---- planning ------------------------------------------------------------ */
 
-enum { LMFAO_FP32 = 0, LMFAO_BF16X3 = 1, LMFAO_BF16X4 = 2 };       /* covariance-block arithmetic */
+enum { LMFAO_FP32 = 0, LMFAO_BF16X3 = 1, LMFAO_BF16X4 = 2, LMFAO_BF16X6 = 3 }; /* covariance-block arithmetic */
 enum { LMFAO_PLAIN = 0, LMFAO_BATCHED = 1 };                        /* schedule */
 enum { LMFAO_HEURISTIC = 0, LMFAO_AUTOTUNE = 1, LMFAO_LEARNED = 2 }; /* tile/grouping choice */
 
 typedef struct {
     int32_t precision;     /* FP32: fp32 FMAs; BF16X3: bf16 hi+lo split on MFMA (hi*hi+hi*lo+lo*hi),
-                              fp32 accumulate; BF16X4 adds lo*lo.  Cross-block merge is fp64 in all. */
+                              fp32 accumulate; BF16X4 adds lo*lo; BF16X6: three bf16 pieces
+                              x = hi+mid+lo (hi*hi+hi*mid+mid*hi+mid*mid+hi*lo+lo*hi), which keeps every
+                              term down to 2^-16 of a product (about 1e-7 per product; BF16X3 and
+                              BF16X4 drop up to 3 and 2 times 2^-16, which a sum dominated by one
+                              repeated value keeps).  Cross-block merge is fp64 in all. */
     int32_t schedule;      /* PLAIN: one launch per view; BATCHED: one fused launch per tree level,
                               captured in a hipGraph and replayed */
     int32_t planner;       /* HEURISTIC: fixed rules; AUTOTUNE: time every candidate tile config
@@ -182,6 +186,9 @@ typedef struct {
     int32_t no_row_codes;  /* 0: filtered tables over several LDS partitions are updated from per-row
                               codes when they qualify (see lmfao_stats.code_scan); 1: the root scan
                               updates them itself, once per partition.  Other values are INVALID_ARG. */
+    int32_t no_hist;       /* 0: unfiltered COUNT-only tables that the root scan cannot keep in one LDS
+                              partition are counted by the count-table scan (see lmfao_stats.hist_scan);
+                              1: the root scan updates them.  Other values are INVALID_ARG. */
 } lmfao_plan_opts;
 
 /* Build the evaluation plan for all queries added so far. */
@@ -214,6 +221,13 @@ typedef struct {
                                     the root scan writes each row's filter mask, key cells and summed
                                     feature values once (4 bytes per column and row of workspace, at
                                     most 16 GiB) and a code scan per partition updates the tables */
+    int32_t hist_scan;           /* 1: unfiltered COUNT-only tables (pairwise counts, Section 2, equation
+                                    (7)) beyond the root scan's LDS are counted apart: the root scan writes
+                                    each row's group-by component values once as 16-bit codes (2 bytes per
+                                    component and row of workspace, at most 16 GiB), and the count-table
+                                    scan counts them into LDS slices of the tables, one partition of
+                                    slices per grid row, adding its cells to the global u64 counts */
+    int32_t hist_parts;          /* LDS partitions of the count-table scan */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);
@@ -321,6 +335,30 @@ lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip
  * top_k or reps below 1; STATE before lmfao_bind. */
 lmfao_status lmfao_choose_learned_verified(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t top_k,
                                            int32_t reps, int32_t *best);
+
+/* ---- unit throughput probes (roofline peaks) ----------------------------- */
+
+enum {
+    LMFAO_PEAK_READ = 0,          /* streaming read of the buffer, 16 bytes per lane per load */
+    LMFAO_PEAK_LDS_U32 = 1,       /* LDS u32 atomic adds at random addresses of a 32K-word table */
+    LMFAO_PEAK_LDS_U32_SPREAD = 2,/* LDS u32 atomic adds, the 64 lanes of a wave on distinct banks */
+    LMFAO_PEAK_LDS_F64 = 3,       /* LDS fp64 atomic adds at random addresses of a 16K-cell table */
+    LMFAO_PEAK_GLOBAL_U64 = 4     /* device-scope u64 atomic adds at random cells of the buffer */
+};
+
+/* Time one probe launch (4 workgroups of 1024 threads per CU; for READ,
+ * `iters` passes over the buffer) on `hip_stream` of the current device with
+ * HIP events: *ms receives the milliseconds and *units the bytes read (READ)
+ * or atomic adds issued (the others), so *units / *ms is the unit's rate.
+ * Each thread issues `iters` atomics.  `buf` is caller-owned device memory:
+ * the data to read, the u64 counters to add to (GLOBAL_U64; its contents are
+ * changed), or room for one 4-byte result per workgroup (LDS probes; READ
+ * also writes those results at its start and reads the rest).  Errors:
+ * INVALID_ARG for a bad kind, iters < 1 or null outputs; WORKSPACE when the
+ * buffer is too small; HIP on a runtime failure.  A measurement aid: the
+ * engine's entry points do not use it. */
+lmfao_status lmfao_measure_peak(int32_t kind, void *buf, size_t buf_bytes, int32_t iters, void *hip_stream,
+                                double *ms, double *units);
 
 /* ---- cost-model network (hand-written device kernels) -------------------- */
 

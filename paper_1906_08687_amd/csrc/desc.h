@@ -206,7 +206,11 @@ struct RootDesc {
     int32_t n_code_feats;              // staged features summed by the tables, written as fp32 codes
     const int32_t *code_feats;         // [n_code_feats] their staged feature ids
     int32_t code_feat_col;             // column of the first of them
-    int32_t pad1;
+    int32_t n_hcodes;                  // count-table scan: component code columns to write
+    uint16_t *hcodes;                  // [n_hcodes][hcode_pitch] component values, 0xFFFF when the
+                                       // row does not join (see HistDesc)
+    int64_t hcode_pitch;               // u16 entries per column (rows rounded up to 64)
+    const int32_t *hcode_comp;         // [n_hcodes] staged component of each column
 };
 
 // ---- grouped tables from per-row codes -----------------------------------------
@@ -239,6 +243,42 @@ struct CodeScanDesc {
     int32_t flush_base[kMaxParts], n_flush[kMaxParts];
     unsigned long long *g_cnt;
     double *g_val;
+};
+
+// ---- count tables from component codes ------------------------------------------
+//
+// Unfiltered COUNT-only grouped tables (the pairwise counts of mutual
+// information, Section 2, equation (7)) are kept out of the root scan when
+// they do not fit its LDS: the root scan writes each row's group-by component
+// values once, as 16-bit codes (0xFFFF when the row does not join), and this
+// scan counts them.  A table is cut into slices of consecutive cells that fit
+// LDS; slices are packed into partitions (blockIdx.y).  A workgroup of a
+// partition counts its rows into LDS (tiny slices in several replicas, so
+// that the lanes of a wave spread their updates over banks) and adds its
+// nonzero cells to the table's global u64 counts.
+constexpr uint16_t kNoCode = 0xFFFFu;
+
+struct HistSlice {
+    int32_t n_comp;                 // components of the table's key (1..kMaxKeyComps)
+    int32_t code[kMaxKeyComps];     // code column of each component
+    int32_t stride[kMaxKeyComps];   // cell = sum code[i] * stride[i]
+    int32_t lo;                     // the slice holds cells [lo, lo + n) of its table
+    int32_t n;
+    int32_t lds_off;                // word offset of its first replica in LDS
+    int32_t reps;                   // replicas (a power of two), rep_stride words apart
+    int32_t rep_stride;
+    int64_t glb_cnt;                // index of the table's first u64 count in g_cnt
+};
+
+struct HistDesc {
+    int64_t n_rows;
+    int64_t rows_per_block;         // multiple of 8
+    int64_t pitch;                  // u16 entries per code column
+    const uint16_t *codes;
+    const HistSlice *slices;
+    const int32_t *part_begin;      // [n_parts + 1] slices of partition p: [part_begin[p], part_begin[p+1])
+    const int32_t *lds_words;       // [n_parts] LDS words of partition p
+    unsigned long long *g_cnt;
 };
 
 // ---- covariance-only root scan ------------------------------------------------

@@ -91,6 +91,28 @@ __device__ __forceinline__ void split_bf16x8(const float *x, bf16x8 &hi, bf16x8 
     lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
 }
 
+// x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), each round to
+// nearest even; x - hi and x - hi - mid are exact in fp32, and hi + mid + lo carries x to within
+// 2^-24 |x| (8 significant bits per piece)
+__device__ __forceinline__ void split3_bf16x8(const float *x, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo) {
+    uint32_t h[4], m[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f32x2 v = {x[2 * i], x[2 * i + 1]};
+        const bf16x2 hb = __builtin_convertvector(v, bf16x2);
+        const f32x2 r1 = v - __builtin_convertvector(hb, f32x2);
+        const bf16x2 mb = __builtin_convertvector(r1, bf16x2);
+        const f32x2 r2 = r1 - __builtin_convertvector(mb, f32x2);
+        const bf16x2 lb = __builtin_convertvector(r2, bf16x2);
+        h[i] = __builtin_bit_cast(uint32_t, hb);
+        m[i] = __builtin_bit_cast(uint32_t, mb);
+        l[i] = __builtin_bit_cast(uint32_t, lb);
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    mid = __builtin_bit_cast(bf16x8, make_uint4(m[0], m[1], m[2], m[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
 constexpr int kFlushTiles = 16;   // mfma accumulators fold into fp32 sums every 16 tiles (1024 rows per wave)
 
 }  // namespace lmfao

@@ -56,11 +56,13 @@ hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts
                        hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
 typedef void (*GramKernel)(const GramDesc *);
-GramKernel gram_kernel(int nt, int nf, bool x4, bool pr);
+GramKernel gram_kernel(int nt, int nf, int pm, bool pr);
 hipError_t launch_gram(GramKernel k, const GramDesc *desc, int grid_x, int waves, size_t lds_bytes, hipStream_t st);
 hipError_t set_gram_lds_limit(GramKernel k, size_t bytes);
 hipError_t set_code_scan_lds_limit(size_t bytes);
 hipError_t launch_code_scan(const CodeScanDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st);
+hipError_t set_hist_lds_limit(size_t bytes);
+hipError_t launch_hist(const HistDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st);
 hipError_t launch_merge(const MergeDesc *desc, int n_gram, hipStream_t st);
 hipError_t launch_assemble(const AssembleDesc *desc, int n_out, int64_t max_cells, hipStream_t st);
 hipError_t launch_rollup(const RollupDesc *desc, int n_items, int64_t max_work, hipStream_t st);
@@ -161,6 +163,7 @@ struct Family {
     std::vector<std::vector<int>> keys;   // component lists
     std::vector<int> filters;             // ascending filter ids; empty = unfiltered
     std::vector<int> tables;              // index f * n_keys + k -> table id
+    bool hist = false;                    // counted by the count-table scan, not the root scan
 };
 
 struct OutTerm {
@@ -245,6 +248,16 @@ struct Plan {
     int code_grid = 0;
     int64_t code_rows_per_block = 0;
     size_t code_lds_bytes = 0;
+    // count tables from 16-bit component codes (unfiltered COUNT-only families beyond the root
+    // scan's LDS): the root scan writes the codes, the count-table scan counts them per partition
+    bool hist = false;
+    std::vector<int> hist_comps;                   // component of each code column
+    int64_t hist_pitch = 0;
+    std::vector<HistSlice> hist_slices;            // partition by partition
+    std::vector<int32_t> hist_part_begin, hist_lds_words;
+    int hist_grid = 0;
+    int64_t hist_rows_per_block = 0;
+    size_t hist_lds_bytes = 0;
     // schedule
     int precision = LMFAO_FP32, schedule = LMFAO_BATCHED, planner = LMFAO_HEURISTIC;
     TileCfg cfg;                      // chosen tile configuration
@@ -330,6 +343,8 @@ struct lmfao_ctx {
     std::vector<size_t> rollup_off;               // per pass: RollupDesc offset in blob
     size_t off_codes = 0;                         // per-row codes
     size_t code_desc_off = 0;                     // CodeScanDesc offset in blob
+    size_t off_hcodes = 0;                        // component codes of the count-table scan
+    size_t hist_desc_off = 0;                     // HistDesc offset in blob
     std::vector<int64_t> rollup_cells;            // per pass: most (cell, sum or count) pairs of a table
     int64_t assemble_cells = 0;                   // most cells of a query result
     // execution
@@ -1009,7 +1024,7 @@ static Layout stage_layout(const Plan &P, int mode, int p1, bool tables, int tab
         L.ngp = round_up(P.n_gram, p1);
         red = 2 * L.ngp * L.ngp;
     } else if (mode >= 2) {
-        red = (mode == 3 ? 3 : 2) * (16 * p1) * (16 * p1) * 2;
+        red = (mode >= 3 ? 3 : 2) * (16 * p1) * (16 * p1) * 2;
     }
     L.total = std::max(o, L.lds_red + red);
     return L;
@@ -1027,6 +1042,10 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
     for (auto &T : P.tables) { T.part = 0; T.lds_cnt = T.lds_val = -1; }
     P.parts = 1;
     if (P.tables.empty() || policy == 0 || budget_words <= 0) return;
+    std::vector<char> in_hist(P.tables.size(), 0);   // tables of the count-table scan stay global
+    for (auto &F : P.fams)
+        if (F.hist)
+            for (int t : F.tables) in_hist[t] = 1;
     if (policy == 1) {
         std::vector<int> idx(P.tables.size());
         for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
@@ -1034,7 +1053,7 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
         int used = 0;
         for (int t : idx) {
             const int w = P.tables[t].words();
-            if (P.tables[t].from >= 0 || used + w > budget_words) continue;
+            if (P.tables[t].from >= 0 || in_hist[t] || used + w > budget_words) continue;
             P.tables[t].lds_cnt = used;
             P.tables[t].lds_val = used + P.tables[t].val_off();
             used += w;
@@ -1045,6 +1064,7 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
     std::vector<std::vector<int>> units;
     for (auto &F : P.fams) {
         const int nk = (int)F.keys.size();
+        if (F.hist) continue;
         if (F.filters.empty()) {
             for (int t : F.tables) units.push_back({t});
         } else {
@@ -1078,6 +1098,19 @@ static void place_tables(const lmfao_ctx *c, Plan &P, int policy, int budget_wor
     (void)c;
 }
 
+// Kernel mode of the covariance block: 0 none, 1 fp32, 2 BF16X3, 3 BF16X4, 4 BF16X6; and the
+// products per tile pair of the dedicated scan in each BF16 mode.
+static int precision_mode(const Plan &P) {
+    if (P.n_gram == 0) return 0;
+    switch (P.precision) {
+        case LMFAO_FP32: return 1;
+        case LMFAO_BF16X3: return 2;
+        case LMFAO_BF16X4: return 3;
+        default: return 4;
+    }
+}
+static int gram_products(int mode) { return mode == 3 ? 4 : (mode == 4 ? 6 : 3); }
+
 // The dedicated covariance scan applies to a BF16 covariance block of at most 64
 // features (16 to 48 of them from the root relation rounded to whole 16-wide tiles:
 // at most 2 such tiles), at most kGramMaxChild children with keys below 2^24, and a
@@ -1091,7 +1124,7 @@ static bool gram_eligible(const lmfao_ctx *c, const Plan &P, int *nt, int *nf) {
     const int n_fact = (int)P.own_feats[P.root].size();
     *nt = (P.n_gram + 15) / 16;
     *nf = (n_fact + 15) / 16;
-    return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, P.mode == 3, false) != nullptr;
+    return *nf <= 2 && *nf <= *nt && gram_kernel(*nt, *nf, gram_products(P.mode), false) != nullptr;
 }
 
 // Pair-row record buffers for the dedicated scan: every child record of at most 8 words (two
@@ -1149,14 +1182,18 @@ static bool family_strided(const Plan &P, const Family &F, FamilyDesc &fd) {
 
 // Per-row codes (see CodeScanDesc): tables that are all filtered, with few sums.
 static bool codes_eligible(const Plan &P) {
-    if (P.fams.empty()) return false;
-    for (auto &F : P.fams)
+    int n = 0;
+    for (auto &F : P.fams) {
+        if (F.hist) continue;
         if (F.filters.empty() || (int)F.vals.size() > kMaxCodeVals) return false;
-    return true;
+        ++n;
+    }
+    return n > 0;
 }
 
 static bool all_strided(const Plan &P) {
     for (auto &F : P.fams) {
+        if (F.hist) continue;
         FamilyDesc fd{};
         if (!family_strided(P, F, fd)) return false;
     }
@@ -1165,11 +1202,109 @@ static bool all_strided(const Plan &P) {
 
 constexpr size_t kMaxCodeBytes = (size_t)16 << 30;   // workspace the per-row codes may take
 
+// The count-table scan (see HistDesc) takes the unfiltered COUNT-only families when the root
+// scan, as placed, cannot keep all of their tables in one LDS partition (some are global, or
+// the tables need several partitions, each a rescan of the root relation).  Every component of
+// those tables must fit a 16-bit code below 0xFFFF.  Slices of at most one LDS of cells are
+// packed first-fit, largest first; slices of at most 2048 cells get up to 32 replicas (a power
+// of two, odd stride) so that the lanes of a wave spread their updates over LDS banks.
+static void plan_hist(const lmfao_ctx *c, Plan &P, int budget) {
+    for (auto &F : P.fams) F.hist = false;
+    P.hist = false;
+    P.hist_comps.clear();
+    P.hist_slices.clear();
+    P.hist_part_begin.clear();
+    P.hist_lds_words.clear();
+    const Rel &root = c->rels[P.root];
+    if (c->opts.no_hist || P.schedule != LMFAO_BATCHED || root.n_rows <= 0) return;
+    std::vector<int> elig;
+    bool spill = P.parts > 1;
+    for (size_t f = 0; f < P.fams.size(); ++f) {
+        const Family &F = P.fams[f];
+        if (!F.filters.empty() || !F.vals.empty()) continue;
+        bool ok = true;
+        for (int t : F.tables) {
+            const Table &T = P.tables[t];
+            if ((int)T.comps.size() > kMaxKeyComps || T.n_cells > ((int64_t)1 << 31) - 1) ok = false;
+            for (int cp : T.comps)
+                if (P.comps[cp].dom >= (int)kNoCode) ok = false;
+            if (T.lds_cnt < 0) spill = true;
+        }
+        if (ok) elig.push_back((int)f);
+    }
+    if (elig.empty() || !spill) return;
+    std::set<int> comps;
+    for (int f : elig)
+        for (int t : P.fams[f].tables)
+            for (int cp : P.tables[t].comps) comps.insert(cp);
+    const int64_t pitch = round_up((int)std::min<int64_t>(root.n_rows, 1 << 30), 64);
+    if ((size_t)comps.size() * (size_t)pitch * 2 > kMaxCodeBytes) return;
+    P.hist_comps.assign(comps.begin(), comps.end());
+    P.hist_pitch = pitch;
+    // slices of every table
+    const int cap = (int)(c->lds_limit / 4) - 64;
+    std::vector<HistSlice> sl;
+    for (int f : elig)
+        for (int t : P.fams[f].tables) {
+            const Table &T = P.tables[t];
+            HistSlice h{};
+            h.n_comp = (int)T.comps.size();
+            int64_t stride = 1;
+            for (int i = h.n_comp - 1; i >= 0; --i) {
+                h.code[i] = (int)(std::find(P.hist_comps.begin(), P.hist_comps.end(), T.comps[i]) - P.hist_comps.begin());
+                h.stride[i] = (int32_t)stride;
+                stride *= P.comps[T.comps[i]].dom;
+            }
+            h.glb_cnt = T.glb_cnt;
+            const int64_t n = T.n_cells;
+            const int64_t k = ceil_div(n, cap);
+            for (int64_t j = 0; j < k; ++j) {
+                HistSlice x = h;
+                x.lo = (int32_t)(n * j / k);
+                x.n = (int32_t)(n * (j + 1) / k - x.lo);
+                x.reps = 1;
+                if (x.n <= 2048)
+                    while (x.reps < 32 && (int64_t)(2 * x.reps) * x.n <= 4096) x.reps *= 2;
+                x.rep_stride = x.n | 1;
+                sl.push_back(x);
+            }
+        }
+    auto words = [](const HistSlice &x) { return (x.reps - 1) * x.rep_stride + x.n; };
+    std::stable_sort(sl.begin(), sl.end(), [&](const HistSlice &a, const HistSlice &b) { return words(a) > words(b); });
+    std::vector<std::vector<HistSlice>> parts;
+    std::vector<int> used;
+    for (auto &x : sl) {
+        size_t p = 0;
+        while (p < parts.size() && used[p] + words(x) > cap) ++p;
+        if (p == parts.size()) { parts.emplace_back(); used.push_back(0); }
+        x.lds_off = used[p];
+        used[p] += round_up(words(x), 4);
+        parts[p].push_back(x);
+    }
+    int max_words = 0;
+    for (size_t p = 0; p < parts.size(); ++p) {
+        P.hist_part_begin.push_back((int32_t)P.hist_slices.size());
+        P.hist_slices.insert(P.hist_slices.end(), parts[p].begin(), parts[p].end());
+        P.hist_lds_words.push_back(used[p]);
+        max_words = std::max(max_words, used[p]);
+    }
+    P.hist_part_begin.push_back((int32_t)P.hist_slices.size());
+    P.hist_lds_bytes = (size_t)max_words * 4;
+    // two rounds of workgroups over the chip (one resident per CU when a partition fills LDS)
+    const int nparts = (int)parts.size();
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2 * (int64_t)c->n_cu, nparts), ceil_div(root.n_rows, 8192)));
+    P.hist_rows_per_block = round_up((int)ceil_div(root.n_rows, gx), 8);
+    P.hist_grid = (int)ceil_div(root.n_rows, P.hist_rows_per_block);
+    for (int f : elig) P.fams[f].hist = true;
+    P.hist = true;
+    place_tables(c, P, P.lds_policy, budget);
+}
+
 static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     Plan &P = c->plan;
     const Rel &root = c->rels[P.root];
     P.cfg = cfg;
-    P.mode = P.n_gram == 0 ? 0 : (P.precision == LMFAO_FP32 ? 1 : (P.precision == LMFAO_BF16X3 ? 2 : 3));
+    P.mode = precision_mode(P);
     P.n_tiles16 = (P.n_gram + 15) / 16;
     if (P.mode == 1) {
         int gb = cfg.gram_block > 0 ? cfg.gram_block : estimate_gram_block(P.n_gram);
@@ -1203,6 +1338,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     }
     const int budget = table_words_fit(c, P, P.mode, p1, has_tables, P.nbuf, P.waves);
     place_tables(c, P, P.lds_policy, budget);
+    plan_hist(c, P, budget);
     // COUNT-only filtered tables that need several partitions: the root scan runs once with no
     // tables and writes per-row codes; a code scan per partition, with the whole LDS for its
     // tables, replays them (when the codes fit their workspace cap)
@@ -1211,7 +1347,8 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         codes_eligible(P)) {
         P.n_mask_codes = P.filters.size() > 32 ? 2 : 1;
         P.n_codes = P.n_mask_codes;
-        for (auto &F : P.fams) P.n_codes += (int)F.keys.size();
+        for (auto &F : P.fams)
+            if (!F.hist) P.n_codes += (int)F.keys.size();
         std::set<int> fs;
         for (auto &F : P.fams)
             for (auto &v : F.vals) {
@@ -1247,7 +1384,9 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         L.with_gram = with_gram;
         L.mode = with_gram ? P.mode : 0;
         L.p1 = with_gram ? p1 : 1;
-        L.tables = !fams.empty();
+        // the batched launch computes the components of the count-table scan's codes even when no
+        // table of its own is left
+        L.tables = !fams.empty() || (P.hist && single_table < 0);
         L.fam_ids = fams;
         L.single_table = single_table;
         int max_words = 0;
@@ -1272,7 +1411,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
             L.gpr = gram_pair_rows(P);
             L.waves = P.gram_waves;
             L.lds_bytes = gram_lds_bytes(P, L.waves, gnf);
-            occ_waves = gnt >= 4 ? 8 : 12;
+            occ_waves = gnt >= 4 || L.mode == 4 ? 8 : 12;
         } else {
             const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
             L.lds_bytes = (size_t)Ly.total * 4;
@@ -1295,7 +1434,8 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
         return L;
     };
     std::vector<int> all_fams;
-    for (size_t f = 0; f < P.fams.size(); ++f) all_fams.push_back((int)f);
+    for (size_t f = 0; f < P.fams.size(); ++f)
+        if (!P.fams[f].hist) all_fams.push_back((int)f);
     const bool need_gram_launch = P.n_gram > 0 || P.need_count;
     if (P.schedule == LMFAO_BATCHED) {
         P.root_launches.push_back(make_launch(need_gram_launch, all_fams, -1));
@@ -1370,6 +1510,8 @@ static size_t compute_ws(lmfao_ctx *c) {
     o = align_up(o + 4 * kMaxRecWords);
     c->off_codes = o;
     if (P.codes) o = align_up(o + (size_t)P.n_codes * (size_t)P.code_pitch * 4);
+    c->off_hcodes = o;
+    if (P.hist) o = align_up(o + P.hist_comps.size() * (size_t)P.hist_pitch * 2);
     c->off_mlp = o;
     o = align_up(o + ((size_t)1 << 20));
     c->off_desc = o;
@@ -1696,6 +1838,14 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             D.code_feats = reinterpret_cast<const int32_t *>(dev(B.vec(P.code_feats)));
             D.code_feat_col = P.code_feat_col;
         }
+        if (P.hist && L.tables && L.single_table < 0) {
+            std::vector<int32_t> slot;
+            for (int cp : P.hist_comps) slot.push_back(P.comps[cp].slot);
+            D.n_hcodes = (int)slot.size();
+            D.hcodes = reinterpret_cast<uint16_t *>(ws + c->off_hcodes);
+            D.hcode_pitch = P.hist_pitch;
+            D.hcode_comp = reinterpret_cast<const int32_t *>(dev(B.vec(slot)));
+        }
         D.n_fam = (int)fdesc.size();
         D.n_parts = L.parts;
         const Layout Ly = stage_layout(P, L.mode, L.p1, L.tables, max_words, P.nbuf, P.waves);
@@ -1812,6 +1962,18 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         csd.val_cols = reinterpret_cast<const ValDesc *>(dev(B.vec(vcols)));
         csd.keys = reinterpret_cast<const KeyDesc *>(dev(keys_off));
         c->code_desc_off = B.put(&csd, sizeof csd);
+    }
+    if (P.hist) {
+        HistDesc hd{};
+        hd.n_rows = c->rels[r0].n_rows;
+        hd.rows_per_block = P.hist_rows_per_block;
+        hd.pitch = P.hist_pitch;
+        hd.codes = reinterpret_cast<const uint16_t *>(ws + c->off_hcodes);
+        hd.slices = reinterpret_cast<const HistSlice *>(dev(B.vec(P.hist_slices)));
+        hd.part_begin = reinterpret_cast<const int32_t *>(dev(B.vec(P.hist_part_begin)));
+        hd.lds_words = reinterpret_cast<const int32_t *>(dev(B.vec(P.hist_lds_words)));
+        hd.g_cnt = gcnt;
+        c->hist_desc_off = B.put(&hd, sizeof hd);
     }
     // ---- merge and assembly ---------------------------------------------------------------------
     MergeDesc md{};
@@ -1963,9 +2125,10 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     o.schedule = LMFAO_BATCHED;
     o.planner = LMFAO_HEURISTIC;
     if (opts) o = *opts;
-    if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X4 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
+    if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X6 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
         o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED || o.block_rows != 0 || o.grid_blocks < 0 ||
         o.scan_every_table < 0 || o.scan_every_table > 1 || o.no_row_codes < 0 || o.no_row_codes > 1 ||
+        o.no_hist < 0 || o.no_hist > 1 ||
         !(o.gram_block == 0 || o.gram_block == 2 || o.gram_block == 4 || o.gram_block == 6 || o.gram_block == 8))
         return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
     invalidate(c);
@@ -1996,6 +2159,8 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->derived_tables = P.n_derived;
     s->strided_families = P.n_strided;
     s->code_scan = P.codes ? 1 : 0;
+    s->hist_scan = P.hist ? 1 : 0;
+    s->hist_parts = P.hist ? (int32_t)P.hist_lds_words.size() : 0;
     s->table_cells = P.table_cells;
     int launches = 1;   // fill
     for (int L = 0; L < P.levels - 1; ++L) {
@@ -2004,7 +2169,7 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
             if (r != P.root && P.height[r] == L) ++nrel;
         launches += P.schedule == LMFAO_BATCHED ? (nrel > 0) : nrel;
     }
-    launches += (int)P.root_launches.size() + (P.codes ? 1 : 0);
+    launches += (int)P.root_launches.size() + (P.codes ? 1 : 0) + (P.hist ? 1 : 0);
     if (P.n_gram > 0 || P.need_count) launches += 1;
     launches += (int)P.rollup_passes.size();
     launches += 1;   // assemble
@@ -2057,7 +2222,7 @@ static lmfao_status upload(lmfao_ctx *c) {
     HIP_TRY(c, hipMemcpy(c->ws + c->off_desc, c->blob.data(), c->blob.size(), hipMemcpyHostToDevice));
     for (auto &L : c->plan.root_launches) {
         if (L.gram) {
-            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3, L.gpr);
+            GramKernel k = gram_kernel(L.gnt, L.gnf, gram_products(L.mode), L.gpr);
             if (L.lds_bytes > 64 * 1024) HIP_TRY(c, set_gram_lds_limit(k, L.lds_bytes));
         } else {
             RootKernel k = root_kernel(L.mode, L.p1, L.tables);
@@ -2065,6 +2230,7 @@ static lmfao_status upload(lmfao_ctx *c) {
         }
     }
     if (c->plan.codes && c->plan.code_lds_bytes > 64 * 1024) HIP_TRY(c, set_code_scan_lds_limit(c->plan.code_lds_bytes));
+    if (c->plan.hist && c->plan.hist_lds_bytes > 64 * 1024) HIP_TRY(c, set_hist_lds_limit(c->plan.hist_lds_bytes));
     return LMFAO_OK;
 }
 
@@ -2133,7 +2299,7 @@ static lmfao_status bind_buffers(lmfao_ctx *c, void *workspace, size_t ws_bytes,
 static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
     for (auto &L : c->plan.root_launches) {
         if (L.gram) {
-            GramKernel k = gram_kernel(L.gnt, L.gnf, L.mode == 3, L.gpr);
+            GramKernel k = gram_kernel(L.gnt, L.gnf, gram_products(L.mode), L.gpr);
             HIP_TRY(c, launch_gram(k, reinterpret_cast<const GramDesc *>(c->ws + c->off_desc + L.desc_off), L.grid_x,
                                    L.waves, L.lds_bytes, st));
             continue;
@@ -2146,6 +2312,9 @@ static lmfao_status enqueue_root(lmfao_ctx *c, hipStream_t st) {
     if (P.codes)
         HIP_TRY(c, launch_code_scan(reinterpret_cast<const CodeScanDesc *>(c->ws + c->off_desc + c->code_desc_off),
                                     P.code_grid, P.parts, P.code_lds_bytes, st));
+    if (P.hist)
+        HIP_TRY(c, launch_hist(reinterpret_cast<const HistDesc *>(c->ws + c->off_desc + c->hist_desc_off), P.hist_grid,
+                               (int)P.hist_lds_words.size(), P.hist_lds_bytes, st));
     return LMFAO_OK;
 }
 
@@ -2349,7 +2518,7 @@ static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
         if (r != P.root) child_keys += P.n_keys[r];
     double upd = 0.0;   // table updates per row (filtered tables counted at half)
     for (auto &T : P.tables) upd += (T.filter < 0 ? 1.0 : 0.5) * (1.0 + (double)T.vals.size());
-    const int mode = P.n_gram == 0 ? 0 : (P.precision == LMFAO_FP32 ? 1 : (P.precision == LMFAO_BF16X3 ? 2 : 3));
+    const int mode = precision_mode(P);
     f[0] = (float)std::log2(rows + 1.0);
     f[1] = (float)P.n_gram;
     f[2] = (float)std::min(64.0, candidate_rounds(c, t));

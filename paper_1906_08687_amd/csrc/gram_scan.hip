@@ -37,13 +37,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 //      loads that bypass registers (a key outside [0, n_keys) reads past the
 //      buffer range and lands as zeros: no join), then request the keys of
 //      tile t+2 (after the last tile these requests repeat it, unused);
-//   5. accumulate hi*hi + hi*lo + lo*hi (+ lo*lo) for every upper-triangle
+//   5. accumulate the products of the split (see PM) for every upper-triangle
 //      16x16 tile pair on MFMA while those copies are in flight.
 // Fact columns and keys are streamed once: their loads are non-temporal, so
 // they do not push the gathered view records out of the caches.  Each wave
 // writes its own fp64 partial of the upper triangle (no LDS reduction).
-template <int NT, int NF, bool X4, bool PR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 ? 2 : 3))) void gram_scan_kernel(
+// PM: products per tile pair: 3 (hi*hi + hi*lo + lo*hi), 4 (adds lo*lo), or 6 (three pieces
+// hi, mid, lo: hi*hi + hi*mid + mid*hi + mid*mid + hi*lo + lo*hi, every term down to 2^-16 of a
+// product kept; the six-product form holds three operand registers per slot tile and runs two
+// waves per SIMD)
+template <int NT, int NF, int PM, bool PR>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 || PM == 6 ? 2 : 3))) void gram_scan_kernel(
     const GramDesc *__restrict__ dp) {
     extern __shared__ __align__(16) uint32_t smem[];
     const AS_CONST GramDesc &d = *cst(dp);
@@ -246,7 +250,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     // Phase 1 of a tile: validity, then every operand of both k-steps split into bf16 hi/lo
     // registers.  After it the tile needs neither its LDS record buffer nor its fact
     // registers, so the next copies can be issued before phase 2 (the MFMAs) runs.
-    bf16x8 oph[2][NT], opl[2][NT];
+    constexpr int NMID = PM == 6 ? NT : 1;
+    bf16x8 oph[2][NT], opl[2][NT], opm[2][NMID];
     auto phase1 = [&](int t) -> bool {
         const int r0 = tile_row(t);
         bool valid = r0 + lane < blk_end;
@@ -293,41 +298,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     for (int i = 0; i < 8; ++i)
                         if (!((vbits >> i) & 1u)) x[i] = 0.f;
                 }
-                split_bf16x8(x, oph[ks][t2], opl[ks][t2]);
+                if (PM == 6) split3_bf16x8(x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
+                else split_bf16x8(x, oph[ks][t2], opl[ks][t2]);
             }
         }
         return true;
     };
     // Phase 2: the MFMAs of both k-steps, from registers only.
+    auto mfma_pass = [&](const bf16x8 *A, const bf16x8 *B) {
+        int p = 0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = a; b < NT; ++b, ++p)
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B[b], acc[p], 0, 0, 0);
+    };
     auto phase2 = [&]() {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            int p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], oph[ks][b], acc[p], 0, 0, 0);
-            p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], opl[ks][b], acc[p], 0, 0, 0);
-            p = 0;
-#pragma unroll
-            for (int a = 0; a < NT; ++a)
-#pragma unroll
-                for (int b = a; b < NT; ++b, ++p)
-                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], oph[ks][b], acc[p], 0, 0, 0);
-            if (X4) {
-                p = 0;
-#pragma unroll
-                for (int a = 0; a < NT; ++a)
-#pragma unroll
-                    for (int b = a; b < NT; ++b, ++p)
-                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opl[ks][a], opl[ks][b], acc[p], 0, 0, 0);
+            mfma_pass(oph[ks], oph[ks]);
+            if (PM == 6) {
+                mfma_pass(oph[ks], opm[ks]);
+                mfma_pass(opm[ks], oph[ks]);
+                mfma_pass(opm[ks], opm[ks]);
             }
+            mfma_pass(oph[ks], opl[ks]);
+            mfma_pass(opl[ks], oph[ks]);
+            if (PM == 4) mfma_pass(opl[ks], opl[ks]);
         }
         if (++since_flush == kFlushTiles) {
 #pragma unroll
@@ -420,28 +417,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
 
 typedef void (*GramKernel)(const GramDesc *);
 
-template <int NT, int NF>
-static GramKernel pick_gram(bool x4, bool pr) {
-    if (pr) return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, true> : (GramKernel)gram_scan_kernel<NT, NF, false, true>;
-    return x4 ? (GramKernel)gram_scan_kernel<NT, NF, true, false> : (GramKernel)gram_scan_kernel<NT, NF, false, false>;
+template <int NT, int NF, int PM>
+static GramKernel pick_pr(bool pr) {
+    return pr ? (GramKernel)gram_scan_kernel<NT, NF, PM, true> : (GramKernel)gram_scan_kernel<NT, NF, PM, false>;
 }
 
-// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2)); pr: pair-row record
-// buffers (every child record at most two quads, a row's quads contiguous) instead of quad-major ones
-GramKernel gram_kernel(int nt, int nf, bool x4, bool pr) {
-    if (nf < 0 || nf > 2 || nf > nt) return nullptr;
+template <int NT, int NF>
+static GramKernel pick_gram(int pm, bool pr) {
+    if (pm == 6) return pick_pr<NT, NF, 6>(pr);
+    return pm == 4 ? pick_pr<NT, NF, 4>(pr) : pick_pr<NT, NF, 3>(pr);
+}
+
+// nt: 16-wide slot tiles (1..4); nf: tiles holding fact slots (0..min(nt, 2)); pm: products per tile
+// pair (3, 4 or 6); pr: pair-row record buffers (every child record at most two quads, a row's quads
+// contiguous) instead of quad-major ones
+GramKernel gram_kernel(int nt, int nf, int pm, bool pr) {
+    if (nf < 0 || nf > 2 || nf > nt || (pm != 3 && pm != 4 && pm != 6)) return nullptr;
     switch (nt * 4 + nf) {
-        case 4: return pick_gram<1, 0>(x4, pr);
-        case 5: return pick_gram<1, 1>(x4, pr);
-        case 8: return pick_gram<2, 0>(x4, pr);
-        case 9: return pick_gram<2, 1>(x4, pr);
-        case 10: return pick_gram<2, 2>(x4, pr);
-        case 12: return pick_gram<3, 0>(x4, pr);
-        case 13: return pick_gram<3, 1>(x4, pr);
-        case 14: return pick_gram<3, 2>(x4, pr);
-        case 16: return pick_gram<4, 0>(x4, pr);
-        case 17: return pick_gram<4, 1>(x4, pr);
-        case 18: return pick_gram<4, 2>(x4, pr);
+        case 4: return pick_gram<1, 0>(pm, pr);
+        case 5: return pick_gram<1, 1>(pm, pr);
+        case 8: return pick_gram<2, 0>(pm, pr);
+        case 9: return pick_gram<2, 1>(pm, pr);
+        case 10: return pick_gram<2, 2>(pm, pr);
+        case 12: return pick_gram<3, 0>(pm, pr);
+        case 13: return pick_gram<3, 1>(pm, pr);
+        case 14: return pick_gram<3, 2>(pm, pr);
+        case 16: return pick_gram<4, 0>(pm, pr);
+        case 17: return pick_gram<4, 1>(pm, pr);
+        case 18: return pick_gram<4, 2>(pm, pr);
     }
     return nullptr;
 }

@@ -26,13 +26,15 @@
 // The covariance-only scan on matrix cores (gram_scan_kernel) is in
 // gram_scan.hip; helpers both files use are in device.h.
 //
-// The covariance block is computed in one of three arithmetics:
+// The covariance block is computed in one of four arithmetics:
 //   FP32      register-blocked fp32 FMAs over a row tile staged in LDS;
 //   BF16X3    every feature split x = hi + lo (bf16, round to nearest even),
 //             hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with fp32
 //             accumulation;
-//   BF16X4    adds lo*lo.
-// In both, fp32 accumulators are folded every few hundred rows into
+//   BF16X4    adds lo*lo;
+//   BF16X6    three pieces x = hi + mid + lo: hi*hi + hi*mid + mid*hi + mid*mid
+//             + hi*lo + lo*hi, every term down to 2^-16 of a product kept.
+// In all, fp32 accumulators are folded every few hundred rows into
 // compensated (TwoSum) fp32 pairs; fp64 appears only in the cross-workgroup
 // reduction at the end of the scan and in the merge.
 #include <hip/hip_runtime.h>
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     constexpr int NT = MODE >= 2 ? P1 : 1;
     constexpr int NHH = NT * (NT + 1) / 2;
     constexpr int NHL = NT * NT;
-    constexpr int NLL = MODE == 3 ? NHH : 1;
+    constexpr int NLL = MODE >= 3 ? NHH : 1;
 
     // ---- block set-up: tables zeroed, constant columns, thresholds ------------------
     if (TABLES) {
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             for (int ks = 0; ks < 2; ++ks) {
                 const int row0 = 32 * ks + 8 * (lane >> 4);
                 const uint32_t vbits = (uint32_t)(vm >> row0) & 0xFFu;
-                bf16x8 fh[NT], fl[NT];
+                bf16x8 fh[NT], fl[NT], fm[MODE == 4 ? NT : 1];
 #pragma unroll
                 for (int t2 = 0; t2 < NT; ++t2) {
                     const int st = lt[t2].stride;
@@ -473,7 +475,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         for (int i = 0; i < 8; ++i)
                             if (!((vbits >> i) & 1u)) x[i] = 0.f;
                     }
-                    split_bf16x8(x, fh[t2], fl[t2]);
+                    if (MODE == 4) split3_bf16x8(x, fh[t2], fm[MODE == 4 ? t2 : 0], fl[t2]);
+                    else split_bf16x8(x, fh[t2], fl[t2]);
                 }
                 int ih = 0;
 #pragma unroll
@@ -482,12 +485,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                     for (int u = t2; u < NT; ++u, ++ih) {
                         chh[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t2], fh[u], chh[ih], 0, 0, 0);
                         if (MODE == 3) cll[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[t2], fl[u], cll[ih], 0, 0, 0);
+                        if (MODE == 4) cll[ih] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm[MODE == 4 ? t2 : 0], fm[MODE == 4 ? u : 0], cll[ih], 0, 0, 0);
                     }
 #pragma unroll
                 for (int t2 = 0; t2 < NT; ++t2)
 #pragma unroll
                     for (int u = 0; u < NT; ++u)
                         chl[t2 * NT + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t2], fl[u], chl[t2 * NT + u], 0, 0, 0);
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2)
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+                        if (MODE == 4)   // hi*mid and hi*lo share the full-square accumulators
+                            chl[t2 * NT + u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[t2], fm[MODE == 4 ? u : 0], chl[t2 * NT + u], 0, 0, 0);
             }
             if (++tiles_since_flush == kFlushTiles) {
                 const f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -498,6 +508,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         }
 
         // ---- grouped tables (this lane's own row) ---------------------------------------------
+        if (TABLES && d.hcodes && row < w_end) {
+            // component codes for the count-table scan: every row of the range once, 0xFFFF when
+            // the row does not join
+            const AS_CONST int32_t *hcomp = cst(d.hcode_comp);
+            uint16_t *hc = d.hcodes + row;
+            for (int j = 0; j < d.n_hcodes; ++j) {
+                const uint32_t v = valid ? W[d.w_comp + hcomp[j] * 64 + lane] : (uint32_t)kNoCode;
+                gst(hc)[(int64_t)j * d.hcode_pitch] = (uint16_t)v;
+            }
+        }
         if (TABLES && d.codes) {
             // per-row codes for the partitioned table scan; rows past the range write nothing
             if (row < w_end) {
@@ -632,7 +652,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     if (MODE >= 2 && do_gram) {
         const int n16 = NT * 16;
         double *rhh = red, *rhl = red + n16 * n16, *rll = red + 2 * n16 * n16;
-        const int nred = (MODE == 3 ? 3 : 2) * n16 * n16;
+        const int nred = (MODE >= 3 ? 3 : 2) * n16 * n16;
         for (int i = tid; i < nred; i += blockDim.x) red[i] = 0.0;
         __syncthreads();
         const int ci = 4 * (lane >> 4), cj = lane & 15;
@@ -644,7 +664,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     atomicAdd(&rhh[(16 * t + ci + e) * n16 + 16 * u + cj], (double)shh[ih][e] + (double)chh[ih][e]);
-                    if (MODE == 3) atomicAdd(&rll[(16 * t + ci + e) * n16 + 16 * u + cj], (double)cll[ih][e]);
+                    if (MODE >= 3) atomicAdd(&rll[(16 * t + ci + e) * n16 + 16 * u + cj], (double)cll[ih][e]);
                 }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -660,7 +680,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             const int i = e / d.n_gram, j = e % d.n_gram;
             if (i <= j) {
                 double v = rhh[i * n16 + j] + rhl[i * n16 + j] + rhl[j * n16 + i];
-                if (MODE == 3) v += rll[i * n16 + j];
+                if (MODE >= 3) v += rll[i * n16 + j];
                 gst(out)[tri_index(i, j, d.n_gram)] = v;
             }
         }
@@ -781,6 +801,79 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// count tables from 16-bit component codes (see HistDesc): one workgroup of
+// 1024 threads per (row block, partition); a thread takes eight consecutive
+// rows per step (one 16-byte load per code column) and counts each row into
+// the slices of its partition that hold its cell
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void hist_scan_kernel(const HistDesc *__restrict__ dp) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    const AS_CONST HistDesc &d = *cst(dp);
+    const int part = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int s0 = cst(d.part_begin)[part], s1 = cst(d.part_begin)[part + 1];
+    const int words = cst(d.lds_words)[part];
+    for (int i = tid; i < words; i += blockDim.x) smem[i] = 0u;
+    __syncthreads();
+    const AS_CONST HistSlice *sl = cst(d.slices);
+    const int64_t r0 = (int64_t)blockIdx.x * d.rows_per_block;
+    const int64_t r1 = r0 + d.rows_per_block < d.n_rows ? r0 + d.rows_per_block : d.n_rows;
+    const uint16_t *codes = d.codes;
+    for (int64_t r = r0 + 8 * tid; r < r1; r += 8 * (int64_t)blockDim.x) {
+        // rows past the end are masked (the columns are padded to 64 rows, so the loads stay inside)
+        const int nv = r1 - r < 8 ? (int)(r1 - r) : 8;
+        for (int si = s0; si < s1; ++si) {
+            const AS_CONST HistSlice &S = sl[si];
+            uint32_t cell[8];
+            bool ok[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                cell[i] = 0u;
+                ok[i] = i < nv;
+            }
+            for (int c = 0; c < S.n_comp; ++c) {
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 v = gld(reinterpret_cast<const u32x4 *>(codes + (int64_t)S.code[c] * d.pitch + r))[0];
+                const uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+                const uint32_t st = (uint32_t)S.stride[c];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t x = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+                    if (x == kNoCode) ok[i] = false;
+                    cell[i] += x * st;
+                }
+            }
+            const uint32_t base = (uint32_t)S.lds_off + (uint32_t)(lane & (S.reps - 1)) * (uint32_t)S.rep_stride;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t k = cell[i] - (uint32_t)S.lo;
+                if (ok[i] && k < (uint32_t)S.n) atomicAdd(&smem[base + k], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int si = s0; si < s1; ++si) {
+        const AS_CONST HistSlice &S = sl[si];
+        for (int k = tid; k < S.n; k += blockDim.x) {
+            uint32_t c = 0u;
+            for (int rp = 0; rp < S.reps; ++rp) c += smem[S.lds_off + rp * S.rep_stride + k];
+            if (c) gadd(d.g_cnt + S.glb_cnt + S.lo + k, (unsigned long long)c);
+        }
+    }
+}
+
+hipError_t set_hist_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute((const void *)hist_scan_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_hist(const HistDesc *desc, int grid_x, int parts, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(hist_scan_kernel, dim3(grid_x, parts), dim3(1024), lds_bytes, st, desc);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -949,6 +1042,14 @@ RootKernel root_kernel(int mode, int p1, bool tables) {
                 case 2: return pick_tables<3, 2>(tables);
                 case 3: return pick_tables<3, 3>(tables);
                 case 4: return pick_tables<3, 4>(tables);
+            }
+            return nullptr;
+        case 4:
+            switch (p1) {
+                case 1: return pick_tables<4, 1>(tables);
+                case 2: return pick_tables<4, 2>(tables);
+                case 3: return pick_tables<4, 3>(tables);
+                case 4: return pick_tables<4, 4>(tables);
             }
             return nullptr;
     }

@@ -22,7 +22,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NOT_ACYCLIC", -3: "UNKNOWN_ATTR", -4: "TYPE", 
 I32, F32 = 0, 1
 KEY, CONT, CAT = 0, 1, 2
 OPS = {"le": 0, "lt": 1, "ge": 2, "gt": 3, "eq": 4, "ne": 5}
-PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x4": 2}
+PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x4": 2, "bf16x6": 3}
 SCHEDULE = {"plain": 0, "batched": 1}
 PLANNER = {"heuristic": 0, "autotune": 1, "learned": 2}
 N_FEATURES = 16
@@ -66,7 +66,7 @@ class _PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("planner", ctypes.c_int32),
                 ("block_rows", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32),
                 ("cost_model", ctypes.c_char_p), ("scan_every_table", ctypes.c_int32),
-                ("no_row_codes", ctypes.c_int32)]
+                ("no_row_codes", ctypes.c_int32), ("no_hist", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -77,7 +77,8 @@ class _Stats(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32), ("lds_tables", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("nbuf", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("dedicated_scan", ctypes.c_int32), ("derived_tables", ctypes.c_int32),
-                ("strided_families", ctypes.c_int32), ("code_scan", ctypes.c_int32)]
+                ("strided_families", ctypes.c_int32), ("code_scan", ctypes.c_int32),
+                ("hist_scan", ctypes.c_int32), ("hist_parts", ctypes.c_int32)]
 
 
 # every symbol the header declares
@@ -86,7 +87,8 @@ SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relat
            "lmfao_result_layout", "lmfao_bind", "lmfao_bind_scratch", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
            "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
-           "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train"]
+           "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train",
+           "lmfao_measure_peak"]
 
 _lib = None
 
@@ -134,6 +136,8 @@ def load(path: str = LIB_PATH):
         "lmfao_adam_step": (st, [i32, P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, P]),
         "lmfao_mlp_train": (st, [i32, P, P, P, P, P, i32, i32, ctypes.c_float, P, P, P, P]),
+        "lmfao_measure_peak": (st, [i32, P, sz, i32, P, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -240,14 +244,16 @@ class Context:
 
     # ---- planning --------------------------------------------------------------------
     def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0,
-             rollup=True, row_codes=True):
+             rollup=True, row_codes=True, hist=True):
         """``rollup``: tables one group-by component short of another table with
         the same filter are summed from it after the scan (``scan_every_table``
         = 0); False makes the scan update every table.  ``row_codes``: filtered
         tables over several LDS partitions are updated from per-row codes when
-        they qualify (``no_row_codes`` = 0)."""
+        they qualify (``no_row_codes`` = 0).  ``hist``: unfiltered COUNT-only
+        tables beyond the root scan's LDS are counted by the count-table scan
+        from 16-bit component codes (``no_hist`` = 0)."""
         o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None,
-                      0 if rollup else 1, 0 if row_codes else 1)
+                      0 if rollup else 1, 0 if row_codes else 1, 0 if hist else 1)
         self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
 
     def stats(self) -> dict:
@@ -338,7 +344,7 @@ class Engine:
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
-                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True, scratch=False):
+                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True, scratch=False, hist=True):
         import torch
         self.torch = torch
         self.db = db
@@ -358,8 +364,8 @@ class Engine:
         for q in self.queries:
             self.ctx.add_query(q)
         self.precision, self.schedule, self.rollup, self.row_codes = precision, schedule, rollup, row_codes
-        self.scratch = scratch
-        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes)
+        self.scratch, self.hist = scratch, hist
+        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes, hist)
         self._bind()
 
     def _bind(self):
@@ -384,7 +390,8 @@ class Engine:
     def replan(self, precision=None, schedule=None, planner="heuristic", grid_blocks=0, gram_block=0):
         self.precision = precision or self.precision
         self.schedule = schedule or self.schedule
-        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup, self.row_codes)
+        self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup, self.row_codes,
+                      self.hist)
         self._bind()
 
     def run(self, stream=None):
@@ -466,3 +473,16 @@ def mlp_train(hidden: int, params, x, target, epochs: int, lr: float, stream=Non
     _check(lib.lmfao_mlp_train(hidden, _ptr(params), _ptr(m), _ptr(v), _ptr(x), _ptr(target), n, epochs, lr,
                                _ptr(grad), _ptr(scratch), _ptr(losses), _stream_handle(stream)), "mlp_train")
     return losses
+
+
+PEAKS = {"read": 0, "lds_u32": 1, "lds_u32_spread": 2, "lds_f64": 3, "global_u64": 4}
+
+
+def measure_peak(kind: str, buf, iters: int, stream=None):
+    """Time one throughput probe (lmfao_measure_peak) on a device tensor ``buf``;
+    returns (milliseconds, bytes read or atomics issued)."""
+    load()
+    ms, units = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.lmfao_measure_peak(PEAKS[kind], _ptr(buf), buf.numel() * buf.element_size(), iters,
+                                   _stream_handle(stream), ctypes.byref(ms), ctypes.byref(units)), "measure_peak")
+    return ms.value, units.value

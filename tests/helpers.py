@@ -108,14 +108,29 @@ def bf16_split(x):
     return hi.astype(np.float64), lo.astype(np.float64)
 
 
-def split_gram(columns, four):
-    """The covariance block the BF16 split computes, over features
-    [1, columns...] of the materialised join: sum of hi*hi + hi*lo + lo*hi
-    (+ lo*lo), every product exact in float64 (8-bit significands)."""
+def bf16_split3(x):
+    """x = hi + mid + lo (+ a remainder below 2^-24 |x|): hi = bf16(x),
+    mid = bf16(x - hi), lo = bf16(x - hi - mid), round to nearest even, as exact
+    float64 (the split of the BF16X6 form)."""
+    x = np.asarray(x, np.float32)
+    hi, mid = bf16_split(x)
+    r = (x.astype(np.float64) - hi - mid).astype(np.float32)     # exact: at most 8 significant bits left
+    lo, _ = bf16_split(r)
+    return hi, mid, lo
+
+
+def split_gram(columns, products):
+    """The covariance block a BF16 split form computes, over features
+    [1, columns...] of the materialised join, every product exact in float64
+    (8-bit significands): products = 3 (hi*hi + hi*lo + lo*hi), 4 (+ lo*lo), or
+    6 (three pieces: hi*hi + hi*mid + mid*hi + mid*mid + hi*lo + lo*hi)."""
     n = len(columns[0]) if columns else 0
     X = np.stack([np.ones(n, np.float32)] + [np.asarray(c, np.float32) for c in columns], axis=1)
+    if products == 6:
+        H, M, L = bf16_split3(X)
+        return H.T @ H + H.T @ M + M.T @ H + M.T @ M + H.T @ L + L.T @ H
     H, L = bf16_split(X)
     G = H.T @ H + H.T @ L + L.T @ H
-    if four:
+    if products == 4:
         G += L.T @ L
     return G

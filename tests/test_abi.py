@@ -321,9 +321,10 @@ def test_plan_option_errors():
     ctx = new_ctx()
     star(ctx)
     ctx.add_query(covariance(["f0"])[1])
-    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None, 0, 0)
-    for field, bad in (("precision", 3), ("schedule", 2), ("planner", 9), ("block_rows", 128), ("grid_blocks", -1),
-                       ("gram_block", 5), ("scan_every_table", 2), ("no_row_codes", -1)):
+    o = lmfao._PlanOpts(0, 1, 0, 0, 0, 0, None, 0, 0, 0)
+    for field, bad in (("precision", 4), ("precision", -1), ("schedule", 2), ("planner", 9), ("block_rows", 128),
+                       ("grid_blocks", -1), ("gram_block", 5), ("scan_every_table", 2), ("no_row_codes", -1),
+                       ("no_hist", 2)):
         x = lmfao._PlanOpts.from_buffer_copy(o)
         setattr(x, field, bad)
         assert ctx.lib.lmfao_plan(ctx.ptr, ctypes.byref(x)) == -1, field
@@ -384,3 +385,39 @@ def test_row_codes_are_planned_for_partitioned_filtered_tables():
     assert _plan_db(db, qs, schedule="plain").stats()["code_scan"] == 0
     db5 = make_database(5)
     assert _plan_db(db5, make_batch(5, db5)).stats()["code_scan"] == 0   # unfiltered pair counts
+
+
+def test_count_tables_are_planned_beyond_the_root_scans_lds():
+    """Unfiltered COUNT-only tables that the root scan cannot hold in one LDS
+    partition (the 105 pair counts of the mutual-information batch) move to
+    the count-table scan: one more launch, 2 bytes of workspace per component
+    code and row, tables cut into LDS slices packed into partitions.  Small
+    pair tables that fit the root scan's LDS (workload 1's single grouped
+    table), the plain schedule and no_hist keep the root scan's updates."""
+    from datagen import make_batch, make_database
+    db5 = make_database(5)
+    qs5 = make_batch(5, db5)
+    on, off = _plan_db(db5, qs5), _plan_db(db5, qs5, hist=False)
+    s_on, s_off = on.stats(), off.stats()
+    assert s_on["hist_scan"] == 1 and s_off["hist_scan"] == 0 and s_off["hist_parts"] == 0
+    assert s_on["launches"] == s_off["launches"] + 1
+    # every pair table's cells are in some partition: at least cells / LDS-words partitions
+    pair_cells = sum(q.n_cells(db5) for q in qs5 if len(q.groupby) == 2)
+    assert s_on["hist_parts"] >= pair_cells // (160 * 1024 // 4)
+    n_rows = db5.relations[0].n_rows
+    assert on.workspace_size() - off.workspace_size() >= 15 * ((n_rows + 63) // 64 * 64) * 2
+    assert _plan_db(db5, qs5, schedule="plain").stats()["hist_scan"] == 0
+    db1 = make_database(1)
+    assert _plan_db(db1, make_batch(1, db1)).stats()["hist_scan"] == 0
+
+
+def test_scratch_binding_needs_a_plan_and_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only error paths")
+    ctx = new_ctx()
+    star(ctx)
+    ctx.add_query(covariance(["f0"])[0])
+    expect("STATE", lambda: ctx.bind_scratch(FAKE, 1 << 20))
+    ctx.plan()
+    expect("HIP", lambda: ctx.bind_scratch(FAKE, 1 << 20))

@@ -9,7 +9,7 @@ on the dedicated BF16 scan, values N(100, 1)).  Every aggregate of every
 batch is compared with the oracle: counts bit for bit, sums under
 tests/helpers.check_sums at 1e-6 (fp32 with fp64 merge) and 1e-5 (bf16 hi+lo
 split).  Each batch runs in the launch configuration the benchmark times
-(bf16x3, batched schedule captured in a hipGraph, tiles chosen by the
+(bf16x6, batched schedule captured in a hipGraph, tiles chosen by the
 learned cost model judged by timing, else by the autotuner) and in the plain
 form (fp32, one launch per view), and the mixed batches also batched in fp32.
 """
@@ -25,7 +25,7 @@ from tests.helpers import compare_results
 
 pytestmark = pytest.mark.gpu
 
-RTOL = {"fp32": 1e-6, "bf16x3": 1e-5}
+RTOL = {"fp32": 1e-6, "bf16x6": 1e-5}
 
 
 def _bench_engine(db, qs, precision, stream):
@@ -51,8 +51,8 @@ def test_random_batch_parity(j):
           flush=True)
     ref = oracle.evaluate(db, qs)
     stream = torch.cuda.Stream()
-    eng = _bench_engine(db, qs, "bf16x3", stream)
-    compare_results(eng.results(), ref, qs, RTOL["bf16x3"], "random %d bf16x3 batched" % j)
+    eng = _bench_engine(db, qs, "bf16x6", stream)
+    compare_results(eng.results(), ref, qs, RTOL["bf16x6"], "random %d bf16x6 batched" % j)
     for sched in ("batched", "plain"):
         eng = Engine(db, qs, precision="fp32", schedule=sched)
         eng.run()
@@ -68,9 +68,9 @@ def test_random_covariance_parity(j):
           (j, [r.n_rows for r in db.relations], len(qs)), flush=True)
     ref = oracle.evaluate(db, qs)
     stream = torch.cuda.Stream()
-    eng = _bench_engine(db, qs, "bf16x3", stream)
+    eng = _bench_engine(db, qs, "bf16x6", stream)
     assert eng.stats()["dedicated_scan"] == 1
-    compare_results(eng.results(), ref, qs, RTOL["bf16x3"], "covariance %d bf16x3" % j)
+    compare_results(eng.results(), ref, qs, RTOL["bf16x6"], "covariance %d bf16x6" % j)
     eng = Engine(db, qs, precision="fp32", schedule="plain")
     eng.run()
     compare_results(eng.results(), ref, qs, RTOL["fp32"], "covariance %d fp32 plain" % j)
@@ -116,7 +116,7 @@ def _ties_queries():
     return qs
 
 
-@pytest.mark.parametrize("precision,schedule", [("fp32", "batched"), ("fp32", "plain"), ("bf16x3", "batched")])
+@pytest.mark.parametrize("precision,schedule", [("fp32", "batched"), ("fp32", "plain"), ("bf16x6", "batched")])
 def test_values_equal_to_thresholds_and_constants(precision, schedule):
     """x = t falls in the bucket of t (x <= t_k <=> bucket <= k), and each
     comparison operator differs from its strict or non-strict twin exactly on

@@ -76,3 +76,27 @@ def test_a_repeated_value_keeps_its_error():
         e, a3, a4 = (np.sum(t) for t in products(np.full(1000, worst), np.full(1000, worst)))
         a = a3 if approx is x3 else a4
         assert 1e-5 < abs(a - e) / e <= 3 * 2.0 ** -16
+
+
+def test_three_piece_split_keeps_every_term_to_2_to_minus_16():
+    """x = hi + mid + lo + r with |r| <= 2^-24 |x|; the six products hi*hi +
+    hi*mid + mid*hi + mid*mid + hi*lo + lo*hi drop only terms of order 2^-24
+    (mid*lo, lo*mid, lo*lo and those of r): below 4 * 2^-24 per product, so even
+    a sum of one repeated value stays far inside 1e-5."""
+    from tests.helpers import bf16_split3
+    rng = np.random.default_rng(3)
+    x = rng.normal(3, 1, 500_000).astype(np.float32) * np.float32(10) ** rng.integers(-3, 4, 500_000).astype(np.float32)
+    y = rng.normal(-2, 5, 500_000).astype(np.float32)
+    hx, mx, lx = bf16_split3(x)
+    assert np.all(np.abs(x.astype(np.float64) - hx - mx - lx) <= 2.0 ** -24 * np.abs(x.astype(np.float64)))
+    hy, my, ly = bf16_split3(y)
+    exact = x.astype(np.float64) * y.astype(np.float64)
+    six = hx * hy + hx * my + mx * hy + mx * my + hx * ly + lx * hy
+    assert np.max(np.abs(six - exact) / np.abs(exact)) <= 4 * 2.0 ** -24
+    # the worst value of the three-product form, repeated: six products stay below 1e-6
+    v = rng.uniform(1, 8, 2_000_000).astype(np.float32)
+    e3 = np.abs(products(v, v)[1] - v.astype(np.float64) ** 2) / v.astype(np.float64) ** 2
+    w = v[np.argmax(e3)]
+    h, m, l = (float(t[0]) for t in bf16_split3(np.array([w], np.float32)))
+    assert e3.max() > 1e-5
+    assert abs(h * h + 2 * h * m + m * m + 2 * h * l - float(w) ** 2) / float(w) ** 2 < 1e-6

@@ -39,7 +39,7 @@ def test_scratch_binding_matches_caller_workspace_twice_second_smaller():
     import torch
     from paper_1906_08687_amd.lmfao import LmfaoError
     # first call: the covariance batch (dedicated BF16 scan), 300k fact rows
-    ref1, eng1, o1 = _pair(4, 300_007, "bf16x3")
+    ref1, eng1, o1 = _pair(4, 300_007, "bf16x6")
     assert eng1.ctx.workspace_size() <= 64 << 20
     eng1.run()
     _same(eng1.results(), ref1.results(), o1, 1e-5, "scratch, covariance 300k")
@@ -68,5 +68,5 @@ def test_scratch_binding_refuses_a_workspace_above_its_size():
     db = make_database(4, n_fact=100_000, dims=(2_000_000, 1_000, 100, 10))
     qs = make_batch(4, db)
     with pytest.raises(LmfaoError) as e:
-        Engine(db, qs, precision="bf16x3", scratch=True)
+        Engine(db, qs, precision="bf16x6", scratch=True)
     assert e.value.code == "WORKSPACE"

@@ -209,7 +209,9 @@ typedef struct {
     int32_t block_rows;          /* fact rows per workgroup of the root scan (a multiple of 64 * waves) */
     int32_t grid_blocks;         /* workgroups of the root scan */
     int32_t gram_block;          /* FP32: register block edge; BF16: padded feature count */
-    int32_t lds_tables;          /* grouped tables: 0 global atomics, 1 greedy LDS, 2 partitioned LDS */
+    int32_t lds_tables;          /* grouped tables: 0 global atomics, 1 greedy LDS, 2 partitioned LDS (the root
+                                    scan rescans per partition), 3 partitioned LDS with per-row codes and the
+                                    count-table scan where they apply (the heuristic choice) */
     int32_t waves;               /* waves per workgroup of the root scan */
     int32_t nbuf;                /* staging buffers per wave (2: next tile copied during this one) */
     int32_t lds_bytes;           /* dynamic LDS of the root scan workgroup */
@@ -292,7 +294,10 @@ lmfao_status lmfao_time_root_group(lmfao_ctx *ctx, void *hip_stream, int32_t war
 
 /* Number of candidate tile configurations of the current plan, and the
  * candidate `i` as {waves per workgroup, staging buffers per wave, workgroups,
- * fp32 register block edge (0 for bf16), table placement policy}. */
+ * fp32 register block edge (0 for bf16), table placement policy (as
+ * lmfao_stats.lds_tables)}.  Candidates vary the tile configuration and the
+ * grouping of tables: all global, greedy LDS, LDS partitions rescanned by the
+ * root scan, or LDS partitions fed by per-row codes or the count-table scan. */
 lmfao_status lmfao_candidates(const lmfao_ctx *ctx, int32_t *n);
 lmfao_status lmfao_candidate(const lmfao_ctx *ctx, int32_t i, int32_t cfg[5]);
 
@@ -359,6 +364,102 @@ enum {
  * engine's entry points do not use it. */
 lmfao_status lmfao_measure_peak(int32_t kind, void *buf, size_t buf_bytes, int32_t iters, void *hip_stream,
                                 double *ms, double *units);
+
+/* ---- application loops on the device (Section 2) ------------------------ */
+
+/* Ridge linear regression by batch gradient descent over the non-centred
+ * covariance matrix (Section 2, linear regression): `cov` is a device array of
+ * n x n doubles, row-major and symmetric, over the vector [1, X_1, ...]
+ * (cov[0] = |D|, the count), `label` (1..n-1) the index of the response,
+ * whose coefficient is fixed at -1.  Minimises
+ *     J = 1/(2|D|) sum (theta . X)^2 + lambda/2 |theta_free|^2
+ * with Barzilai-Borwein step sizes (the first 1/(trace/|D| + lambda)) until the
+ * gradient norm is at most tol times its first value or max_iters steps ran,
+ * all in one launch on `hip_stream`.  Writes theta[n] (device; -1 at the label)
+ * and info[3] (device: J, steps taken, final gradient norm).  n <= 64, else
+ * INVALID_ARG, as for a label outside 1..n-1, lambda < 0 or tol < 0. */
+lmfao_status lmfao_ridge_bgd(const double *cov, int32_t n, int32_t label, double lambda, int32_t max_iters,
+                             double tol, double *theta, double *info, void *hip_stream);
+
+/* Mutual information of attribute pairs (Section 2, equation (7)) from their
+ * pairwise COUNT GROUP BY tables: tables[p] (a device array of device pointers)
+ * points at dom_a x dom_b u64 counts, row-major, with doms[2p], doms[2p+1]
+ * (device int32); mi[p] (device) receives sum over nonzero cells of
+ * delta/alpha * log(alpha * delta / (beta * gamma)), alpha the total and
+ * beta, gamma the row and column sums (natural log; 0 for an empty table).
+ * max_dom bounds every domain (at most 2048, else TOO_LARGE). */
+lmfao_status lmfao_mutual_information(const unsigned long long *const *tables, const int32_t *doms, int32_t n_pairs,
+                                      int32_t max_dom, double *mi, void *hip_stream);
+
+/* Chow-Liu tree over n attributes (2..64, else INVALID_ARG / TOO_LARGE):
+ * `mi` is a device n x n symmetric array of mutual informations; pairs
+ * (i < j) are taken by decreasing value (equal values: lower pair index i, j
+ * in row-major order first) when they join two components.  Writes
+ * edges[2 * (n - 1)] (device int32 pairs i, j in the order taken) and
+ * total[1] (device: the sum of their mutual informations). */
+lmfao_status lmfao_chow_liu(const double *mi, int32_t n, int32_t *edges, double *total, void *hip_stream);
+
+enum { LMFAO_SPLIT_VARIANCE = 0, LMFAO_SPLIT_GINI = 1 };
+
+typedef struct {
+    const uint64_t *counts;   /* device: VARIANCE [n_cells]; GINI [n_labels][n_cells] */
+    const double *sums;       /* device, VARIANCE only: cell c's SUM(y) at sums[c * sum_stride],
+                                 SUM(y^2) at sums[c * sum_stride + 1] */
+    int32_t sum_stride;
+    int32_t n_cells;          /* buckets (thresholds + 1) or categories of the split attribute */
+    int32_t categorical;      /* 0: split X <= t_c puts buckets 0..c left; 1: split X = c puts cell c left */
+    int32_t node;             /* tree node (0..n_nodes-1) these histograms belong to */
+} lmfao_split_input;
+
+typedef struct {
+    double cost;              /* lowest cost of the node's splits */
+    int32_t input;            /* its input (index into the inputs array), -1 if the node has none */
+    int32_t cell;             /* its threshold index (continuous) or category (categorical) */
+    int32_t pad;
+    int32_t pad2;
+} lmfao_split_result;
+
+/* Best split of every node of a decision-tree level (Section 2, decision
+ * trees) from per-(node, attribute) histograms, one workgroup per node:
+ * VARIANCE (regression trees): cost = sum y^2 - (sum y)^2 / n of both sides;
+ * GINI (classification trees, n_labels <= 16): cost = n (1 - sum_k p_k^2) of
+ * both sides.  Splits with an empty side are skipped; the lowest (cost,
+ * input, cell) wins.  `inputs` and `out[n_nodes]` are device arrays. */
+lmfao_status lmfao_best_splits(const lmfao_split_input *inputs, int32_t n_inputs, int32_t n_nodes, int32_t criterion,
+                               int32_t n_labels, lmfao_split_result *out, void *hip_stream);
+
+/* ---- training the cost model --------------------------------------------- */
+
+typedef struct {
+    int32_t hidden;     /* hidden units per layer (1..1024; see lmfao_mlp_param_count) */
+    int32_t epochs;     /* full-batch Adam steps (1..16384) */
+    float lr;           /* Adam step size */
+    int32_t pad;
+    uint64_t seed;      /* seed of the He-style initialisation */
+} lmfao_train_opts;
+
+/* Device workspace (bytes) lmfao_train_cost_model needs for the timing file
+ * `timing_db` (the lines lmfao_autotune appends) and `hidden` units, with room
+ * for up to 16384 epochs' losses.  INVALID_ARG for an unreadable or malformed
+ * file. */
+lmfao_status lmfao_train_workspace_size(const char *timing_db, int32_t hidden, size_t *bytes);
+
+/* Train the cost model of lmfao_choose_learned on the timings in `timing_db`
+ * and write its weights file `weights_out`.  Lines whose workload features
+ * (features 0, 1, 3-8, 12, 13: those that do not describe the tile candidate)
+ * agree form one workload; each line's target is min(log(ms / best ms of its
+ * workload), log 4).  Features and targets are standardised, the parameters
+ * drawn from `opts->seed`, and `opts->epochs` full-batch Adam steps run on the
+ * device (lmfao_mlp_train) on `hip_stream` inside the caller's 256-byte
+ * aligned `workspace` (lmfao_train_workspace_size bytes; the library
+ * allocates nothing).  *final_loss (may be NULL) receives the last step's
+ * mean squared error on the standardised targets.  Weights file: "LMFAOMLP",
+ * int32 hidden, float32 feature means[16] and scales[16], target mean and
+ * scale, then the parameters in the layout of lmfao_mlp_forward.  Errors:
+ * INVALID_ARG (bad options, unreadable or malformed timing file, unwritable
+ * output), WORKSPACE, HIP. */
+lmfao_status lmfao_train_cost_model(const char *timing_db, const char *weights_out, const lmfao_train_opts *opts,
+                                    void *workspace, size_t ws_bytes, void *hip_stream, float *final_loss);
 
 /* ---- cost-model network (hand-written device kernels) -------------------- */
 

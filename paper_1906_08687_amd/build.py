@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblmfao.so")
-SOURCES = ["kernels.hip", "gram_scan.hip", "mlp.hip", "peaks.hip", "engine.cpp"]
+SOURCES = ["kernels.hip", "gram_scan.hip", "mlp.hip", "peaks.hip", "apps.hip", "engine.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -10,7 +10,9 @@ pull the fit away from the near-optimal ones (workloads are told apart by the
 features that do not depend on the candidate).  Timings come from the
 engine itself: the exhaustive autotuner appends one line per timed candidate
 to a timing file; training runs on the device with the library's own
-forward/backward/Adam kernels; the planner queries the network through
+forward/backward/Adam kernels, inside the library (lmfao_train_cost_model
+builds the targets and the standardisation from the timing file); the planner
+queries the network through
 lmfao_choose_learned and keeps the heuristic configuration whenever the
 model is absent or predicts a non-finite time.
 
@@ -32,7 +34,7 @@ WEIGHTS = os.path.join(HERE, "weights.bin")
 N_FEATURES = lmfao.N_FEATURES
 
 
-def collect(workloads, timing_db: str, precision: str = "bf16x3", reps: int = 3, device: int = 0,
+def collect(workloads, timing_db: str, precision: str = "bf16x6", reps: int = 3, device: int = 0,
             log=None) -> List[Tuple[int, float]]:
     """Time every tile candidate of every workload (db, queries) and append
     the timings to ``timing_db``.  Returns (best candidate, best ms) per
@@ -92,27 +94,8 @@ def relative_log_ms(X: np.ndarray, ms: np.ndarray) -> np.ndarray:
     return np.minimum(y - best[g], RELATIVE_CAP)
 
 
-def train(X: np.ndarray, ms: np.ndarray, hidden: int = 32, epochs: int = 3000, lr: float = 3e-3,
-          device: int = 0, seed: int = 1):
-    """Fit the relative log time (relative_log_ms) on the device; returns (norm vector, params,
-    losses)."""
-    import torch
-    X = np.asarray(X, np.float64)
-    y = relative_log_ms(X, ms)
-    mean, std = X.mean(axis=0), X.std(axis=0)
-    std[std == 0] = 1.0
-    ym, ys = y.mean(), y.std() or 1.0
-    dev = torch.device("cuda", device)
-    xt = torch.from_numpy(((X - mean) / std).astype(np.float32)).to(dev).contiguous()
-    yt = torch.from_numpy(((y - ym) / ys).astype(np.float32)).to(dev).contiguous()
-    p = torch.from_numpy(init_params(hidden, seed)).to(dev)
-    losses = lmfao.mlp_train(hidden, p, xt, yt, epochs, lr)
-    torch.cuda.synchronize()
-    norm = np.concatenate([mean, std, [ym, ys]]).astype(np.float32)
-    return norm, p.cpu().numpy(), losses.cpu().numpy()
-
-
 def save(path: str, hidden: int, norm: np.ndarray, params: np.ndarray):
+    """Write a weights file in the library's layout (used by tests that build a model by hand)."""
     with open(path, "wb") as f:
         f.write(b"LMFAOMLP")
         f.write(struct.pack("<i", hidden))

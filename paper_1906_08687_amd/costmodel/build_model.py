@@ -1,21 +1,24 @@
 """Train the cost model on the device and measure what it gains.
 
-    python -m paper_1906_08687_amd.costmodel.build_model [--train 120] [--test 30]
-    python -m paper_1906_08687_amd.costmodel.build_model --collect 0 60      (timings only)
-    python -m paper_1906_08687_amd.costmodel.build_model --collect 0 30 --family cov
-    python -m paper_1906_08687_amd.costmodel.build_model --fit --test 30     (train and evaluate)
+    python -m paper_1906_08687_amd.costmodel.build_model --collect 0 110                (random batches)
+    python -m paper_1906_08687_amd.costmodel.build_model --collect 0 90 --family cov    (covariance stars)
+    python -m paper_1906_08687_amd.costmodel.build_model --fit --test 50 --test-cov 20 --report eval.json
 
-1. time every tile candidate of training workloads 0..train-1 with the
-   exhaustive autotuner (lmfao_autotune appends to the timing file): random
-   mixed batches (datagen.configs.random_workload, general root scan) and
-   random covariance-only star batches (random_covariance_workload, the
-   dedicated covariance scan, up to 100M fact rows);
-2. fit the network to log(ms) with the library's forward/backward/Adam
-   kernels and write the weights file;
-3. on held-out workloads 150.. of both families, and on the 100M-row
-   covariance benchmark batch, compare the root-scan time of the heuristic
-   tile choice, the learned choice and the autotuner's best:
-   gain = sum t(heuristic) / sum t(learned), regret = sum t(learned) / sum t(best).
+1. time every candidate (tile configuration and table grouping) of training
+   workloads j < 150 with the exhaustive autotuner (lmfao_autotune appends to
+   the timing file): random mixed batches (datagen.configs.random_workload,
+   general root scan) and random covariance-only star batches
+   (random_covariance_workload, the dedicated covariance scan, up to 100M fact
+   rows), in the benchmark's precision;
+2. train the network in the library (lmfao_train_cost_model: workload
+   grouping, relative log-time targets, standardisation and Adam on the
+   device) and write the weights file;
+3. on held-out workloads 150.. of both families (random batches up to 20M
+   fact rows), and on the 100M-row covariance benchmark batch, time the root
+   scan under the heuristic choice, the model's top choice, the model's top
+   four judged by timing together with the heuristic choice, and the
+   autotuner's best: gain = t(heuristic) / t(learned), regret =
+   t(learned) / t(autotuner's best), as sums and geometric means.
 """
 from __future__ import annotations
 
@@ -39,7 +42,9 @@ def main():
     ap.add_argument("--family", choices=["random", "cov"], default="random",
                     help="training workloads of --collect: random mixed batches or covariance-only stars")
     ap.add_argument("--max-rows", type=int, default=None,
-                    help="largest fact (default 8M for random batches, 100M for covariance stars)")
+                    help="largest fact of the training workloads (default 8M for random batches, 100M for "
+                         "covariance stars; held-out random batches go up to 20M)")
+    ap.add_argument("--precision", default="bf16x6")
     ap.add_argument("--test-cov", type=int, default=10, help="held-out covariance-only workloads")
     ap.add_argument("--no-bench-workload", action="store_true",
                     help="skip the 100M-row covariance benchmark batch in the evaluation")
@@ -55,7 +60,7 @@ def main():
     from datagen import make_batch, make_database
     from datagen.configs import random_covariance_workload, random_workload
     from .. import lmfao
-    from . import WEIGHTS, collect, load_db, save, train
+    from . import WEIGHTS, collect, load_db
 
     here = os.path.dirname(os.path.abspath(__file__))
     db_path = args.timing_db or os.path.join(here, "timings.csv")
@@ -70,7 +75,8 @@ def main():
         t0 = time.time()
         for j in range(args.collect[0], args.collect[1]):
             w = random_workload(j, rand_rows) if args.family == "random" else random_covariance_workload(j, cov_rows)
-            collect([w], db_path, log=lambda m, j=j: log("train %s %d: %s" % (args.family, j, m)))
+            collect([w], db_path, precision=args.precision,
+                    log=lambda m, j=j: log("train %s %d: %s" % (args.family, j, m)))
         log("collected workloads %d..%d in %.0fs" % (args.collect[0], args.collect[1] - 1, time.time() - t0))
         return 0
     t0 = time.time()
@@ -78,50 +84,65 @@ def main():
         if os.path.exists(db_path):
             os.remove(db_path)
         for j in range(args.train):
-            collect([random_workload(j, rand_rows)], db_path, log=lambda m, j=j: log("train %d: %s" % (j, m)))
+            collect([random_workload(j, rand_rows)], db_path, precision=args.precision,
+                    log=lambda m, j=j: log("train %d: %s" % (j, m)))
     X, cfg, ms = load_db(db_path)
     log("collected %d timings in %.0fs" % (len(ms), time.time() - t0))
-    norm, params, losses = train(X, ms, args.hidden, args.epochs, args.lr)
-    save(weights, args.hidden, norm, params)
-    log("trained: loss %.4f -> %.4f (standardised log ms)" % (losses[0], losses[-1]))
+    first = lmfao.train_cost_model(db_path, weights, args.hidden, 1, args.lr)
+    loss = lmfao.train_cost_model(db_path, weights, args.hidden, args.epochs, args.lr)
+    log("trained in the library: loss %.4f after one step, %.4f after %d (standardised relative log ms)" %
+        (first, loss, args.epochs))
 
     stream = torch.cuda.Stream()
 
     def evaluate(name, db, qs):
-        eng = lmfao.Engine(db, qs, precision="bf16x3")
+        eng = lmfao.Engine(db, qs, precision=args.precision)
         eng.run(stream)
         t_h = eng.ctx.time_root_group(stream, 2, 10)
-        best = eng.ctx.choose_learned(weights, stream)
+        top = eng.ctx.choose_learned(weights, stream)
         eng._bind()
         eng.run(stream)
         t_l = eng.ctx.time_root_group(stream, 2, 10)
-        eng.ctx.autotune(stream, None, 3)
+        eng.replan()
+        eng.run(stream)
+        ver = eng.ctx.choose_learned_verified(weights, stream, 4, 3)
+        eng._bind()
+        eng.run(stream)
+        t_v = eng.ctx.time_root_group(stream, 2, 10)
+        eng.ctx.autotune(stream, None, 2)
         eng._bind()
         eng.run(stream)
         t_b = eng.ctx.time_root_group(stream, 2, 10)
         dedicated = int(eng.stats()["dedicated_scan"])
-        log("test %s: %d fact rows, heuristic %.3f ms, learned %.3f ms, autotuned %.3f ms" %
-            (name, db.relations[0].n_rows, t_h, t_l, t_b))
+        n_cand = len(eng.ctx.candidates())
+        log("test %s: %d fact rows, %d candidates, heuristic %.3f ms, learned %.3f ms, learned top-4 timed %.3f ms, "
+            "autotuned %.3f ms" % (name, db.relations[0].n_rows, n_cand, t_h, t_l, t_v, t_b))
         del eng
         torch.cuda.empty_cache()
-        return {"workload": name, "fact_rows": int(db.relations[0].n_rows), "queries": len(qs),
-                "dedicated_scan": dedicated, "heuristic_ms": t_h, "learned_ms": t_l, "best_ms": t_b, "chosen": best}
+        return {"workload": name, "fact_rows": int(db.relations[0].n_rows), "queries": len(qs), "candidates": n_cand,
+                "dedicated_scan": dedicated, "heuristic_ms": t_h, "learned_ms": t_l, "learned_top4_timed_ms": t_v,
+                "best_ms": t_b, "chosen": top, "chosen_timed": ver}
 
     def summary(rows):
-        th = sum(r["heuristic_ms"] for r in rows)
-        tl = sum(r["learned_ms"] for r in rows)
-        tb = sum(r["best_ms"] for r in rows)
-        return {"workloads": len(rows), "sum_ms": {"heuristic": th, "learned": tl, "autotune_best": tb},
-                "gain_vs_heuristic": th / tl, "regret_vs_autotune": tl / tb,
-                "geomean_gain": float(np.exp(np.mean([np.log(r["heuristic_ms"] / r["learned_ms"]) for r in rows]))),
-                "geomean_regret": float(np.exp(np.mean([np.log(r["learned_ms"] / r["best_ms"]) for r in rows])))}
+        out = {"workloads": len(rows)}
+        th = [r["heuristic_ms"] for r in rows]
+        tb = [r["best_ms"] for r in rows]
+        for key, label in (("learned_ms", "learned"), ("learned_top4_timed_ms", "learned_top4_timed")):
+            tl = [r[key] for r in rows]
+            out[label] = {"sum_ms": sum(tl), "gain_vs_heuristic": sum(th) / sum(tl),
+                          "regret_vs_autotune": sum(tl) / sum(tb),
+                          "geomean_gain": float(np.exp(np.mean(np.log(np.array(th) / np.array(tl))))),
+                          "geomean_regret": float(np.exp(np.mean(np.log(np.array(tl) / np.array(tb)))))}
+        out["sum_ms"] = {"heuristic": sum(th), "autotune_best": sum(tb)}
+        return out
 
-    rand = [evaluate("random %d" % j, *random_workload(j, rand_rows)) for j in range(150, 150 + args.test)]
+    rand = [evaluate("random %d" % j, *random_workload(j, 20_000_000)) for j in range(150, 150 + args.test)]
     cov = [evaluate("covariance %d" % j, *random_covariance_workload(j, cov_rows))
            for j in range(150, 150 + args.test_cov)]
     report = {"train_workloads": args.train if not args.fit else "from " + os.path.basename(db_path),
-              "timings": int(len(ms)), "max_rows": {"random": rand_rows, "covariance": cov_rows},
-              "hidden": args.hidden, "epochs": args.epochs, "final_loss": float(losses[-1]),
+              "timings": int(len(ms)), "max_rows": {"train random": rand_rows, "held-out random": 20_000_000,
+                                                    "covariance": cov_rows},
+              "precision": args.precision, "hidden": args.hidden, "epochs": args.epochs, "final_loss": loss,
               "random": summary(rand), "covariance": summary(cov), "all": summary(rand + cov)}
     if not args.no_bench_workload:
         db = make_database(4, "full")

@@ -186,7 +186,8 @@ struct TileCfg {
     int nbuf = 0;           // staging buffers per wave (0 = heuristic)
     int grid_x = 0;         // requested workgroups (0 = heuristic)
     int gram_block = 0;     // fp32 register block edge
-    int lds_policy = -1;    // 0 global tables, 1 greedy LDS, 2 partitioned LDS (-1 = heuristic)
+    int lds_policy = -1;    // 0 global tables, 1 greedy LDS, 2 partitioned LDS, 3 partitioned LDS with
+                            // per-row codes and the count-table scan where they apply (-1 = heuristic)
 };
 
 struct RootLaunch {         // one launch of the root scan (batched: one; plain: one per view)
@@ -1216,7 +1217,7 @@ static void plan_hist(const lmfao_ctx *c, Plan &P, int budget) {
     P.hist_part_begin.clear();
     P.hist_lds_words.clear();
     const Rel &root = c->rels[P.root];
-    if (c->opts.no_hist || P.schedule != LMFAO_BATCHED || root.n_rows <= 0) return;
+    if (c->opts.no_hist || P.schedule != LMFAO_BATCHED || P.lds_policy != 3 || root.n_rows <= 0) return;
     std::vector<int> elig;
     bool spill = P.parts > 1;
     for (size_t f = 0; f < P.fams.size(); ++f) {
@@ -1316,7 +1317,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     const bool has_tables = !P.tables.empty();
     // table placement
     int policy = cfg.lds_policy;
-    if (policy < 0) policy = 2;
+    if (policy < 0) policy = 3;
     P.lds_policy = has_tables ? policy : 0;
     // waves per workgroup and staging buffers: the most resident waves per CU
     // (LDS-limited), two buffers when they fit next to the tables
@@ -1343,7 +1344,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     // tables and writes per-row codes; a code scan per partition, with the whole LDS for its
     // tables, replays them (when the codes fit their workspace cap)
     P.codes = false;
-    if (!c->opts.no_row_codes && P.schedule == LMFAO_BATCHED && P.lds_policy == 2 && P.parts > 1 && root.n_rows > 0 &&
+    if (!c->opts.no_row_codes && P.schedule == LMFAO_BATCHED && P.lds_policy == 3 && P.parts > 1 && root.n_rows > 0 &&
         codes_eligible(P)) {
         P.n_mask_codes = P.filters.size() > 32 ? 2 : 1;
         P.n_codes = P.n_mask_codes;
@@ -2436,7 +2437,13 @@ static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
         if (gbs.empty()) gbs.push_back(8);
     }
     std::vector<int> pols{0};
-    if (!P.tables.empty()) pols = {0, 1, 2};
+    if (!P.tables.empty()) {
+        pols = {0, 1, 2};
+        // 3 (partitions with per-row codes or the count-table scan) only where either applies
+        bool grouped = false;
+        for (auto &F : P.fams) grouped = grouped || F.hist || (F.filters.empty() && F.vals.empty());
+        if (grouped || codes_eligible(P)) pols.push_back(3);
+    }
     if (!P.root_launches.empty() && P.root_launches[0].gram && P.root_launches.size() == 1) {
         // the dedicated covariance scan: one record buffer, no register blocks or tables
         for (int wv : {1, 2, 4})
@@ -2622,6 +2629,177 @@ static bool load_weights(const char *path, int &hidden, std::vector<float> &norm
     if (!in) return false;
     hidden = h;
     return true;
+}
+
+// ---- training the cost model from the autotuner's timing file ------------------------------------
+//
+// One line per timed candidate: LMFAO_N_FEATURES features, the 5 configuration values of
+// lmfao_candidate, milliseconds.  Lines whose workload features (those not describing the tile
+// candidate) agree belong to one workload; a line's target is min(log(ms / best ms of its
+// workload), log 4): only the ranking inside a plan matters, and every candidate 4x slower than
+// the best is simply bad.  Features and targets are standardised (a constant feature keeps
+// scale 1), the parameters are drawn He-style from a SplitMix64 stream (normal values by
+// Box-Muller), and full-batch Adam runs on the device with the network's own kernels.
+static const int kWorkloadFeatures[] = {0, 1, 3, 4, 5, 6, 7, 8, 12, 13};
+
+struct Timings {
+    std::vector<float> x;        // [n][LMFAO_N_FEATURES]
+    std::vector<double> ms;
+};
+
+static bool read_timings(const char *path, Timings &T, std::string &err) {
+    std::ifstream in(path);
+    if (!in) { err = std::string("cannot open ") + path; return false; }
+    std::string line;
+    int ln = 0;
+    while (std::getline(in, line)) {
+        ++ln;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        std::vector<double> v;
+        std::stringstream ss(line);
+        std::string tok;
+        while (std::getline(ss, tok, ',')) {
+            char *end = nullptr;
+            const double d = strtod(tok.c_str(), &end);
+            if (end == tok.c_str()) { err = "bad number on line " + std::to_string(ln); return false; }
+            v.push_back(d);
+        }
+        if ((int)v.size() != LMFAO_N_FEATURES + 6 || !(v.back() > 0.0)) {
+            err = "line " + std::to_string(ln) + " is not 16 features, 5 configuration values and milliseconds > 0";
+            return false;
+        }
+        for (int f = 0; f < LMFAO_N_FEATURES; ++f) T.x.push_back((float)v[f]);
+        T.ms.push_back(v.back());
+    }
+    if (T.ms.empty()) { err = "no timings"; return false; }
+    return true;
+}
+
+static uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double unit_open(uint64_t &s) { return ((double)(splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+static size_t train_ws_bytes(int hidden, int n) {
+    const int np = lmfao_mlp_param_count(hidden);
+    return align_up((size_t)n * LMFAO_N_FEATURES * 4) + align_up((size_t)n * 4) + 4 * align_up((size_t)np * 4) +
+           align_up((size_t)lmfao_mlp_scratch_floats(hidden, n) * 4);
+}
+
+extern "C" lmfao_status lmfao_train_workspace_size(const char *timing_db, int32_t hidden, size_t *bytes) {
+    if (!timing_db || !bytes || lmfao_mlp_param_count(hidden) <= 0) return LMFAO_ERR_INVALID_ARG;
+    Timings T;
+    std::string err;
+    if (!read_timings(timing_db, T, err)) return LMFAO_ERR_INVALID_ARG;
+    *bytes = train_ws_bytes(hidden, (int)T.ms.size()) + (size_t)16 * 4 * 1024;   // + room for the losses
+    return LMFAO_OK;
+}
+
+extern "C" lmfao_status lmfao_train_cost_model(const char *timing_db, const char *weights_out,
+                                               const lmfao_train_opts *opts, void *workspace, size_t ws_bytes,
+                                               void *hip_stream, float *final_loss) {
+    if (!timing_db || !weights_out || !opts || !workspace || opts->epochs < 1 || opts->epochs > 16 * 1024 ||
+        !(opts->lr > 0.f) || lmfao_mlp_param_count(opts->hidden) <= 0)
+        return LMFAO_ERR_INVALID_ARG;
+    Timings T;
+    std::string err;
+    if (!read_timings(timing_db, T, err)) return LMFAO_ERR_INVALID_ARG;
+    const int n = (int)T.ms.size(), H = opts->hidden, np = lmfao_mlp_param_count(H);
+    if ((uintptr_t)workspace % kAlign || ws_bytes < train_ws_bytes(H, n) + (size_t)opts->epochs * 4)
+        return LMFAO_ERR_WORKSPACE;
+    // workloads and targets
+    std::map<std::vector<double>, int> group;
+    std::vector<int> g(n);
+    for (int i = 0; i < n; ++i) {
+        std::vector<double> key;
+        for (int f : kWorkloadFeatures) key.push_back(std::round((double)T.x[(size_t)i * LMFAO_N_FEATURES + f] * 1e4));
+        auto it = group.emplace(key, (int)group.size()).first;
+        g[i] = it->second;
+    }
+    std::vector<double> best(group.size(), INFINITY), y(n);
+    for (int i = 0; i < n; ++i) best[g[i]] = std::min(best[g[i]], std::log(T.ms[i]));
+    for (int i = 0; i < n; ++i) y[i] = std::min(std::log(T.ms[i]) - best[g[i]], std::log(4.0));
+    // standardisation
+    std::vector<float> norm(2 * LMFAO_N_FEATURES + 2);
+    for (int f = 0; f < LMFAO_N_FEATURES; ++f) {
+        double m = 0.0, q = 0.0;
+        for (int i = 0; i < n; ++i) m += T.x[(size_t)i * LMFAO_N_FEATURES + f];
+        m /= n;
+        for (int i = 0; i < n; ++i) {
+            const double d = T.x[(size_t)i * LMFAO_N_FEATURES + f] - m;
+            q += d * d;
+        }
+        double sd = std::sqrt(q / n);
+        if (sd == 0.0) sd = 1.0;
+        norm[f] = (float)m;
+        norm[LMFAO_N_FEATURES + f] = (float)sd;
+    }
+    double ym = 0.0, yq = 0.0;
+    for (double v : y) ym += v;
+    ym /= n;
+    for (double v : y) yq += (v - ym) * (v - ym);
+    double ys = std::sqrt(yq / n);
+    if (ys == 0.0) ys = 1.0;
+    norm[2 * LMFAO_N_FEATURES] = (float)ym;
+    norm[2 * LMFAO_N_FEATURES + 1] = (float)ys;
+    std::vector<float> xs((size_t)n * LMFAO_N_FEATURES), ts(n);
+    for (int i = 0; i < n; ++i) {
+        for (int f = 0; f < LMFAO_N_FEATURES; ++f)
+            xs[(size_t)i * LMFAO_N_FEATURES + f] =
+                (float)(((double)T.x[(size_t)i * LMFAO_N_FEATURES + f] - norm[f]) / norm[LMFAO_N_FEATURES + f]);
+        ts[i] = (float)((y[i] - ym) / ys);
+    }
+    // parameters: W1[H][16], b1[H], W2[H][H], b2[H], W3[H], b3 (He-style; biases zero)
+    std::vector<float> p(np, 0.f);
+    uint64_t rs = opts->seed;
+    auto normal = [&]() {
+        const double u1 = unit_open(rs), u2 = unit_open(rs);
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    size_t o = 0;
+    for (int i = 0; i < H * LMFAO_N_FEATURES; ++i) p[o++] = (float)(normal() * std::sqrt(2.0 / LMFAO_N_FEATURES));
+    o += H;
+    for (int i = 0; i < H * H; ++i) p[o++] = (float)(normal() * std::sqrt(2.0 / H));
+    o += H;
+    for (int i = 0; i < H; ++i) p[o++] = (float)(normal() * std::sqrt(1.0 / H));
+    // device buffers in the caller's workspace
+    uint8_t *w = static_cast<uint8_t *>(workspace);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { uint8_t *q = w + off; off += align_up(bytes); return q; };
+    float *dx = reinterpret_cast<float *>(take((size_t)n * LMFAO_N_FEATURES * 4));
+    float *dt = reinterpret_cast<float *>(take((size_t)n * 4));
+    float *dp = reinterpret_cast<float *>(take((size_t)np * 4));
+    float *dm = reinterpret_cast<float *>(take((size_t)np * 4));
+    float *dv = reinterpret_cast<float *>(take((size_t)np * 4));
+    float *dg = reinterpret_cast<float *>(take((size_t)np * 4));
+    float *dscr = reinterpret_cast<float *>(take((size_t)lmfao_mlp_scratch_floats(H, n) * 4));
+    float *dl = reinterpret_cast<float *>(w + off);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (hipMemcpyAsync(dx, xs.data(), xs.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dt, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dp, p.data(), p.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(dm, 0, (size_t)np * 4, st) != hipSuccess || hipMemsetAsync(dv, 0, (size_t)np * 4, st) != hipSuccess)
+        return LMFAO_ERR_HIP;
+    lmfao_status s = lmfao_mlp_train(H, dp, dm, dv, dx, dt, n, opts->epochs, opts->lr, dg, dscr, dl, hip_stream);
+    if (s != LMFAO_OK) return s;
+    float last = 0.f;
+    if (hipMemcpyAsync(p.data(), dp, p.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&last, dl + opts->epochs - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return LMFAO_ERR_HIP;
+    if (final_loss) *final_loss = last;
+    std::ofstream out(weights_out, std::ios::binary);
+    if (!out) return LMFAO_ERR_INVALID_ARG;
+    const int32_t h32 = H;
+    out.write("LMFAOMLP", 8);
+    out.write(reinterpret_cast<const char *>(&h32), 4);
+    out.write(reinterpret_cast<const char *>(norm.data()), norm.size() * 4);
+    out.write(reinterpret_cast<const char *>(p.data()), p.size() * 4);
+    return out ? LMFAO_OK : LMFAO_ERR_INVALID_ARG;
 }
 
 // Cost-model scores of every candidate (inference on the device, in the workspace).  Returns

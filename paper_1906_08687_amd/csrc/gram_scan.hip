@@ -133,6 +133,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         acc[p] = f32x4{0.f, 0.f, 0.f, 0.f};
         sacc[p] = acc[p];
     }
+    // six products: on a diagonal tile pair (a, a) the cross terms hi*mid + mid*hi and hi*lo + lo*hi
+    // are the transposes of each other, so hi*mid and hi*lo alone are accumulated here (one MFMA
+    // each instead of two) and added to their transposes when the partial is written; they are
+    // 2^-8 and 2^-16 of the block, so their fp32 chains need no second level
+    constexpr int NX = PM == 6 ? NT : 1;
+    f32x4 accx[NX];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) accx[a] = f32x4{0.f, 0.f, 0.f, 0.f};
     unsigned long long count = 0;
     int since_flush = 0;
 
@@ -313,18 +321,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             for (int b = a; b < NT; ++b, ++p)
                 acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B[b], acc[p], 0, 0, 0);
     };
+    // off-diagonal tile pairs (a < b) only
+    auto mfma_cross = [&](const bf16x8 *A, const bf16x8 *B) {
+        int p = 0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = a; b < NT; ++b, ++p)
+                if (b > a) acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[a], B[b], acc[p], 0, 0, 0);
+    };
     auto phase2 = [&]() {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             mfma_pass(oph[ks], oph[ks]);
             if (PM == 6) {
-                mfma_pass(oph[ks], opm[ks]);
-                mfma_pass(opm[ks], oph[ks]);
+                mfma_cross(oph[ks], opm[ks]);
+                mfma_cross(opm[ks], oph[ks]);
                 mfma_pass(opm[ks], opm[ks]);
+                mfma_cross(oph[ks], opl[ks]);
+                mfma_cross(opl[ks], oph[ks]);
+#pragma unroll
+                for (int a = 0; a < NX; ++a) {
+                    accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], opm[ks][a < NMID ? a : 0], accx[a], 0, 0, 0);
+                    accx[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oph[ks][a], opl[ks][a], accx[a], 0, 0, 0);
+                }
+            } else {
+                mfma_pass(oph[ks], opl[ks]);
+                mfma_pass(opl[ks], oph[ks]);
+                if (PM == 4) mfma_pass(opl[ks], opl[ks]);
             }
-            mfma_pass(oph[ks], opl[ks]);
-            mfma_pass(opl[ks], oph[ks]);
-            if (PM == 4) mfma_pass(opl[ks], opl[ks]);
         }
         if (++since_flush == kFlushTiles) {
 #pragma unroll
@@ -391,6 +416,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
 
     // ---- every wave writes its own partial: fp64 upper triangle, staged feature order ------
     // (each unordered feature pair is one slot pair: one lane of one accumulator owns it)
+    // The diagonal cross terms go through the wave's own LDS region (free after the last tile)
+    // so that each lane can read the transposed entry: xt[a][e] = accx[a] at (column, row).
+    float xt[NX][4];
+    if (PM == 6) {
+        float *tr = reinterpret_cast<float *>(reinterpret_cast<char *>(smem) + rbase);
+        wave_sync();
+#pragma unroll
+        for (int a = 0; a < NX; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tr[a * 256 + (4 * lg + e) * 16 + li] = accx[a][e];
+        wave_sync();
+#pragma unroll
+        for (int a = 0; a < NX; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xt[a][e] = tr[a * 256 + li * 16 + 4 * lg + e];
+    }
     const int ng = d.n_gram;
     const int pidx = blockIdx.x * nwaves + wave;
     double *out = d.gram_partial + (int64_t)pidx * (ng * (ng + 1) / 2);
@@ -408,7 +449,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     if (a == b && sa > sb) continue;
                     const int fa = gld(&dp->slot[sa].feat)[0];
                     if (fa < 0 || fb < 0) continue;
-                    gst(out)[tri_index(min(fa, fb), max(fa, fb), ng)] = (double)sacc[p][e] + (double)acc[p][e];
+                    double v = (double)sacc[p][e] + (double)acc[p][e];
+                    if (PM == 6 && a == b) v += (double)accx[a < NX ? a : 0][e] + (double)xt[a < NX ? a : 0][e];
+                    gst(out)[tri_index(min(fa, fb), max(fa, fb), ng)] = v;
                 }
             }
     }

@@ -810,8 +810,11 @@ __global__ __launch_bounds__(1024) void code_scan_kernel(const CodeScanDesc *__r
 // the slices of its partition that hold its cell
 // ---------------------------------------------------------------------------
 
+constexpr int kHistChunks = 4;   // 8-row chunks per thread and slice whose loads are issued together
+
 __global__ __launch_bounds__(1024) void hist_scan_kernel(const HistDesc *__restrict__ dp) {
     extern __shared__ __align__(16) uint32_t smem[];
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const AS_CONST HistDesc &d = *cst(dp);
     const int part = blockIdx.y;
     const int tid = threadIdx.x;
@@ -824,35 +827,55 @@ __global__ __launch_bounds__(1024) void hist_scan_kernel(const HistDesc *__restr
     const int64_t r0 = (int64_t)blockIdx.x * d.rows_per_block;
     const int64_t r1 = r0 + d.rows_per_block < d.n_rows ? r0 + d.rows_per_block : d.n_rows;
     const uint16_t *codes = d.codes;
-    for (int64_t r = r0 + 8 * tid; r < r1; r += 8 * (int64_t)blockDim.x) {
-        // rows past the end are masked (the columns are padded to 64 rows, so the loads stay inside)
-        const int nv = r1 - r < 8 ? (int)(r1 - r) : 8;
+    // per step the workgroup covers kHistChunks consecutive stretches of 8 * blockDim rows; thread
+    // t takes 8 rows of each, so every load instruction of a wave reads 1 KiB contiguous, and the
+    // loads of all chunks and components of a slice are in flight together
+    const int64_t span = 8 * (int64_t)blockDim.x;
+    for (int64_t r = r0; r < r1; r += kHistChunks * span) {
         for (int si = s0; si < s1; ++si) {
             const AS_CONST HistSlice &S = sl[si];
-            uint32_t cell[8];
-            bool ok[8];
+            u32x4 v[kHistChunks][kMaxKeyComps];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                cell[i] = 0u;
-                ok[i] = i < nv;
-            }
-            for (int c = 0; c < S.n_comp; ++c) {
-                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                const u32x4 v = gld(reinterpret_cast<const u32x4 *>(codes + (int64_t)S.code[c] * d.pitch + r))[0];
-                const uint32_t w[4] = {v[0], v[1], v[2], v[3]};
-                const uint32_t st = (uint32_t)S.stride[c];
+            for (int j = 0; j < kHistChunks; ++j) {
+                const int64_t row = r + j * span + 8 * tid;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const uint32_t x = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
-                    if (x == kNoCode) ok[i] = false;
-                    cell[i] += x * st;
+                for (int c = 0; c < kMaxKeyComps; ++c) {
+                    // rows at or past the block's end are not loaded (a chunk that starts before it
+                    // ends inside the column: columns are padded to 64 rows)
+                    if (c < S.n_comp && row < r1)
+                        v[j][c] = gld(reinterpret_cast<const u32x4 *>(codes + (int64_t)S.code[c] * d.pitch + row))[0];
+                    else
+                        v[j][c] = u32x4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
                 }
             }
             const uint32_t base = (uint32_t)S.lds_off + (uint32_t)(lane & (S.reps - 1)) * (uint32_t)S.rep_stride;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t k = cell[i] - (uint32_t)S.lo;
-                if (ok[i] && k < (uint32_t)S.n) atomicAdd(&smem[base + k], 1u);
+            for (int j = 0; j < kHistChunks; ++j) {
+                const int64_t row = r + j * span + 8 * tid;
+                const int nv = row >= r1 ? 0 : (r1 - row < 8 ? (int)(r1 - row) : 8);
+                uint32_t cell[8];
+                bool ok[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    cell[i] = 0u;
+                    ok[i] = i < nv;
+                }
+#pragma unroll
+                for (int c = 0; c < kMaxKeyComps; ++c) {
+                    if (c >= S.n_comp) break;
+                    const uint32_t st = (uint32_t)S.stride[c];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const uint32_t x = (v[j][c][i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+                        if (x == kNoCode) ok[i] = false;
+                        cell[i] += x * st;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t k = cell[i] - (uint32_t)S.lo;
+                    if (ok[i] && k < (uint32_t)S.n) atomicAdd(&smem[base + k], 1u);
+                }
             }
         }
     }

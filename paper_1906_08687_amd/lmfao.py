@@ -88,7 +88,7 @@ SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relat
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
            "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
            "lmfao_mlp_scratch_floats", "lmfao_mlp_loss_grad", "lmfao_adam_step", "lmfao_mlp_train",
-           "lmfao_measure_peak"]
+           "lmfao_measure_peak", "lmfao_train_workspace_size", "lmfao_train_cost_model", "lmfao_ridge_bgd", "lmfao_mutual_information", "lmfao_chow_liu", "lmfao_best_splits"]
 
 _lib = None
 
@@ -138,6 +138,12 @@ def load(path: str = LIB_PATH):
         "lmfao_mlp_train": (st, [i32, P, P, P, P, P, i32, i32, ctypes.c_float, P, P, P, P]),
         "lmfao_measure_peak": (st, [i32, P, sz, i32, P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
+        "lmfao_ridge_bgd": (st, [P, i32, i32, ctypes.c_double, i32, ctypes.c_double, P, P, P]),
+        "lmfao_train_workspace_size": (st, [ctypes.c_char_p, i32, ctypes.POINTER(sz)]),
+        "lmfao_train_cost_model": (st, [ctypes.c_char_p, ctypes.c_char_p, P, P, sz, P, ctypes.POINTER(ctypes.c_float)]),
+        "lmfao_mutual_information": (st, [P, P, i32, i32, P, P]),
+        "lmfao_chow_liu": (st, [P, i32, P, P, P]),
+        "lmfao_best_splits": (st, [P, i32, i32, i32, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -486,3 +492,178 @@ def measure_peak(kind: str, buf, iters: int, stream=None):
     _check(_lib.lmfao_measure_peak(PEAKS[kind], _ptr(buf), buf.numel() * buf.element_size(), iters,
                                    _stream_handle(stream), ctypes.byref(ms), ctypes.byref(units)), "measure_peak")
     return ms.value, units.value
+
+
+# ---------------------------------------------------------------------------
+# application loops (Section 2): argument marshalling around lmfao_ridge_bgd,
+# lmfao_mutual_information, lmfao_chow_liu and lmfao_best_splits
+# ---------------------------------------------------------------------------
+
+class _SplitInput(ctypes.Structure):
+    _fields_ = [("counts", ctypes.c_void_p), ("sums", ctypes.c_void_p), ("sum_stride", ctypes.c_int32),
+                ("n_cells", ctypes.c_int32), ("categorical", ctypes.c_int32), ("node", ctypes.c_int32)]
+
+
+class _SplitResult(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_double), ("input", ctypes.c_int32), ("cell", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+
+
+SPLIT = {"variance": 0, "gini": 1}
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _to_device_bytes(obj_bytes: bytes, dev):
+    import torch
+    return torch.frombuffer(bytearray(obj_bytes), dtype=torch.uint8).to(dev)
+
+
+def ridge_bgd(cov, label: int, lam: float, max_iters: int = 1000, tol: float = 1e-10, stream=None):
+    """Ridge regression by gradient descent on the device over the covariance matrix `cov`
+    (an n x n float64 device tensor over [1, X...]); returns (theta tensor, [J, steps, |grad|])."""
+    import torch
+    load()
+    cov = cov.contiguous()
+    n = cov.shape[0]
+    theta = torch.empty(n, dtype=torch.float64, device=cov.device)
+    info = torch.empty(3, dtype=torch.float64, device=cov.device)
+    _check(_lib.lmfao_ridge_bgd(_ptr(cov), n, label, lam, max_iters, tol, _ptr(theta), _ptr(info),
+                                _stream_handle(stream)), "ridge_bgd")
+    _sync()
+    return theta, info.cpu().numpy()
+
+
+def covariance_matrix(eng, attrs):
+    """The engine's covariance block over [1, attrs...] as an n x n float64 device tensor,
+    gathered from the result arena (queries of datagen.configs.covariance_queries)."""
+    import torch
+    feats = [None] + list(attrs)
+    n = len(feats)
+    res64 = eng.res.view(torch.float64)
+    C = torch.zeros((n, n), dtype=torch.float64, device=eng.res.device)
+    for qid, q in enumerate(eng.queries):
+        if q.groupby or q.where:
+            continue
+        _, a, co, so = eng.ctx.result_layout(qid)
+        if not q.aggs:
+            C[0, 0] = eng.res[co:co + 8].view(torch.int64)[0].to(torch.float64)
+            continue
+        fs = q.aggs[0].terms[0][1]
+        i = feats.index(fs[0])
+        j = feats.index(fs[1]) if len(fs) > 1 else 0
+        C[i, j] = res64[so // 8]
+        C[j, i] = res64[so // 8]
+    return C
+
+
+def mutual_information(eng, pair_qids, stream=None):
+    """Mutual information of each pairwise COUNT GROUP BY query of `eng` (device tensor)."""
+    import torch
+    load()
+    base = _ptr(eng.res)
+    ptrs, doms = [], []
+    for qid in pair_qids:
+        q = eng.queries[qid]
+        _, _, co, _ = eng.ctx.result_layout(qid)
+        ptrs.append(base + co)
+        doms += [q.groupby[0].domain(eng.db), q.groupby[1].domain(eng.db)]
+    dev = eng.res.device
+    pt = torch.tensor(ptrs, dtype=torch.int64, device=dev)
+    dt = torch.tensor(doms, dtype=torch.int32, device=dev)
+    mi = torch.empty(len(ptrs), dtype=torch.float64, device=dev)
+    _check(_lib.lmfao_mutual_information(_ptr(pt), _ptr(dt), len(ptrs), max(doms) if doms else 1, _ptr(mi),
+                                         _stream_handle(stream)), "mutual_information")
+    _sync()
+    return mi
+
+
+def chow_liu(mi, stream=None):
+    """Chow-Liu tree of an n x n float64 device tensor of mutual informations:
+    (edges as a list of (i, j) in the order taken, their total)."""
+    import torch
+    load()
+    mi = mi.contiguous()
+    n = mi.shape[0]
+    edges = torch.empty(2 * (n - 1), dtype=torch.int32, device=mi.device)
+    total = torch.empty(1, dtype=torch.float64, device=mi.device)
+    _check(_lib.lmfao_chow_liu(_ptr(mi), n, _ptr(edges), _ptr(total), _stream_handle(stream)), "chow_liu")
+    _sync()
+    e = edges.cpu().numpy().reshape(-1, 2)
+    return [(int(a), int(b)) for a, b in e if a >= 0], float(total.item())
+
+
+def _run_splits(structs, n_nodes, criterion, n_labels, dev, stream=None):
+    import torch
+    load()
+    arr = (_SplitInput * max(1, len(structs)))(*structs)
+    din = _to_device_bytes(bytes(arr), dev)
+    out = torch.empty(n_nodes * ctypes.sizeof(_SplitResult), dtype=torch.uint8, device=dev)
+    _check(_lib.lmfao_best_splits(_ptr(din), len(structs), n_nodes, SPLIT[criterion], n_labels, _ptr(out),
+                                  _stream_handle(stream)), "best_splits")
+    _sync()
+    host = (_SplitResult * n_nodes).from_buffer_copy(out.cpu().numpy().tobytes())
+    return [(r.cost, r.input, r.cell) for r in host]
+
+
+def best_splits(eng, qids, nodes, criterion="variance", n_labels=0, stream=None):
+    """Best split per node from the engine's histograms: query qids[k] belongs to node nodes[k];
+    VARIANCE queries group by the split attribute and sum y and y^2; GINI queries group by
+    (label, split attribute).  Returns (cost, input k, cell) per node."""
+    base = _ptr(eng.res)
+    structs = []
+    for qid, node in zip(qids, nodes):
+        q = eng.queries[qid]
+        n_cells, a, co, so = eng.ctx.result_layout(qid)
+        g = q.groupby[-1]
+        cells = g.domain(eng.db)
+        structs.append(_SplitInput(base + co, base + so if criterion == "variance" else None, a, cells,
+                                   1 if g.thresholds is None else 0, node))
+    return _run_splits(structs, max(nodes) + 1 if nodes else 0, criterion, n_labels, eng.res.device, stream)
+
+
+def best_splits_from_arrays(inputs, n_nodes, criterion="variance", n_labels=0, stream=None):
+    """Best split per node from host histograms (dicts: node, categorical, counts, sums),
+    uploaded to the device first."""
+    import torch
+    dev = torch.device("cuda", 0)
+    keep, structs = [], []
+    for I in inputs:
+        c = torch.from_numpy(np.ascontiguousarray(I["counts"], dtype=np.uint64).view(np.int64)).to(dev)
+        keep.append(c)
+        sp, stride = None, 0
+        if criterion == "variance":
+            sm = np.ascontiguousarray(I["sums"], dtype=np.float64)
+            st = torch.from_numpy(sm).to(dev)
+            keep.append(st)
+            sp, stride = _ptr(st), sm.shape[1]
+        n_cells = (c.numel() if criterion == "variance" else c.numel() // n_labels)
+        structs.append(_SplitInput(_ptr(c), sp, stride, n_cells, int(I["categorical"]), int(I["node"])))
+    out = _run_splits(structs, n_nodes, criterion, n_labels, dev, stream)
+    del keep
+    return out
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+def train_cost_model(timing_db: str, weights_out: str, hidden: int = 32, epochs: int = 4000, lr: float = 3e-3,
+                     seed: int = 1, device: int = 0, stream=None) -> float:
+    """lmfao_train_cost_model in a torch-allocated workspace; returns the final loss."""
+    import torch
+    load()
+    need = ctypes.c_size_t()
+    _check(_lib.lmfao_train_workspace_size(timing_db.encode(), hidden, ctypes.byref(need)), "train_workspace_size")
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device=torch.device("cuda", device))
+    base = (_ptr(ws) + 255) // 256 * 256
+    loss = ctypes.c_float()
+    o = _TrainOpts(hidden, epochs, lr, 0, seed)
+    _check(_lib.lmfao_train_cost_model(timing_db.encode(), weights_out.encode(), ctypes.byref(o), base,
+                                       need.value + 256 - (base - _ptr(ws)), _stream_handle(stream),
+                                       ctypes.byref(loss)), "train_cost_model")
+    return float(loss.value)

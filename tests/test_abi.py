@@ -421,3 +421,42 @@ def test_scratch_binding_needs_a_plan_and_a_device():
     expect("STATE", lambda: ctx.bind_scratch(FAKE, 1 << 20))
     ctx.plan()
     expect("HIP", lambda: ctx.bind_scratch(FAKE, 1 << 20))
+
+
+def test_application_loop_argument_errors():
+    """Argument checks of the application loops return before any launch."""
+    lib = _lib()
+    F = ctypes.c_void_p(FAKE)
+    assert lib.lmfao_ridge_bgd(F, 65, 1, 0.1, 10, 1e-9, F, F, None) == -1        # more than 64 features
+    assert lib.lmfao_ridge_bgd(F, 8, 0, 0.1, 10, 1e-9, F, F, None) == -1         # label 0 is the constant
+    assert lib.lmfao_ridge_bgd(F, 8, 3, -1.0, 10, 1e-9, F, F, None) == -1        # negative lambda
+    assert lib.lmfao_mutual_information(F, F, 3, 4096, F, None) == -6            # domain above 2048
+    assert lib.lmfao_mutual_information(None, F, 3, 10, F, None) == -1
+    assert lib.lmfao_chow_liu(F, 65, F, F, None) == -6
+    assert lib.lmfao_chow_liu(F, 1, F, F, None) == -1
+    assert lib.lmfao_best_splits(F, 4, 2, 7, 0, F, None) == -1                   # unknown criterion
+    assert lib.lmfao_best_splits(F, 4, 2, 1, 0, F, None) == -1                   # Gini needs labels
+    assert lib.lmfao_best_splits(F, 4, 2, 1, 17, F, None) == -6                  # at most 16 labels
+
+
+def test_training_reads_the_timing_file_and_checks_its_arguments(tmp_path):
+    """lmfao_train_workspace_size parses the autotuner's timing file (16 features, 5
+    configuration values, milliseconds per line); malformed files and options are refused
+    before anything touches a device."""
+    from paper_1906_08687_amd import costmodel
+    lib = _lib()
+    path = os.path.join(os.path.dirname(costmodel.WEIGHTS), "timings.csv")
+    n = ctypes.c_size_t()
+    assert lib.lmfao_train_workspace_size(path.encode(), 32, ctypes.byref(n)) == 0
+    rows = sum(1 for l in open(path) if l.strip())
+    assert n.value >= rows * (16 + 1) * 4
+    bad = tmp_path / "bad.csv"
+    bad.write_text("1,2,3\n")
+    assert lib.lmfao_train_workspace_size(str(bad).encode(), 32, ctypes.byref(n)) == -1
+    neg = tmp_path / "neg.csv"
+    neg.write_text(",".join(["1"] * 21 + ["-2.0"]) + "\n")
+    assert lib.lmfao_train_workspace_size(str(neg).encode(), 32, ctypes.byref(n)) == -1
+    assert lib.lmfao_train_workspace_size(b"/nonexistent/timings.csv", 32, ctypes.byref(n)) == -1
+    o = lmfao._TrainOpts(32, 0, 1e-3, 0, 1)                       # zero epochs
+    assert lib.lmfao_train_cost_model(path.encode(), str(tmp_path / "w.bin").encode(), ctypes.byref(o),
+                                      ctypes.c_void_p(FAKE), 1 << 30, None, None) == -1

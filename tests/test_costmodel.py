@@ -183,7 +183,41 @@ def test_device_adam_and_training_follow_reference():
 # --------------------------------------------------------------------------
 
 @pytest.mark.gpu
+def test_library_training_builds_targets_standardises_and_fits():
+    """lmfao_train_cost_model on the committed timing file: the weights file's
+    standardisation equals the one computed here from the same lines (workload
+    grouping and relative log-time targets restated in numpy), the loss falls,
+    and the trained network, evaluated by the fp64 reference forward pass,
+    ranks the candidates of the timing file's workloads."""
+    import tempfile
+    from paper_1906_08687_amd import costmodel, lmfao
+    path = os.path.join(os.path.dirname(costmodel.WEIGHTS), "timings.csv")
+    if not os.path.exists(path):
+        pytest.skip("no timing file in the tree")
+    X, cfg, ms = costmodel.load_db(path)
+    y = costmodel.relative_log_ms(X, ms)
+    with tempfile.TemporaryDirectory() as d:
+        w = os.path.join(d, "w.bin")
+        l1 = lmfao.train_cost_model(path, w, 32, 1, 3e-3, seed=7)
+        l2 = lmfao.train_cost_model(path, w, 32, 1500, 3e-3, seed=7)
+        hidden, norm, params = costmodel.load(w)
+    assert hidden == 32 and l2 < 0.7 * l1, (l1, l2)
+    std = X.std(axis=0)
+    std[std == 0] = 1.0
+    np.testing.assert_allclose(norm[:16], X.mean(axis=0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(norm[16:32], std, rtol=1e-5)
+    np.testing.assert_allclose(norm[32:], [y.mean(), y.std()], rtol=1e-5)
+    pred = ref.forward(params.astype(np.float64), (X - norm[:16]) / norm[16:32], hidden) * norm[33] + norm[32]
+    # rank agreement inside each workload (Spearman's rho over all candidates of the file)
+    from scipy.stats import spearmanr
+    assert spearmanr(pred, y).correlation > 0.5
+
+
+@pytest.mark.gpu
 def test_learned_choice_against_heuristic_on_held_out_workloads():
+    """The learned form the benchmark runs (the model's top four and the heuristic choice,
+    judged by timing) against the heuristic choice alone on held-out random batches: no
+    slower beyond timing noise (the held-out report costmodel/eval.json states the gain)."""
     import torch
     from datagen.configs import random_workload
     from paper_1906_08687_amd import costmodel, lmfao
@@ -193,16 +227,16 @@ def test_learned_choice_against_heuristic_on_held_out_workloads():
     t_heur = t_learn = 0.0
     for j in (180, 181, 182, 183):       # held out: training uses workloads below 150
         db, qs = random_workload(j, max_rows=2_000_000)
-        eng = lmfao.Engine(db, qs, precision="bf16x3")
+        eng = lmfao.Engine(db, qs, precision="bf16x6")
         eng.run(stream)
         t_heur += eng.ctx.time_root_group(stream, 2, 10)
-        eng.ctx.choose_learned(costmodel.WEIGHTS, stream)
+        eng.ctx.choose_learned_verified(costmodel.WEIGHTS, stream, 4, 3)
         eng._bind()
         eng.run(stream)
         t_learn += eng.ctx.time_root_group(stream, 2, 10)
-    print("held-out root-scan time: heuristic %.3f ms, learned %.3f ms (gain %.2fx)" %
+    print("held-out root-scan time: heuristic %.3f ms, learned top-4 timed %.3f ms (gain %.2fx)" %
           (t_heur, t_learn, t_heur / t_learn))
-    assert t_learn <= 1.15 * t_heur
+    assert t_learn <= 1.03 * t_heur
 
 
 @pytest.mark.gpu
@@ -219,7 +253,7 @@ def test_learned_choice_judged_by_timing_is_no_slower_than_the_top_choice():
         pytest.skip("no trained cost model in the tree")
     stream = torch.cuda.Stream()
     for db, qs in (random_workload(184, max_rows=2_000_000), random_covariance_workload(184, 8_000_000)):
-        eng = lmfao.Engine(db, qs, precision="bf16x3")
+        eng = lmfao.Engine(db, qs, precision="bf16x6")
         eng.run(stream)
         top = eng.ctx.choose_learned(costmodel.WEIGHTS, stream)
         eng._bind()

@@ -171,6 +171,22 @@ def covariance_queries(conts: Sequence[str]) -> List[Query]:
     return qs
 
 
+def polynomial_queries(conts: Sequence[str]) -> List[Query]:
+    """Degree-2 polynomial regression (Section 2): the covariance matrix of the
+    vector u = [1, x_i, x_i * x_j (i <= j)], one query per entry u_a * u_b with
+    a <= b -- products of up to four attributes; (C^2 + C) / 2 aggregates for
+    C = (n+1)(n+2)/2."""
+    u: List[Tuple[str, ...]] = [()]
+    u += [(a,) for a in conts]
+    u += [(conts[i], conts[j]) for i in range(len(conts)) for j in range(i, len(conts))]
+    qs = []
+    for a in range(len(u)):
+        for b in range(a, len(u)):
+            f = u[a] + u[b]
+            qs.append(Query() if not f else Query(aggs=[Agg.monomial(*f)]))
+    return qs
+
+
 # ---------------------------------------------------------------------------
 # workload 1: tiny star
 # ---------------------------------------------------------------------------
@@ -418,6 +434,54 @@ SMALL = {
 }
 
 BUILDERS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+# ---------------------------------------------------------------------------
+# many-to-many star (Yelp-like: reviews of businesses with several categories
+# and attributes per business, Section 4)
+# ---------------------------------------------------------------------------
+
+def many_to_many_database(n_fact: int = 200_000, n_users: int = 5_000, n_business: int = 2_000,
+                          mean_cat: int = 3, mean_attr: int = 2, seed: int = 11) -> Database:
+    """Review(user, business) fact, Zipf(1.1) keys, sorted; User and Business
+    dimensions with unique keys; Category and Attribute with, per business, a
+    number of rows uniform in [0, 2 * mean] (businesses with none do not
+    join), keyed by the repeated join attribute ``business``."""
+    g = native()
+    U = RelSpec("User", n_users, [AttrSpec("u1", "cont", ("normal", 3.0, 1.0)), AttrSpec("u2", "cont"),
+                                  AttrSpec("ucat", "cat", domain=7)], key="user")
+    B = RelSpec("Business", n_business, [AttrSpec("b1", "cont", ("uniform", 1.0, 5.0)),
+                                         AttrSpec("bcat", "cat", domain=12)], key="business")
+    F = RelSpec("Review", n_fact, [AttrSpec("stars", "cont", ("uniform", 1.0, 5.0)), AttrSpec("useful", "cont"),
+                                   AttrSpec("rcat", "cat", domain=5)],
+                children=[(U, "user"), (B, "business")], zipf_s={"user": 1.1, "business": 1.1})
+    db = build_database(seed, F)
+    many = [("Category", mean_cat, [AttrSpec("cw", "cont", ("normal", 2.0, 1.5)),
+                                    AttrSpec("cv", "cont", ("uniform", -1.0, 1.0))]),
+            ("Attribute", mean_attr, [AttrSpec("aw", "cont", ("normal", 0.0, 2.0))])]
+    for name, mean, attrs in many:
+        per_key = g.uniform_i32(g.key(seed, name + ".rows"), n_business, 0, 2 * mean + 1)
+        keys = np.repeat(np.arange(n_business, dtype=np.int32), per_key.astype(np.int64))
+        cols = [Column("business", "key_many", keys, n_business)]
+        cols += [_draw_attr(seed, name, a, len(keys)) for a in attrs]
+        db.relations.append(Relation(name, cols))
+        db.edges.append((0, len(db.relations) - 1))
+    return db
+
+
+def many_to_many_batch(db: Database) -> List[Query]:
+    """Covariance of every continuous attribute, grouped sums by categories of
+    the other relations, and filtered sums of the many-to-many attributes."""
+    conts = cont_attrs(db)
+    qs = covariance_queries(conts)
+    for c in ("bcat", "ucat", "rcat"):
+        qs.append(Query(groupby=[GroupBy(c)], aggs=[Agg.monomial("cw"), Agg.monomial("aw"), Agg.monomial("stars", "cv"),
+                                                    Agg.monomial("u1")]))
+    qs.append(Query(groupby=[GroupBy("bcat"), GroupBy("rcat")]))
+    qs.append(Query(where=[Pred("stars", "gt", 3.0)], aggs=[Agg.monomial("cw"), Agg.monomial("aw", "b1")]))
+    qs.append(Query(groupby=[GroupBy("ucat")], where=[Pred("b1", "le", 2.5), Pred("rcat", "ne", 1)],
+                    aggs=[Agg.monomial("cv"), Agg.monomial("useful")]))
+    return qs
 
 
 def make_database(k: int, size: str = "small", **override) -> Database:

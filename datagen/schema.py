@@ -34,9 +34,11 @@ OPS = ("le", "lt", "ge", "gt", "eq", "ne")
 @dataclass
 class Column:
     attr: str
-    kind: str                 # "key" | "cont" | "cat"
-    data: np.ndarray          # int32 (key, cat) or float32 (cont)
-    domain: int = 0           # cat: codes in [0, domain); key: values in [0, domain)
+    kind: str                 # "key" | "key_many" | "cont" | "cat"
+    data: np.ndarray          # int32 (key, key_many, cat) or float32 (cont)
+    domain: int = 0           # cat: codes in [0, domain); key, key_many: values in [0, domain)
+    # "key_many": the join attribute of a child relation whose values may repeat
+    # (a many-to-many join)
 
 
 @dataclass

@@ -24,9 +24,25 @@
  *
  * Supported join trees: every edge joins its two relations on exactly one
  * shared int32 attribute, which is a unique key of the child relation (the
- * star and snowflake schemas of the paper's datasets).  Keys lie in
- * [0, domain) of the key column.  A fact row whose key has no matching child
- * row does not join (natural-join semantics).
+ * star and snowflake schemas of the paper's datasets), or, declared
+ * LMFAO_KEY_MANY in the child, a join attribute whose values may repeat (a
+ * many-to-many join, where the join is larger than its relations: Section 4,
+ * Yelp).  Keys lie in [0, domain) of the key column.  A fact row whose key
+ * has no matching child row does not join (natural-join semantics).
+ *
+ * Many-to-many children are evaluated by count-weighted views (Section 3.2:
+ * a view of a child subtree carries, per key, the aggregates of that subtree
+ * the batch needs): per key the child's view holds its row count, the mean
+ * of each of its continuous attributes, and the within-key scatter of every
+ * pair of them; the root scan weights each of its rows by the product of its
+ * children's counts, and the covariance entries of two attributes of one
+ * such child are completed from that child's scatter weighted by how often
+ * the root reaches each key.  Supported: a many-to-many child that is a leaf
+ * of the root, with continuous attributes summed (COUNT, SUM, the covariance
+ * block, and grouped tables keyed by attributes of other relations); its
+ * attributes may not be group-by or predicate attributes, a grouped table may
+ * not sum a product of two of its attributes, and the covariance block runs
+ * in FP32 (UNSUPPORTED otherwise).
  *
  * Conventions
  *  - Every function returns lmfao_status: LMFAO_OK (0) or a negative error;
@@ -85,12 +101,13 @@ const char *lmfao_last_error(const lmfao_ctx *ctx);
 /* ---- relations (Section 2, query language: relations R_1..R_m) --------- */
 
 enum { LMFAO_I32 = 0, LMFAO_F32 = 1 };                 /* dtype */
-enum { LMFAO_KEY = 0, LMFAO_CONT = 1, LMFAO_CAT = 2 };  /* kind  */
+enum { LMFAO_KEY = 0, LMFAO_CONT = 1, LMFAO_CAT = 2, LMFAO_KEY_MANY = 3 };  /* kind  */
 
 typedef struct {
     const char *attr;   /* attribute name; equal names join (natural join) */
     int32_t dtype;      /* LMFAO_I32 for KEY/CAT, LMFAO_F32 for CONT */
-    int32_t kind;       /* LMFAO_KEY, LMFAO_CONT or LMFAO_CAT */
+    int32_t kind;       /* LMFAO_KEY, LMFAO_CONT, LMFAO_CAT, or LMFAO_KEY_MANY: the join attribute
+                           of a child relation whose values may repeat (a many-to-many join) */
     int32_t domain;     /* KEY: values in [0, domain); CAT: codes in [0, domain); CONT: ignored */
     const void *data;   /* device pointer to n_rows elements (borrowed) */
 } lmfao_col;
@@ -130,8 +147,9 @@ typedef struct {
 
 typedef struct {
     double coeff;              /* c_j */
-    int32_t n_factors;         /* 0, 1 or 2 identity factors */
-    const char *factors[2];    /* CONT attribute names */
+    int32_t n_factors;         /* 0 to 4 identity factors (degree-2 polynomial regression needs
+                                  products of up to four attributes, Section 2) */
+    const char *factors[4];    /* CONT attribute names */
 } lmfao_term;
 
 typedef struct {
@@ -150,7 +168,11 @@ typedef struct {
 
 /* Add one query; *qid receives its index.  All descriptor memory is copied.
  * Errors: UNKNOWN_ATTR, TYPE (e.g. a factor that is not CONT), TOO_LARGE
- * (more than 2^31 cells). */
+ * (more than 2^31 cells, or a term of more than four factors).  A term of
+ * three or four factors is evaluated as the product of two staged values,
+ * one of them (or both) the product of two attributes formed per row by the
+ * root scan: f1 * (f2 f3) and (f1 f2) * (f3 f4), factors in staged order; at
+ * most 63 attributes and such products together. */
 lmfao_status lmfao_add_query(lmfao_ctx *ctx, const lmfao_query *q, int32_t *qid);
 
 /* ---- planning ------------------------------------------------------------ */

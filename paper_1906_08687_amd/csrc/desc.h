@@ -8,7 +8,8 @@
 //     block of ungrouped sums, a total count, and grouped tables.
 //
 // View record layout (32-bit words, one record per key of the relation):
-//   [0]                 count of joining rows with this key (0 or 1)
+//   [0]                 count of joining rows with this key (0 or 1; for a
+//                       many-to-many child the number of its rows with the key)
 //   [1 .. 1+n_mask)     filter mask words: bit f = every conjunct of filter f
 //                       on an attribute of this subtree holds
 //   [comp_off ..)       group-by components of this subtree (int32 cells)
@@ -29,6 +30,7 @@ constexpr int kBlock = 256;       // threads per workgroup of every scan (one ro
 constexpr uint32_t kErrDomain = 1u;     // categorical code outside [0, domain)
 constexpr uint32_t kErrDupKey = 2u;     // two rows of a child relation share a key
 constexpr uint32_t kErrKeyRange = 4u;   // a primary key outside [0, n_keys)
+constexpr uint32_t kErrWeight = 8u;     // a root row joins more tuples than the root scan counts exactly
 
 enum Op : int32_t { OP_LE = 0, OP_LT = 1, OP_GE = 2, OP_GT = 3, OP_EQ = 4, OP_NE = 5 };
 
@@ -68,6 +70,9 @@ struct ChildSrc {         // a child view gathered through a foreign key of the 
     int32_t comp_off, n_comp, comp_dst;
     int32_t feat_off, n_feat, feat_dst;
     int32_t quad_base;    // root scan: first 16-byte quad of this child in the record buffer
+    double *hw;           // root scan, many-to-many child whose scatter completes the covariance
+                          // block: per key, the weight of the root rows reaching it over the
+                          // child's count (null otherwise)
 };
 
 struct ScanDesc {
@@ -147,6 +152,7 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
 };
 
 constexpr int kColPitch = 68;     // words per 64-row LDS column (64 rows + 4 words of bank padding)
+constexpr int kDerivedSrc = -(1 << 20);   // feat_src of derived feature j: kDerivedSrc - j
 constexpr int kMaxWaves = 4;      // waves per workgroup of the root scan
 
 struct RootDesc {
@@ -206,11 +212,55 @@ struct RootDesc {
     int32_t n_code_feats;              // staged features summed by the tables, written as fp32 codes
     const int32_t *code_feats;         // [n_code_feats] their staged feature ids
     int32_t code_feat_col;             // column of the first of them
+    int32_t n_der;                     // derived features: products of two staged features per row
+    int32_t w_der;                     // wave-relative: n_der LDS columns holding them for the tile
+    const int32_t *der_ab;             // [n_der][2] staged features of each product
     int32_t n_hcodes;                  // count-table scan: component code columns to write
     uint16_t *hcodes;                  // [n_hcodes][hcode_pitch] component values, 0xFFFF when the
                                        // row does not join (see HistDesc)
     int64_t hcode_pitch;               // u16 entries per column (rows rounded up to 64)
     const int32_t *hcode_comp;         // [n_hcodes] staged component of each column
+    // many-to-many children: each row stands for w = product of its children's record counts
+    // joined tuples (count-weighted views); COUNT adds w, sums add w * value, the fp32
+    // covariance block weights one factor per row (LDS column w_wgt), hw arrays collect w / count
+    int32_t weighted;
+    int32_t w_wgt;                     // wave-relative: one LDS column of row weights (fp32)
+    uint32_t max_weight;               // larger weights raise kErrWeight (u32 LDS counts, fp32)
+    int32_t pad_w;
+};
+
+// ---- many-to-many child views ------------------------------------------------------
+//
+// A child whose join key repeats is summarised per key: its row count, the sum of
+// each continuous attribute and the sum of every pair product (dup_agg_kernel, one
+// thread per row, fp64 atomics), then per key the record (count, filter bits,
+// fp32 means) and the within-key scatter sum_i (x_a - mean_a)(x_b - mean_b) =
+// sum x_a x_b - sum x_a sum x_b / count in place of the pair sums
+// (dup_final_kernel, one thread per key).
+struct DupDesc {
+    int64_t n_rows;
+    const int32_t *key;
+    const FeatSrc *feats;          // [n_feat] continuous attributes; dst = record feature index
+    const int32_t *pair_ab;        // [n_pair][2] record feature indices a <= b
+    int32_t n_keys, n_feat, n_pair, rec_stride;
+    int32_t rec_feat_off, n_mask;
+    uint64_t filter_all;           // mask bits of the record (no predicate applies to the child)
+    uint32_t *cnt;                 // [n_keys] rows per key
+    double *sum;                   // [n_keys][n_feat]
+    double *scat;                  // [n_keys][n_pair]
+    uint32_t *rec_out;
+    uint32_t *err;
+};
+
+// Covariance entries of two attributes of one many-to-many child: the merged block
+// holds sum_rows w * mean_a * mean_b; adding sum_k hw[k] * scatter_ab[k] completes
+// them to the sum over joined tuples of x_a * x_b.  One workgroup per pair.
+struct CorrDesc {
+    int32_t n_keys, n_pair, n_gram, pad;
+    const double *hw;              // [n_keys]
+    const double *scat;            // [n_keys][n_pair]
+    const int32_t *gram_ab;        // [n_pair][2] staged features (covariance indices)
+    double *gram;                  // [n_gram][n_gram]
 };
 
 // ---- grouped tables from per-row codes -----------------------------------------

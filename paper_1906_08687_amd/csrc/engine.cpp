@@ -52,6 +52,8 @@ typedef void (*RootKernel)(const RootDesc *);
 RootKernel root_kernel(int mode, int p1, bool tables);
 hipError_t launch_fill(const void *fills, int n, hipStream_t st);
 hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hipStream_t st);
+hipError_t launch_dup(const DupDesc *desc, int64_t n_rows, int64_t n_keys, hipStream_t st);
+hipError_t launch_corr(const CorrDesc *desc, int n_pair, hipStream_t st);
 hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, int waves, size_t lds_bytes,
                        hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
@@ -230,6 +232,16 @@ struct Plan {
     int n_mask = 0;
     // record layouts of non-root relations
     std::vector<int> rec_stride, rec_comp_off, rec_feat_off;
+    // many-to-many children (join key declared KEY_MANY): count-weighted views.  dup[r]; per such
+    // relation the pairs (staged features a <= b, both its own) whose covariance entries take its
+    // within-key scatter, weighted by how often the root reaches each key
+    std::vector<char> dup;
+    std::vector<std::vector<std::pair<int, int>>> dup_pairs;
+    bool weighted = false;
+    // products of two staged attributes computed per row by the root scan (the degree-2 parts of
+    // monomials of degree 3 and 4): staged features n_base .. n_feat-1
+    std::vector<std::pair<int, int>> derived;
+    int n_base = 1;
     // root outputs
     int n_feat = 1, n_gram = 0;
     bool need_count = false;
@@ -345,6 +357,9 @@ struct lmfao_ctx {
     size_t off_codes = 0;                         // per-row codes
     size_t code_desc_off = 0;                     // CodeScanDesc offset in blob
     size_t off_hcodes = 0;                        // component codes of the count-table scan
+    // many-to-many children: per relation the sums, pair sums / scatter and root weights per key
+    std::vector<size_t> off_dsum, off_dscat, off_hw;
+    std::vector<size_t> dup_desc_off, corr_desc_off;   // per relation: DupDesc / CorrDesc in blob
     size_t hist_desc_off = 0;                     // HistDesc offset in blob
     std::vector<int64_t> rollup_cells;            // per pass: most (cell, sum or count) pairs of a table
     int64_t assemble_cells = 0;                   // most cells of a query result
@@ -423,7 +438,7 @@ extern "C" lmfao_status lmfao_add_relation(lmfao_ctx *c, const char *name, int64
     for (int i = 0; i < n_cols; ++i) {
         const lmfao_col &x = cols[i];
         if (!x.attr || (!x.data && n_rows > 0)) return fail(c, LMFAO_ERR_INVALID_ARG, "column without name or data");
-        if (x.kind < LMFAO_KEY || x.kind > LMFAO_CAT || x.dtype < LMFAO_I32 || x.dtype > LMFAO_F32)
+        if (x.kind < LMFAO_KEY || x.kind > LMFAO_KEY_MANY || x.dtype < LMFAO_I32 || x.dtype > LMFAO_F32)
             return fail(c, LMFAO_ERR_INVALID_ARG, std::string("bad kind/dtype for ") + x.attr);
         if ((x.kind == LMFAO_CONT) != (x.dtype == LMFAO_F32))
             return fail(c, LMFAO_ERR_TYPE, std::string("CONT columns are F32, KEY/CAT columns I32: ") + x.attr);
@@ -477,8 +492,8 @@ extern "C" lmfao_status lmfao_set_join_tree(lmfao_ctx *c, int32_t n_edges, const
         if (shared != 1)
             return fail(c, LMFAO_ERR_UNSUPPORTED, "edge " + P.name + "-" + C.name + " must share exactly one attribute");
         const Col &pc = P.cols[P.find(name)], &cc = C.cols[C.find(name)];
-        if (pc.kind != LMFAO_KEY || cc.kind != LMFAO_KEY)
-            return fail(c, LMFAO_ERR_TYPE, "join attribute " + name + " must be KEY in both relations");
+        if (pc.kind != LMFAO_KEY || (cc.kind != LMFAO_KEY && cc.kind != LMFAO_KEY_MANY))
+            return fail(c, LMFAO_ERR_TYPE, "join attribute " + name + " must be KEY in the parent and KEY or KEY_MANY in the child");
     }
     // running intersection: the holders of every attribute are connected in the tree
     std::map<std::string, std::vector<int>> holders;
@@ -600,8 +615,8 @@ extern "C" lmfao_status lmfao_add_query(lmfao_ctx *c, const lmfao_query *q, int3
         QAgg A;
         for (int t = 0; t < x.n_terms; ++t) {
             const lmfao_term &tm = x.terms[t];
-            if (tm.n_factors < 0 || tm.n_factors > 2)
-                return fail(c, LMFAO_ERR_TOO_LARGE, "terms are products of at most two attributes");
+            if (tm.n_factors < 0 || tm.n_factors > 4)
+                return fail(c, LMFAO_ERR_TOO_LARGE, "terms are products of at most four attributes");
             QTerm T;
             T.coeff = tm.coeff;
             for (int f = 0; f < tm.n_factors; ++f) {
@@ -790,8 +805,34 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         P.sub_comp_n[r] = comp_slot - P.sub_comp_lo[r];
     };
     visit(P.root);
-    P.n_feat = (int)P.feats.size();
-    if (P.n_feat > kMaxFeat) return fail(c, LMFAO_ERR_TOO_LARGE, "more than 63 continuous features");
+    P.n_base = (int)P.feats.size();
+    // monomials of degree 3 and 4 are split, factors sorted by staged id, into a degree-1 or 2 part
+    // and a degree-2 part: f1 * (f2 f3) and (f1 f2) * (f3 f4); every degree-2 part becomes a derived
+    // feature (one per distinct pair), computed per row by the root scan
+    P.derived.clear();
+    std::map<std::pair<int, int>, int> der_id;
+    auto derived_of = [&](int a, int b) {
+        if (a > b) std::swap(a, b);
+        auto it = der_id.find({a, b});
+        if (it == der_id.end()) {
+            it = der_id.emplace(std::make_pair(a, b), P.n_base + (int)P.derived.size()).first;
+            P.derived.push_back({a, b});
+        }
+        return it->second;
+    };
+    for (auto &R : rq)
+        for (auto &ag : R.aggs)
+            for (auto &t : ag) {
+                if (t.second.size() <= 2) continue;
+                std::vector<int> ids;
+                for (auto &f : t.second) ids.push_back(feat_id[f]);
+                std::sort(ids.begin(), ids.end());
+                if (ids.size() == 3) derived_of(ids[1], ids[2]);
+                else { derived_of(ids[0], ids[1]); derived_of(ids[2], ids[3]); }
+            }
+    P.n_feat = P.n_base + (int)P.derived.size();
+    if (P.n_feat > kMaxFeat)
+        return fail(c, LMFAO_ERR_TOO_LARGE, "more than 63 continuous features and products of two of them");
     if (comp_slot > kMaxComp) return fail(c, LMFAO_ERR_TOO_LARGE, "more than 32 group-by components");
     P.own_preds.assign(m, {});
     for (size_t f = 0; f < P.filters.size(); ++f)
@@ -799,9 +840,14 @@ static lmfao_status build_logical(lmfao_ctx *c) {
 
     // ---- outputs: covariance block, tables (merge of same group-by + filter) --------
     auto mono = [&](const std::vector<ARef> &fs) -> std::pair<int, int> {
-        int a = fs.size() > 0 ? feat_id[fs[0]] : 0;
-        int b = fs.size() > 1 ? feat_id[fs[1]] : 0;
-        if (fs.size() == 1) { b = a; a = 0; }
+        std::vector<int> ids;
+        for (auto &f : fs) ids.push_back(feat_id[f]);
+        std::sort(ids.begin(), ids.end());
+        int a = 0, b = 0;
+        if (ids.size() == 1) b = ids[0];
+        else if (ids.size() == 2) { a = ids[0]; b = ids[1]; }
+        else if (ids.size() == 3) { a = ids[0]; b = der_id.at({ids[1], ids[2]}); }
+        else { a = der_id.at({ids[0], ids[1]}); b = der_id.at({ids[2], ids[3]}); }
         if (a > b) std::swap(a, b);
         return {a, b};
     };
@@ -967,6 +1013,35 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         P.rec_stride[r] = round_up(P.rec_feat_off[r] + P.sub_feat_n[r], 4);
         if (P.rec_stride[r] > kMaxRecWords) return fail(c, LMFAO_ERR_TOO_LARGE, "view record of " + c->rels[r].name + " too wide");
     }
+    // ---- many-to-many children: count-weighted views (see the header for the supported class) --
+    P.dup.assign(m, 0);
+    P.dup_pairs.assign(m, {});
+    P.weighted = false;
+    for (int r = 0; r < m; ++r)
+        if (r != P.root && c->rels[r].cols[P.pk_col[r]].kind == LMFAO_KEY_MANY) P.dup[r] = 1;
+    for (int r = 0; r < m; ++r) {
+        if (!P.dup[r]) continue;
+        const std::string nm = c->rels[r].name;
+        if (P.parent[r] != P.root || !P.children[r].empty())
+            return fail(c, LMFAO_ERR_UNSUPPORTED, "many-to-many relation " + nm + " must be a leaf child of the root");
+        if (!P.own_comps[r].empty())
+            return fail(c, LMFAO_ERR_UNSUPPORTED, "a group-by attribute of many-to-many relation " + nm);
+        if (!P.own_preds[r].empty())
+            return fail(c, LMFAO_ERR_UNSUPPORTED, "a predicate on many-to-many relation " + nm);
+        auto own = [&](int f) { return f >= P.sub_feat_lo[r] && f < P.sub_feat_lo[r] + P.sub_feat_n[r]; };
+        for (auto &d : P.derived)
+            if (own(d.first) || own(d.second))
+                return fail(c, LMFAO_ERR_UNSUPPORTED, "a product of three or four attributes with one of many-to-many relation " + nm);
+        for (auto &T : P.tables)
+            for (auto &v : T.vals)
+                if (own(v.first) && own(v.second))
+                    return fail(c, LMFAO_ERR_UNSUPPORTED, "a grouped sum of two attributes of many-to-many relation " + nm);
+        if (P.n_gram > 0) {
+            for (int a = P.sub_feat_lo[r]; a < P.sub_feat_lo[r] + P.sub_feat_n[r]; ++a)
+                for (int b = a; b < P.sub_feat_lo[r] + P.sub_feat_n[r]; ++b) P.dup_pairs[r].push_back({a, b});
+        }
+        P.weighted = true;
+    }
     // ---- statistics (Table 2 analogue) ---------------------------------------------------------
     P.app_aggs = 0;
     for (auto &Q : c->queries) P.app_aggs += 1 + (int)Q.aggs.size();
@@ -981,7 +1056,7 @@ static lmfao_status build_logical(lmfao_ctx *c) {
 // LDS layout of the root scan for a tile configuration (32-bit words).
 struct Layout {
     int n_fact = 0, n_aux = 0, n_quads = 0, nbuf = 2, waves = 2;
-    int w_fact = 0, w_aux = 0, w_rec = 0, w_comp = 0, wave_words = 0;
+    int w_fact = 0, w_aux = 0, w_rec = 0, w_comp = 0, w_der = 0, w_wgt = 0, wave_words = 0;
     int lds_consts = 0, lds_thr = 0, lds_wave = 0, lds_red = 0, thr_words = 0, ngp = 0;
     int total = 0;
 };
@@ -1010,6 +1085,10 @@ static Layout stage_layout(const Plan &P, int mode, int p1, bool tables, int tab
     w += nbuf * L.n_quads * 256;
     L.w_comp = w;
     if (tables) w += (int)P.comps.size() * 64;
+    L.w_der = w;
+    w += (int)P.derived.size() * kColPitch;
+    L.w_wgt = w;
+    if (P.weighted) w += 64;
     L.wave_words = round_up(w, 4);
     for (int ci : P.own_comps[P.root]) L.thr_words += (int)P.comps[ci].thr.size();
     int o = round_up(table_words, 4);
@@ -1117,7 +1196,7 @@ static int gram_products(int mode) { return mode == 3 ? 4 : (mode == 4 ? 6 : 3);
 // at most 2 such tiles), at most kGramMaxChild children with keys below 2^24, and a
 // root of at least 64 rows.  *nt and *nf receive its slot tiles and fact tiles.
 static bool gram_eligible(const lmfao_ctx *c, const Plan &P, int *nt, int *nf) {
-    if (P.mode < 2 || P.n_gram <= 0 || P.n_gram > kGramMaxSlots) return false;
+    if (P.mode < 2 || P.n_gram <= 0 || P.n_gram > kGramMaxSlots || !P.derived.empty() || P.weighted) return false;
     if ((int)P.children[P.root].size() > kGramMaxChild) return false;
     if (c->rels[P.root].n_rows < 64) return false;
     for (int ch : P.children[P.root])
@@ -1217,7 +1296,7 @@ static void plan_hist(const lmfao_ctx *c, Plan &P, int budget) {
     P.hist_part_begin.clear();
     P.hist_lds_words.clear();
     const Rel &root = c->rels[P.root];
-    if (c->opts.no_hist || P.schedule != LMFAO_BATCHED || P.lds_policy != 3 || root.n_rows <= 0) return;
+    if (c->opts.no_hist || P.schedule != LMFAO_BATCHED || P.lds_policy != 3 || root.n_rows <= 0 || P.weighted) return;
     std::vector<int> elig;
     bool spill = P.parts > 1;
     for (size_t f = 0; f < P.fams.size(); ++f) {
@@ -1305,6 +1384,8 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     Plan &P = c->plan;
     const Rel &root = c->rels[P.root];
     P.cfg = cfg;
+    if (P.weighted && P.n_gram > 0 && P.precision != LMFAO_FP32)
+        return fail(c, LMFAO_ERR_UNSUPPORTED, "many-to-many joins need the FP32 covariance form");
     P.mode = precision_mode(P);
     P.n_tiles16 = (P.n_gram + 15) / 16;
     if (P.mode == 1) {
@@ -1344,7 +1425,7 @@ static lmfao_status build_physical(lmfao_ctx *c, const TileCfg &cfg) {
     // tables and writes per-row codes; a code scan per partition, with the whole LDS for its
     // tables, replays them (when the codes fit their workspace cap)
     P.codes = false;
-    if (!c->opts.no_row_codes && P.schedule == LMFAO_BATCHED && P.lds_policy == 3 && P.parts > 1 && root.n_rows > 0 &&
+    if (!c->opts.no_row_codes && !P.weighted && P.schedule == LMFAO_BATCHED && P.lds_policy == 3 && P.parts > 1 && root.n_rows > 0 &&
         codes_eligible(P)) {
         P.n_mask_codes = P.filters.size() > 32 ? 2 : 1;
         P.n_codes = P.n_mask_codes;
@@ -1485,12 +1566,22 @@ static size_t compute_ws(lmfao_ctx *c) {
     o += kAlign;
     c->off_rec.assign(m, 0);
     c->off_seen.assign(m, 0);
+    c->off_dsum.assign(m, 0);
+    c->off_dscat.assign(m, 0);
+    c->off_hw.assign(m, 0);
     for (int r = 0; r < m; ++r) {
         if (r == P.root) continue;
         c->off_rec[r] = o;
         o = align_up(o + (size_t)P.n_keys[r] * P.rec_stride[r] * 4);
         c->off_seen[r] = o;
         o = align_up(o + (size_t)P.n_keys[r] * 4);
+        if (!P.dup[r]) continue;
+        c->off_dsum[r] = o;
+        o = align_up(o + (size_t)P.n_keys[r] * P.own_feats[r].size() * 8);
+        c->off_dscat[r] = o;
+        o = align_up(o + (size_t)P.n_keys[r] * P.dup_pairs[r].size() * 8);
+        c->off_hw[r] = o;
+        if (!P.dup_pairs[r].empty()) o = align_up(o + (size_t)P.n_keys[r] * 8);
     }
     c->off_gcnt = o;
     o = align_up(o + (size_t)P.table_cells * 8);
@@ -1573,6 +1664,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             s.feat_off = P.rec_feat_off[ch];
             s.n_feat = P.sub_feat_n[ch];
             s.feat_dst = P.sub_feat_lo[ch] - feat_base;
+            s.hw = P.dup[ch] && !P.dup_pairs[ch].empty() ? reinterpret_cast<double *>(ws + c->off_hw[ch]) : nullptr;
             v.push_back(s);
         }
         return v;
@@ -1580,9 +1672,59 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     // ---- view scans of non-root relations, grouped by level ----------------------------
     c->level_rels.assign(P.levels, {});
     c->view_desc_off.assign(m, 0);
+    c->dup_desc_off.assign(m, 0);
+    c->corr_desc_off.assign(m, 0);
     std::vector<ScanDesc> vdescs(m);
     for (int r = 0; r < m; ++r) {
         if (r == P.root) continue;
+        if (P.dup[r]) {
+            // many-to-many child: per-key aggregation instead of a one-row-per-key record
+            DupDesc d{};
+            d.n_rows = c->rels[r].n_rows;
+            d.key = static_cast<const int32_t *>(c->rels[r].cols[P.pk_col[r]].data);
+            std::vector<FeatSrc> fs;
+            for (int f : P.own_feats[r]) {
+                FeatSrc x{};
+                x.col = static_cast<const float *>(c->rels[r].cols[P.feats[f].col].data);
+                x.dst = f - P.sub_feat_lo[r];
+                fs.push_back(x);
+            }
+            std::sort(fs.begin(), fs.end(), [](const FeatSrc &a, const FeatSrc &b) { return a.dst < b.dst; });
+            std::vector<int32_t> ab, gab;
+            for (auto &pr : P.dup_pairs[r]) {
+                ab.push_back(pr.first - P.sub_feat_lo[r]);
+                ab.push_back(pr.second - P.sub_feat_lo[r]);
+                gab.push_back(pr.first);
+                gab.push_back(pr.second);
+            }
+            if (ab.empty()) ab.assign(2, 0);
+            if (gab.empty()) gab.assign(2, 0);
+            d.feats = reinterpret_cast<const FeatSrc *>(dev(B.vec(fs)));
+            d.pair_ab = reinterpret_cast<const int32_t *>(dev(B.vec(ab)));
+            d.n_keys = P.n_keys[r];
+            d.n_feat = (int)fs.size();
+            d.n_pair = (int)P.dup_pairs[r].size();
+            d.rec_stride = P.rec_stride[r];
+            d.rec_feat_off = P.rec_feat_off[r];
+            d.n_mask = P.n_mask;
+            d.filter_all = filter_all;
+            d.cnt = reinterpret_cast<uint32_t *>(ws + c->off_seen[r]);
+            d.sum = reinterpret_cast<double *>(ws + c->off_dsum[r]);
+            d.scat = reinterpret_cast<double *>(ws + c->off_dscat[r]);
+            d.rec_out = reinterpret_cast<uint32_t *>(ws + c->off_rec[r]);
+            d.err = err;
+            c->dup_desc_off[r] = B.put(&d, sizeof d);
+            CorrDesc cd{};
+            cd.n_keys = P.n_keys[r];
+            cd.n_pair = d.n_pair;
+            cd.n_gram = P.n_gram;
+            cd.hw = reinterpret_cast<const double *>(ws + c->off_hw[r]);
+            cd.scat = d.scat;
+            cd.gram_ab = reinterpret_cast<const int32_t *>(dev(B.vec(gab)));
+            cd.gram = reinterpret_cast<double *>(ws + c->off_gram);
+            c->corr_desc_off[r] = B.put(&cd, sizeof cd);
+            continue;
+        }
         c->level_rels[P.height[r]].push_back(r);
         ScanDesc d{};
         d.n_rows = c->rels[r].n_rows;
@@ -1674,6 +1816,12 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     // word of the row-major record buffer ((quad_base + w / 4) * 256 + w % 4)
     std::vector<int32_t> feat_src(std::max(1, P.n_feat), 0), comp_map(std::max<size_t>(1, P.comps.size()), -1);
     for (size_t j = 0; j < P.own_feats[r0].size(); ++j) feat_src[P.own_feats[r0][j]] = -1 - (int)j;
+    std::vector<int32_t> der_ab(std::max<size_t>(2, 2 * P.derived.size()), 0);
+    for (size_t j = 0; j < P.derived.size(); ++j) {
+        feat_src[P.n_base + j] = kDerivedSrc - (int)j;
+        der_ab[2 * j] = P.derived[j].first;
+        der_ab[2 * j + 1] = P.derived[j].second;
+    }
     for (size_t k = 0; k < P.children[r0].size(); ++k) {
         const int ch = P.children[r0][k];
         for (int i = 0; i < P.sub_feat_n[ch]; ++i) {
@@ -1685,7 +1833,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
             comp_map[P.sub_comp_lo[ch] + i] = (rch[k].quad_base + w / 4) * 256 + w % 4;
         }
     }
-    const size_t feat_src_off = B.vec(feat_src), comp_src_off = B.vec(comp_map);
+    const size_t feat_src_off = B.vec(feat_src), comp_src_off = B.vec(comp_map), der_ab_off = B.vec(der_ab);
     std::vector<uint64_t> fact_ptrs;
     for (int f : P.own_feats[r0]) fact_ptrs.push_back((uint64_t)(uintptr_t)c->rels[r0].cols[P.feats[f].col].data);
     while (fact_ptrs.size() % 16) fact_ptrs.push_back(0);   // the scan preloads 16 entries at a time
@@ -1868,6 +2016,14 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         D.n_thr_words = Ly.thr_words;
         D.fact_cols = reinterpret_cast<const float *const *>(dev(fact_cols_off));
         D.feat_src = reinterpret_cast<const int32_t *>(dev(feat_src_off));
+        D.n_der = (int)P.derived.size();
+        D.w_der = Ly.w_der;
+        D.der_ab = reinterpret_cast<const int32_t *>(dev(der_ab_off));
+        D.weighted = P.weighted ? 1 : 0;
+        D.w_wgt = Ly.w_wgt;
+        // weights up to 2^24 are exact in fp32, and a workgroup's weights add up below 2^32
+        // in its uint32 LDS counts
+        D.max_weight = (uint32_t)std::min<int64_t>(1 << 24, 0xFFFFFFFFll / std::max<int64_t>(1, L.desc.rows_per_block));
         D.comp_src = reinterpret_cast<const int32_t *>(dev(comp_src_off));
         D.aux_cols = reinterpret_cast<const float *const *>(dev(aux_off));
         D.thr_all = reinterpret_cast<const float *>(dev(thr_all_off));
@@ -2072,6 +2228,11 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         if (r == P.root) continue;
         fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_rec[r]), (int64_t)P.n_keys[r] * P.rec_stride[r]});
         fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_seen[r]), (int64_t)P.n_keys[r]});
+        if (!P.dup[r]) continue;
+        const int64_t nk = P.n_keys[r];
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_dsum[r]), nk * (int64_t)P.own_feats[r].size() * 2});
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_dscat[r]), nk * (int64_t)P.dup_pairs[r].size() * 2});
+        if (!P.dup_pairs[r].empty()) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_hw[r]), nk * 2});
     }
     if (P.table_cells) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gcnt), P.table_cells * 2});
     if (P.table_vals) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gval), P.table_vals * 2});
@@ -2323,6 +2484,9 @@ static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
     Plan &P = c->plan;
     uint8_t *db = c->ws + c->off_desc;
     HIP_TRY(c, launch_fill(db + c->fill_off, c->n_fills, st));
+    for (size_t r = 0; r < c->rels.size(); ++r)
+        if (P.dup[r])
+            HIP_TRY(c, launch_dup(reinterpret_cast<const DupDesc *>(db + c->dup_desc_off[r]), c->rels[r].n_rows, P.n_keys[r], st));
     for (int L = 0; L + 1 < P.levels; ++L) {
         const auto &rels = c->level_rels[L];
         if (rels.empty()) continue;
@@ -2339,6 +2503,9 @@ static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
     if (s != LMFAO_OK) return s;
     if (P.n_gram > 0 || P.need_count)
         HIP_TRY(c, launch_merge(reinterpret_cast<const MergeDesc *>(db + c->merge_off), P.n_gram, st));
+    for (size_t r = 0; r < c->rels.size(); ++r)
+        if (P.dup[r] && P.n_gram > 0)
+            HIP_TRY(c, launch_corr(reinterpret_cast<const CorrDesc *>(db + c->corr_desc_off[r]), (int)P.dup_pairs[r].size(), st));
     for (size_t i = 0; i < c->rollup_off.size(); ++i)
         HIP_TRY(c, launch_rollup(reinterpret_cast<const RollupDesc *>(db + c->rollup_off[i]),
                                  (int)P.rollup_passes[i].size(), c->rollup_cells[i], st));
@@ -2390,6 +2557,8 @@ extern "C" lmfao_status lmfao_sync(lmfao_ctx *c) {
     if (flags & kErrDomain) return fail(c, LMFAO_ERR_DOMAIN, "a categorical code lies outside its domain");
     if (flags & kErrKeyRange) return fail(c, LMFAO_ERR_DOMAIN, "a child key lies outside [0, domain)");
     if (flags & kErrDupKey) return fail(c, LMFAO_ERR_UNSUPPORTED, "a child relation has a duplicate join key");
+    if (flags & kErrWeight)
+        return fail(c, LMFAO_ERR_TOO_LARGE, "a fact row joins more tuples than the root scan counts exactly");
     return LMFAO_OK;
 }
 

@@ -183,6 +183,81 @@ __global__ __launch_bounds__(kBlock) void view_build_kernel(const ScanDesc *__re
     if (seen_before != 0u) gor(d.err, kErrDupKey);
 }
 
+// ---------------------------------------------------------------------------
+// many-to-many child views: per-key count, sums and pair sums (one thread per
+// row), then records and within-key scatter (one thread per key)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void dup_agg_kernel(const DupDesc *__restrict__ dp) {
+    const AS_CONST DupDesc &d = *cst(dp);
+    const int64_t row = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (row >= d.n_rows) return;
+    const int32_t k = gld(d.key)[row];
+    if (k < 0 || k >= d.n_keys) {
+        gor(d.err, kErrKeyRange);
+        return;
+    }
+    __hip_atomic_fetch_add(gst(d.cnt + k), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const AS_CONST FeatSrc *fs = cst(d.feats);
+    for (int i = 0; i < d.n_feat; ++i) gadd(d.sum + (int64_t)k * d.n_feat + fs[i].dst, (double)gld(fs[i].col)[row]);
+    const AS_CONST int32_t *ab = cst(d.pair_ab);
+    for (int p = 0; p < d.n_pair; ++p) {
+        // record feature index i is attribute fs[i] (dst == i), so a pair reads its two columns
+        const double xa = gld(fs[ab[2 * p]].col)[row], xb = gld(fs[ab[2 * p + 1]].col)[row];
+        gadd(d.scat + (int64_t)k * d.n_pair + p, xa * xb);   // a product of two fp32 values is exact in fp64
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void dup_final_kernel(const DupDesc *__restrict__ dp) {
+    const AS_CONST DupDesc &d = *cst(dp);
+    const int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (k >= d.n_keys) return;
+    const uint32_t n = gld(d.cnt)[k];
+    uint32_t *rec = d.rec_out + k * d.rec_stride;
+    gst(rec)[0] = n;
+    if (d.n_mask > 0) gst(rec)[1] = (uint32_t)d.filter_all;
+    if (d.n_mask > 1) gst(rec)[2] = (uint32_t)(d.filter_all >> 32);
+    if (n == 0u) return;   // no row with this key: the record stays zero and the key does not join
+    const double inv = 1.0 / (double)n;
+    const double *sm = d.sum + k * d.n_feat;
+    for (int i = 0; i < d.n_feat; ++i) gst(rec)[d.rec_feat_off + i] = __float_as_uint((float)(gld(sm)[i] * inv));
+    const AS_CONST int32_t *ab = cst(d.pair_ab);
+    double *q = d.scat + k * d.n_pair;
+    for (int p = 0; p < d.n_pair; ++p) {
+        const double sa = gld(sm)[ab[2 * p]], sb = gld(sm)[ab[2 * p + 1]];
+        gst(q)[p] = gld(q)[p] - sa * (sb * inv);
+    }
+}
+
+// covariance entries of two attributes of a many-to-many child: one workgroup per pair, the
+// keys summed in a fixed order (hw holds integers, so the sum does not depend on the run)
+__global__ __launch_bounds__(kBlock) void corr_kernel(const CorrDesc *__restrict__ dp) {
+    const AS_CONST CorrDesc &d = *cst(dp);
+    __shared__ double part[kBlock];
+    const int p = blockIdx.x;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < d.n_keys; k += kBlock) {
+        const double h = gld(d.hw)[k];
+        if (h != 0.0) s += h * gld(d.scat)[k * d.n_pair + p];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int a = cst(d.gram_ab)[2 * p], b = cst(d.gram_ab)[2 * p + 1];
+        double *g = d.gram;
+        gst(g)[a * d.n_gram + b] += part[0];
+        if (a != b) gst(g)[b * d.n_gram + a] += part[0];
+    }
+}
+
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
 
 // Where a staged feature of a tile lives in LDS: word(row) = base + buf * step + row * stride.
 struct FeatLoc {
@@ -194,6 +269,7 @@ __device__ __forceinline__ FeatLoc feat_loc(const RootDesc &d, int f, int src, i
     if (f == 0) return {d.lds_consts, 0, 1};                 // constant 1
     if (f >= d.n_feat) return {d.lds_consts + 64, 0, 1};     // padding feature 0
     if (src >= 0) return {wave + d.w_rec + src, d.n_quads * 256, 4};   // child record word
+    if (src <= kDerivedSrc) return {wave + d.w_der + (kDerivedSrc - src) * kColPitch, 0, 1};   // product, this tile
     return {wave + d.w_fact + (-1 - src) * kColPitch, d.n_fact * kColPitch, 1};
 }
 
@@ -392,12 +468,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         uint64_t mask = s.filter_all;
         const uint32_t *rb = W + d.w_rec + buf * d.n_quads * 256;
         const uint32_t *ab = W + d.w_aux + buf * d.n_aux * kColPitch;
+        unsigned long long w64 = 1ull;   // joined tuples this row stands for (weighted plans)
 #pragma unroll
         for (int c = 0; c < kMaxChild; ++c) {
             if (c < s.n_child) {
                 const uint4 q0 = *reinterpret_cast<const uint4 *>(rb + (children[c].quad_base * 64 + lane) * 4);
                 if (q0.x == 0u) valid = false;
                 if (s.n_mask > 0) mask &= (uint64_t)q0.y | (s.n_mask > 1 ? (uint64_t)q0.z << 32 : 0ull);
+                if (d.weighted) w64 = min(w64, 1ull << 32) * q0.x;
+            }
+        }
+        uint32_t wt = 1u;
+        if (d.weighted) {
+            if (valid && w64 > d.max_weight) gor(d.err, kErrWeight);
+            wt = valid ? (uint32_t)min(w64, (unsigned long long)d.max_weight) : 0u;
+            if (MODE == 1 && do_gram) W[d.w_wgt + lane] = __float_as_uint((float)wt);
+            if (do_gram && valid) {
+                // per key of a many-to-many child: the tuples reaching it over its own count
+#pragma unroll
+                for (int c = 0; c < kMaxChild; ++c) {
+                    if (c < s.n_child && children[c].hw) {
+                        const uint32_t n = rb[(children[c].quad_base * 64 + lane) * 4];
+                        const int32_t k = gld(children[c].fk)[row];
+                        gadd(children[c].hw + k, (double)wt / (double)n);
+                    }
+                }
             }
         }
         for (int p = 0; p < s.n_pred; ++p) {
@@ -428,9 +523,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             }
         }
         const uint64_t vm = __ballot(valid);
-        if (do_count) my_count += valid ? 1ull : 0ull;
+        if (do_count) my_count += valid ? (unsigned long long)wt : 0ull;
+        // derived features: the row's products of two staged features (fp32), one LDS column each
+        if (d.n_der > 0) {
+            const AS_CONST int32_t *ab = cst(d.der_ab);
+            for (int j = 0; j < d.n_der; ++j) {
+                const int fa = ab[2 * j], fb = ab[2 * j + 1];
+                const FeatLoc La = feat_loc(d, fa, gld(d.feat_src)[fa], wbase);
+                const FeatLoc Lb = feat_loc(d, fb, gld(d.feat_src)[fb], wbase);
+                const float v = fsm[La.base + buf * La.step + lane * La.stride] * fsm[Lb.base + buf * Lb.step + lane * Lb.stride];
+                W[d.w_der + j * kColPitch + lane] = __float_as_uint(v);
+            }
+            wave_sync();
+        }
 
         // ---- covariance block ---------------------------------------------------------------
+        if (MODE == 1 && do_gram && d.weighted) wave_sync();   // the tile's row weights are in LDS
         if (MODE == 1 && do_gram && gact) {
             int pa[GB], pb[GB];
 #pragma unroll
@@ -438,16 +546,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 pa[q] = la[q].base + buf * la[q].step;
                 pb[q] = lb[q].base + buf * lb[q].step;
             }
-            for (int r = gph; r < 64; r += nph) {
-                if (!((vm >> r) & 1ull)) continue;
-                float a[GB], b[GB];
+            auto rows = [&](auto weighted) {
+                for (int r = gph; r < 64; r += nph) {
+                    if (!((vm >> r) & 1ull)) continue;
+                    float a[GB], b[GB];
 #pragma unroll
-                for (int q = 0; q < GB; ++q) { a[q] = fsm[pa[q] + r * la[q].stride]; b[q] = fsm[pb[q] + r * lb[q].stride]; }
+                    for (int q = 0; q < GB; ++q) { a[q] = fsm[pa[q] + r * la[q].stride]; b[q] = fsm[pb[q] + r * lb[q].stride]; }
+                    if (decltype(weighted)::value) {
+                        const float wr = fsm[wbase + d.w_wgt + r];
 #pragma unroll
-                for (int i = 0; i < GB; ++i)
+                        for (int q = 0; q < GB; ++q) a[q] *= wr;
+                    }
 #pragma unroll
-                    for (int j = 0; j < GB; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
-            }
+                    for (int i = 0; i < GB; ++i)
+#pragma unroll
+                        for (int j = 0; j < GB; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+                }
+            };
+            if (d.weighted) rows(BoolTag<true>{});
+            else rows(BoolTag<false>{});
             if (++tiles_since_flush == 4) {
 #pragma unroll
                 for (int i = 0; i < GB; ++i)
@@ -544,6 +661,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             }
         } else if (TABLES && valid) {
             const uint32_t *cr = W + d.w_comp + lane;
+            const double wd = (double)wt;   // 1 unless the plan is weighted; products are exact in fp64
             auto fval = [&](int f) -> double {
                 const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
                 return (double)fsm[L.base + buf * L.step + lane * L.stride];
@@ -566,12 +684,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                                 const int bi = __ffsll((long long)b) - 1;
                                 b &= b - 1;
                                 const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
-                                atomicAdd(&smem[u + K.off_cnt + cell], 1u);
+                                atomicAdd(&smem[u + K.off_cnt + cell], wt);
                                 if (F.n_vals) {
                                     double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
                                     for (int v = 0; v < F.n_vals; ++v) {
                                         const AS_CONST ValDesc &vd = vals[F.val_base + v];
-                                        atomicAdd(vs + v, fval(vd.a) * fval(vd.b));
+                                        atomicAdd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                                     }
                                 }
                             }
@@ -600,18 +718,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         // in fp64 (runs of one dimension key repeat a value thousands of
                         // times in a row, beyond what fp32 sums exactly)
                         if (T.lds_cnt >= 0) {
-                            atomicAdd(&smem[d.lds_tables + T.lds_cnt + cell], 1u);
+                            atomicAdd(&smem[d.lds_tables + T.lds_cnt + cell], wt);
                             double *vs = reinterpret_cast<double *>(smem + d.lds_tables + T.lds_val) + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
-                                atomicAdd(vs + v, fval(vd.a) * fval(vd.b));
+                                atomicAdd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                             }
                         } else {
-                            gadd(d.g_cnt + T.glb_cnt + cell, 1ull);
+                            gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wt);
                             double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
-                                gadd(vs + v, fval(vd.a) * fval(vd.b));
+                                gadd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                             }
                         }
                     }
@@ -1088,6 +1206,18 @@ hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hi
     const int64_t blocks = (max_rows + kBlock - 1) / kBlock;
     if (blocks == 0 || n_scans == 0) return hipSuccess;
     hipLaunchKernelGGL(view_build_kernel, dim3((unsigned)blocks, (unsigned)n_scans), dim3(kBlock), 0, st, descs);
+    return hipGetLastError();
+}
+
+hipError_t launch_dup(const DupDesc *desc, int64_t n_rows, int64_t n_keys, hipStream_t st) {
+    const int64_t rb = (n_rows + kBlock - 1) / kBlock, kb = (n_keys + kBlock - 1) / kBlock;
+    if (rb > 0) hipLaunchKernelGGL(dup_agg_kernel, dim3((unsigned)rb), dim3(kBlock), 0, st, desc);
+    if (kb > 0) hipLaunchKernelGGL(dup_final_kernel, dim3((unsigned)kb), dim3(kBlock), 0, st, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr(const CorrDesc *desc, int n_pair, hipStream_t st) {
+    if (n_pair > 0) hipLaunchKernelGGL(corr_kernel, dim3(n_pair), dim3(kBlock), 0, st, desc);
     return hipGetLastError();
 }
 

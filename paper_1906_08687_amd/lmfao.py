@@ -20,7 +20,7 @@ OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "NOT_ACYCLIC", -3: "UNKNOWN_ATTR", -4: "TYPE", -5: "DOMAIN", -6: "TOO_LARGE",
           -7: "WORKSPACE", -8: "STATE", -9: "HIP", -10: "UNSUPPORTED"}
 I32, F32 = 0, 1
-KEY, CONT, CAT = 0, 1, 2
+KEY, CONT, CAT, KEY_MANY = 0, 1, 2, 3
 OPS = {"le": 0, "lt": 1, "ge": 2, "gt": 3, "eq": 4, "ne": 5}
 PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x4": 2, "bf16x6": 3}
 SCHEDULE = {"plain": 0, "batched": 1}
@@ -49,7 +49,7 @@ class _Pred(ctypes.Structure):
 
 
 class _Term(ctypes.Structure):
-    _fields_ = [("coeff", ctypes.c_double), ("n_factors", ctypes.c_int32), ("factors", ctypes.c_char_p * 2)]
+    _fields_ = [("coeff", ctypes.c_double), ("n_factors", ctypes.c_int32), ("factors", ctypes.c_char_p * 4)]
 
 
 class _Agg(ctypes.Structure):
@@ -233,8 +233,8 @@ class Context:
         for i, a in enumerate(q.aggs):
             terms = (_Term * max(1, len(a.terms)))()
             for j, (coeff, facs) in enumerate(a.terms):
-                names = (ctypes.c_char_p * 2)()
-                for k, f in enumerate(facs):
+                names = (ctypes.c_char_p * 4)()
+                for k, f in enumerate(facs[:4]):      # the library refuses more than four factors
                     b = f.encode()
                     keep.append(b)
                     names[k] = b
@@ -363,7 +363,7 @@ class Engine:
             for c in r.columns:
                 t = self.cols[(r.name, c.attr)]
                 dtype = F32 if c.kind == "cont" else I32
-                kind = {"key": KEY, "cont": CONT, "cat": CAT}[c.kind]
+                kind = {"key": KEY, "cont": CONT, "cat": CAT, "key_many": KEY_MANY}[c.kind]
                 spec.append((c.attr, dtype, kind, int(c.domain), _ptr(t)))
             self.ctx.add_relation(r.name, r.n_rows, spec)
         self.ctx.set_join_tree(db.edges)

@@ -275,9 +275,9 @@ def test_query_errors():
     expect("TYPE", lambda: ctx.add_query(Query(aggs=[Agg.monomial("k1")])))               # key as a factor
     expect("INVALID_ARG", lambda: ctx.add_query(Query(groupby=[GroupBy("y", [1.0, 0.0])])))
     expect("INVALID_ARG", lambda: ctx.add_query(Query(groupby=[GroupBy("y", [1.0, 1.0])])))
-    # a term names at most two factors: n_factors = 3 is refused before the array is read
-    names = (ctypes.c_char_p * 2)(b"x", b"y")
-    term = (lmfao._Term * 1)(lmfao._Term(1.0, 3, names))
+    # a term names at most four factors: n_factors = 5 is refused before the array is read
+    names = (ctypes.c_char_p * 4)(b"x", b"y", b"x", b"y")
+    term = (lmfao._Term * 1)(lmfao._Term(1.0, 5, names))
     agg = (lmfao._Agg * 1)(lmfao._Agg(1, term))
     q = lmfao._Query(0, None, 0, None, 1, agg)
     qid = ctypes.c_int32()
@@ -353,13 +353,13 @@ def _plan_db(db, qs, **kw):
         spec = []
         for c in r.columns:
             dtype = lmfao.F32 if c.kind == "cont" else lmfao.I32
-            kind = {"key": lmfao.KEY, "cont": lmfao.CONT, "cat": lmfao.CAT}[c.kind]
+            kind = {"key": lmfao.KEY, "cont": lmfao.CONT, "cat": lmfao.CAT, "key_many": lmfao.KEY_MANY}[c.kind]
             spec.append((c.attr, dtype, kind, int(c.domain), FAKE))
         ctx.add_relation(r.name, r.n_rows, spec)
     ctx.set_join_tree(db.edges)
     for q in qs:
         ctx.add_query(q)
-    ctx.plan("fp32", kw.pop("schedule", "batched"), **kw)
+    ctx.plan(kw.pop("precision", "fp32"), kw.pop("schedule", "batched"), **kw)
     return ctx
 
 
@@ -460,3 +460,52 @@ def test_training_reads_the_timing_file_and_checks_its_arguments(tmp_path):
     o = lmfao._TrainOpts(32, 0, 1e-3, 0, 1)                       # zero epochs
     assert lib.lmfao_train_cost_model(path.encode(), str(tmp_path / "w.bin").encode(), ctypes.byref(o),
                                       ctypes.c_void_p(FAKE), 1 << 30, None, None) == -1
+
+
+def test_polynomial_moments_are_planned_with_derived_products():
+    """Degree-2 polynomial regression (Section 2): the covariance over [1, x, x_i x_j]
+    holds every moment of degree <= 4; the plan stages each attribute and each product of
+    two attributes once (1 + n + n(n+1)/2 features) and runs the general root scan."""
+    from datagen import make_database
+    from datagen.configs import cont_attrs, polynomial_queries
+    db = make_database(1, n_fact=1000)
+    attrs = cont_attrs(db)[:6]
+    qs = polynomial_queries(attrs)
+    c = 1 + 6 + 21
+    assert len(qs) == c * (c + 1) // 2
+    st = _plan_db(db, qs).stats()
+    assert st["features"] == c and st["dedicated_scan"] == 0
+    # nine attributes: 1 + 9 + 45 = 55 staged values, within the 64 of the covariance block
+    assert _plan_db(db, polynomial_queries(cont_attrs(db)[:9])).stats()["features"] == 1 + 9 + 45
+
+
+def test_many_to_many_children_plan_as_count_weighted_views():
+    """A child whose join key repeats (KEY_MANY) is planned as a
+    count-weighted view: FP32 covariance, grouped sums keyed by other
+    relations and sums of its attributes plan; what the weighted view cannot
+    answer is refused at plan time with UNSUPPORTED: a BF16 covariance block,
+    a group-by or predicate on one of its attributes, a grouped sum of a
+    product of two of its attributes, a many-to-many relation below the root's
+    children, and a unique key declared on the parent side only."""
+    from datagen.configs import cont_attrs, covariance_queries, many_to_many_batch, many_to_many_database
+    import numpy as np
+    from datagen.schema import Agg, GroupBy, Pred, Query
+    db = many_to_many_database(n_fact=2000, n_users=50, n_business=40)
+    qs = many_to_many_batch(db)
+    st = _plan_db(db, qs).stats()
+    assert st["launches"] >= 1
+    for prec in ("bf16x3", "bf16x6"):
+        with pytest.raises(lmfao.LmfaoError) as e:
+            _plan_db(db, qs, precision=prec)
+        assert e.value.code == "UNSUPPORTED"
+    # tables only: any precision (tables are summed in fp64)
+    _plan_db(db, qs[len(covariance_queries(cont_attrs(db))):], precision="bf16x6")
+    bad = [Query(groupby=[GroupBy("cw", np.array([0.0, 1.0], np.float32))]),
+           Query(where=[Pred("aw", "gt", 0.0)]),
+           Query(groupby=[GroupBy("bcat")], aggs=[Agg.monomial("cw", "cv")])]
+    for q in bad:
+        with pytest.raises(lmfao.LmfaoError) as e:
+            _plan_db(db, [q])
+        assert e.value.code == "UNSUPPORTED", q
+    # the product of two attributes of one many-to-many child is fine ungrouped (covariance block)
+    _plan_db(db, [Query(aggs=[Agg.monomial("cw", "cv")])])

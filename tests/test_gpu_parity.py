@@ -171,3 +171,23 @@ def test_regression_tree_every_tile_candidate_agrees():
         eng.run()
         compare(eng.results(), ref, qs, RTOL["fp32"], "workload 3 candidate %s" % cfg)
     assert seen == {0, 1}
+
+
+@pytest.mark.parametrize("precision,schedule", [("fp32", "batched"), ("bf16x6", "batched"), ("fp32", "plain")])
+def test_polynomial_regression_moments(precision, schedule):
+    """Degree-2 polynomial regression (Section 2) over workload 1's nine continuous
+    attributes: every entry of U^T U for U = [1, x_i, x_i x_j] (1540 aggregates, products
+    of up to four attributes from the fact and both dimensions), plus degree-3 and 4
+    monomials grouped by a categorical attribute and under a filter."""
+    from datagen.configs import cont_attrs, polynomial_queries
+    db = make_database(1, n_fact=60_013)
+    attrs = cont_attrs(db)
+    qs = polynomial_queries(attrs)
+    qs += [Query([GroupBy("c")], [], [Agg.monomial("x1", "y2", "z1"), Agg.monomial("x2", "x2", "y3", "z2")]),
+           Query([], [Pred("z1", "gt", 0.0)], [Agg([(2.0, ("x1", "x3", "y1")), (-1.0, ("y1", "y1", "z2", "x4"))])])]
+    ref = oracle.evaluate(db, qs)
+    print("case: polynomial moments, %d queries, %s %s" % (len(qs), precision, schedule), flush=True)
+    eng = _engine(db, qs, precision=precision, schedule=schedule)
+    assert eng.stats()["features"] == 1 + 9 + 45
+    eng.run()
+    compare(eng.results(), ref, qs, RTOL[precision], "polynomial %s %s" % (precision, schedule))

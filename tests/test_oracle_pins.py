@@ -365,3 +365,57 @@ def test_aggregate_count_formulas():
     assert len(qs) == 32 * 30
     # RT: 32 nodes x 30 attributes x (COUNT + 2 sums) grouped by bucket
     assert sum(len(q.aggs) + 1 for q in qs) == 32 * 30 * 3
+
+
+def test_polynomial_moments_match_the_gram_of_the_monomial_vector():
+    """Degree-2 polynomial regression (Section 2): the batch's aggregates are the
+    entries of U^T U for U = [1, x_i, x_i x_j] over the materialised join
+    (numpy, math.fsum), ((C^2 + C) / 2 of them for C = C(n+2, 2))."""
+    from datagen.configs import polynomial_queries
+    db = make_database(1, n_fact=4_001)
+    J = materialize(db)
+    attrs = cont_attrs(db)[:4]
+    qs = polynomial_queries(attrs)
+    C = math.comb(len(attrs) + 2, 2)
+    assert len(qs) == (C * C + C) // 2
+    res = oracle.evaluate(db, qs, n_threads=4)
+    cols = [np.ones(len(J[attrs[0]]))] + [J[a] for a in attrs]
+    cols += [J[attrs[i]] * J[attrs[j]] for i in range(len(attrs)) for j in range(i, len(attrs))]
+    k = 0
+    for a in range(len(cols)):
+        for b in range(a, len(cols)):
+            r = res[k]
+            prod = cols[a] * cols[b]
+            if not qs[k].aggs:
+                assert int(r.counts[0]) == len(prod)
+            else:
+                ref = math.fsum(prod)
+                # the oracle forms each product of up to four fp32 values in fp64 (rounded once or twice)
+                assert abs(r.sums[0, 0] - ref) <= 1e-14 * math.fsum(np.abs(prod)) + 1e-300
+                assert abs(r.abs_sums[0, 0] - math.fsum(np.abs(prod))) <= 1e-12 * r.abs_sums[0, 0]
+            k += 1
+
+
+def test_oracle_many_to_many_star_matches_brute_force_and_closed_form_count():
+    """A Yelp-like star whose Category and Attribute children repeat the join
+    key (bag semantics of the natural join): the oracle equals the exact
+    brute force on every query of the many-to-many batch, and the size of the
+    join is sum over reviews of (categories x attributes of the business), a
+    closed form from per-key row counts."""
+    from datagen.configs import many_to_many_batch, many_to_many_database
+    db = many_to_many_database(n_fact=60, n_users=6, n_business=5, mean_cat=2, mean_attr=1, seed=3)
+    qs = many_to_many_batch(db)
+    got = oracle.evaluate(db, qs, n_threads=2)
+    exact = oracle.brute_force(db, qs)
+    for q, g, (cnt, sums, _) in zip(qs, got, exact):
+        assert list(g.counts) == cnt
+        for cell in range(len(cnt)):
+            for a in range(len(q.aggs)):
+                ref = float(sums[cell][a])
+                assert abs(g.sums[cell, a] - ref) <= 2 * math.ulp(max(abs(ref), 1e-300))
+    b = db.rel("Review").col("business").data
+    n_cat = np.bincount(db.rel("Category").col("business").data, minlength=5)
+    n_att = np.bincount(db.rel("Attribute").col("business").data, minlength=5)
+    count = [i for i, q in enumerate(qs) if not q.groupby and not q.where and not q.aggs]
+    total = int(np.sum(n_cat[b].astype(np.int64) * n_att[b]))
+    assert total > 0 and int(got[count[0]].counts[0]) == total

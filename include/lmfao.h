@@ -37,12 +37,16 @@
  * pair of them; the root scan weights each of its rows by the product of its
  * children's counts, and the covariance entries of two attributes of one
  * such child are completed from that child's scatter weighted by how often
- * the root reaches each key.  Supported: a many-to-many child that is a leaf
- * of the root, with continuous attributes summed (COUNT, SUM, the covariance
- * block, and grouped tables keyed by attributes of other relations); its
- * attributes may not be group-by or predicate attributes, a grouped table may
- * not sum a product of two of its attributes, and the covariance block runs
- * in FP32 (UNSUPPORTED otherwise).
+ * the root reaches each key.  A query that groups by, filters on, or (when
+ * grouped or filtered, or in a product of three or four factors) multiplies
+ * attributes of such a child is evaluated at that child as its root (see
+ * lmfao_plan_opts.root_policy): a view from the tree root keyed by the join
+ * key, each fact row weighted by the counts of the other children, joined
+ * with the child's rows.  Supported: many-to-many children that are leaves
+ * of the root; a query touching two of them that way, a grouped sum of a
+ * product of two attributes of one of them in a query evaluated elsewhere,
+ * and a BF16 covariance block with one, are UNSUPPORTED (the covariance
+ * block runs in FP32).
  *
  * Conventions
  *  - Every function returns lmfao_status: LMFAO_OK (0) or a negative error;
@@ -180,6 +184,7 @@ lmfao_status lmfao_add_query(lmfao_ctx *ctx, const lmfao_query *q, int32_t *qid)
 enum { LMFAO_FP32 = 0, LMFAO_BF16X3 = 1, LMFAO_BF16X4 = 2, LMFAO_BF16X6 = 3 }; /* covariance-block arithmetic */
 enum { LMFAO_PLAIN = 0, LMFAO_BATCHED = 1 };                        /* schedule */
 enum { LMFAO_HEURISTIC = 0, LMFAO_AUTOTUNE = 1, LMFAO_LEARNED = 2 }; /* tile/grouping choice */
+enum { LMFAO_ROOT_TREE = 0, LMFAO_ROOT_FIND = 1 };                  /* root of each query */
 
 typedef struct {
     int32_t precision;     /* FP32: fp32 FMAs; BF16X3: bf16 hi+lo split on MFMA (hi*hi+hi*lo+lo*hi),
@@ -211,6 +216,27 @@ typedef struct {
     int32_t no_hist;       /* 0: unfiltered COUNT-only tables that the root scan cannot keep in one LDS
                               partition are counted by the count-table scan (see lmfao_stats.hist_scan);
                               1: the root scan updates them.  Other values are INVALID_ARG. */
+    int32_t root_policy;   /* Where each query is evaluated (Section 3.3: each aggregate to its own
+                              root).  ROOT_TREE: at the join tree's root.  ROOT_FIND: the paper's
+                              root assignment: every grouped or filtered query gives each relation
+                              the fraction of its group-by attributes that relation holds (1/m to
+                              every relation when it has none); relations are taken by decreasing
+                              total weight, ties to the larger relation, and each becomes the root
+                              of every query not yet assigned that holds a group-by attribute in it
+                              (or has none).  Readings for the device: the ungrouped, unfiltered
+                              sums (the covariance block) stay at the tree root, where one fused scan
+                              computes them, and take no part in the weights; a relation below a
+                              child of the tree root passes its queries to that child; a query whose
+                              view towards its root would exceed 2^24 cells, or group by more than
+                              three attributes outside the root's subtree, stays at the tree root.
+                              A query at root R != tree root is evaluated by a view flowing from the
+                              tree root towards R (Section 3.2, directional views): a grouped table
+                              of the root scan keyed by the join key of R and the query's group-by
+                              attributes outside R's subtree, then a scan of R's keys (or, for a
+                              many-to-many R, of R's rows) that joins it with R's side of the query.
+                              Under both policies, a query that groups by, filters on or multiplies
+                              two attributes of one many-to-many child is evaluated at that child.
+                              Other values are INVALID_ARG. */
 } lmfao_plan_opts;
 
 /* Build the evaluation plan for all queries added so far. */
@@ -252,9 +278,15 @@ typedef struct {
                                     scan counts them into LDS slices of the tables, one partition of
                                     slices per grid row, adding its cells to the global u64 counts */
     int32_t hist_parts;          /* LDS partitions of the count-table scan */
+    int32_t target_queries;      /* queries evaluated at a root other than the join tree's root (see
+                                    lmfao_plan_opts.root_policy) */
 } lmfao_stats;
 
 lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);
+
+/* Relation at which query `qid` is evaluated (its root, Section 3.3), after
+ * lmfao_plan.  Errors: STATE before planning, INVALID_ARG for a bad qid. */
+lmfao_status lmfao_query_root(const lmfao_ctx *ctx, int32_t qid, int32_t *rel);
 
 /* ---- memory -------------------------------------------------------------- */
 
@@ -345,7 +377,10 @@ lmfao_status lmfao_autotune(lmfao_ctx *ctx, void *hip_stream, const char *timing
  * (inference runs on the device in the workspace), select the lowest
  * predicted time, execute it once on `hip_stream`, and store its index in
  * *best.  Keeps the heuristic configuration (and returns LMFAO_OK with
- * *best = -1) if the model is missing or predicts a non-finite time. */
+ * *best = -1) if the model is missing or predicts a non-finite time.  When
+ * the chosen configuration needs more workspace or result memory than is
+ * bound, it is selected but not executed and the context is left unbound:
+ * query the sizes and bind again before executing. */
 lmfao_status lmfao_choose_learned(lmfao_ctx *ctx, const char *weights, void *hip_stream, int32_t *best);
 
 /* Learned choice judged by measurement: rank every candidate with the cost

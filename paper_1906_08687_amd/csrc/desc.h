@@ -148,7 +148,8 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
     int32_t unit_words;
     int32_t part_base[kMaxParts];
     int32_t code_base;    // per-row codes: column of this family's first key
-    int32_t pad_c;
+    int32_t wdiv;         // weighted plans: root child whose record count divides the row weight
+                          // (views towards a many-to-many child), -1 none
 };
 
 constexpr int kColPitch = 68;     // words per 64-row LDS column (64 rows + 4 words of bank padding)
@@ -249,6 +250,61 @@ struct DupDesc {
     double *sum;                   // [n_keys][n_feat]
     double *scat;                  // [n_keys][n_pair]
     uint32_t *rec_out;
+    uint32_t *err;
+};
+
+// ---- queries evaluated at another root (directional views, Section 3.2-3.3) ----------
+//
+// A query whose root R is a child of the tree root is answered from a grouped table of the
+// root scan keyed by (join key of R, the query's group-by components outside R's subtree) --
+// the view flowing from the tree root towards R -- joined with R: one thread per key of R
+// (its view record carries R's subtree: validity, filter bit, components, features) or, for a
+// many-to-many R, per row of R (its columns, predicates evaluated here).  For every cell o of
+// the view's other components with a nonzero count, the query's cell gets the view's count and,
+// per aggregate, sum over terms of coeff * (R's factors) * (the view's sum of the other factors).
+struct TargetSrc {        // one group-by position of the query, in query order
+    int32_t from_o;       // >= 0: index among the view's non-key components; -1: R's side
+    int32_t rec_word;     // R's side, keyed R: record word of the component
+    int64_t stride;       // cell stride of this position in the query's result
+    CompSrc comp;         // R's side, many-to-many R: the attribute (column, thresholds, domain)
+};
+
+constexpr int kMaxTermFactors = 4;
+constexpr int kMaxTargetTerms = 16;   // terms of a query evaluated at another root
+
+struct TargetTerm {
+    int32_t agg;
+    int32_t val;                          // view value index of the other factors; -1: the view's count
+    double coeff;
+    int32_t n_fac;                        // factors on R's side (0..4)
+    int32_t rec_word[kMaxTermFactors];    // keyed R: record words
+    int32_t pad;
+    const float *col[kMaxTermFactors];    // many-to-many R: columns
+};
+
+struct TargetDesc {
+    int32_t dup;                     // 1: iterate R's rows (many-to-many); 0: R's keys
+    int32_t n_gb, n_terms, n_aggs;
+    int64_t n_items;                 // keys or rows of R
+    const int32_t *key;              // many-to-many: R's join key column
+    const uint32_t *rec;             // keyed: R's view records
+    int32_t rec_stride;
+    int32_t mask_word;               // keyed: record word holding the query's filter bit, -1 none
+    uint32_t mask_bit;
+    int32_t n_pred;
+    const PredSrc *preds;            // many-to-many: the query's predicates on R
+    const TargetSrc *gb;             // [n_gb]
+    const TargetTerm *terms;         // [n_terms]
+    int64_t n_ocells;                // view cells per key of R
+    int32_t n_o;                     // the view's non-key components
+    int32_t o_dom[kMaxKeyComps];     // their domains, in key order
+    int32_t n_vals;                  // sums per view cell
+    int32_t n_keys;                  // key domain of R
+    int32_t pad;
+    const unsigned long long *vcnt;  // the view: counts [n_keys * n_ocells]
+    const double *vval;              // sums [n_keys * n_ocells][n_vals]
+    unsigned long long *res_cnt;     // the query's result cells
+    double *res_sum;                 // [cells][n_aggs]
     uint32_t *err;
 };
 

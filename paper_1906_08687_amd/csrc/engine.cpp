@@ -54,6 +54,7 @@ hipError_t launch_fill(const void *fills, int n, hipStream_t st);
 hipError_t launch_views(const ScanDesc *descs, int n_scans, int64_t max_rows, hipStream_t st);
 hipError_t launch_dup(const DupDesc *desc, int64_t n_rows, int64_t n_keys, hipStream_t st);
 hipError_t launch_corr(const CorrDesc *desc, int n_pair, hipStream_t st);
+hipError_t launch_target(const TargetDesc *descs, int n_targets, int64_t max_items, hipStream_t st);
 hipError_t launch_root(RootKernel k, const RootDesc *desc, int grid_x, int parts, int waves, size_t lds_bytes,
                        hipStream_t st);
 hipError_t set_root_lds_limit(RootKernel k, size_t bytes);
@@ -146,6 +147,7 @@ struct Conj {              // one conjunct of a filter
 struct Table {
     std::vector<int> comps;             // component ids (group-by order)
     int filter = -1;                    // -1: none
+    int wdiv = -1;                      // view towards many-to-many child wdiv: rows weighted without its count
     std::vector<std::pair<int, int>> vals;   // monomials (feature a <= b), sorted
     int64_t n_cells = 1;
     // placement
@@ -166,6 +168,7 @@ struct Family {
     std::vector<int> filters;             // ascending filter ids; empty = unfiltered
     std::vector<int> tables;              // index f * n_keys + k -> table id
     bool hist = false;                    // counted by the count-table scan, not the root scan
+    int wdiv = -1;                        // as Table::wdiv, shared by the family's tables
 };
 
 struct OutTerm {
@@ -177,10 +180,33 @@ struct OutTerm {
 struct Output {
     bool gram = false;
     int table = -1;
+    int target = -1;                   // evaluated at another root: index into Plan::targets
     int64_t n_cells = 1;
     int n_aggs = 0;
     size_t cnt_off = 0, sum_off = 0;   // bytes in the result arena
     std::vector<OutTerm> terms;
+};
+
+// A query evaluated at a root R other than the tree root (R a child of it): the view from the
+// tree root towards R is the grouped table `table`, keyed by (fk_comp, o_comps); R's side is
+// joined by the target scan.
+struct TargetPlan {
+    int q = -1, rel = -1;
+    bool dup = false;                 // R is a many-to-many child: its rows are scanned
+    int filter = -1;
+    std::vector<int> gb_comp;         // per group-by position of the query: component id
+    std::vector<int> gb_o;            // per position: index among o_comps, -1 on R's side
+    std::vector<int> o_comps;         // group-by components outside R's subtree
+    int fk_comp = -1;
+    int table = -1;
+    struct Term {
+        int agg = 0;
+        double coeff = 1.0;
+        std::vector<ARef> rfac, ofac; // factors on R's side and outside it
+        int val = -1;                 // value of the view summing ofac (-1: its count)
+    };
+    std::vector<Term> terms;
+    int64_t n_cells = 1;
 };
 
 struct TileCfg {
@@ -238,6 +264,10 @@ struct Plan {
     std::vector<char> dup;
     std::vector<std::vector<std::pair<int, int>>> dup_pairs;
     bool weighted = false;
+    // roots per query (Section 3.3): the relation each query is evaluated at; queries at a child
+    // of the tree root are answered by a view towards it and the target scan
+    std::vector<int> qroot;
+    std::vector<TargetPlan> targets;
     // products of two staged attributes computed per row by the root scan (the degree-2 parts of
     // monomials of degree 3 and 4): staged features n_base .. n_feat-1
     std::vector<std::pair<int, int>> derived;
@@ -353,6 +383,9 @@ struct lmfao_ctx {
     std::vector<std::vector<int>> level_rels;     // relations per level (non-root)
     std::vector<size_t> view_desc_off;            // per relation: ScanDesc offset in blob
     size_t merge_off = 0, assemble_off = 0;
+    int n_assemble = 0;                           // outputs the assemble kernel writes
+    size_t target_desc_off = 0;                   // TargetDesc array (one per target query) in blob
+    int64_t target_items = 0;                     // most keys or rows of a target scan
     std::vector<size_t> rollup_off;               // per pass: RollupDesc offset in blob
     size_t off_codes = 0;                         // per-row codes
     size_t code_desc_off = 0;                     // CodeScanDesc offset in blob
@@ -772,6 +805,134 @@ static lmfao_status build_logical(lmfao_ctx *c) {
     }
     P.n_mask = P.filters.empty() ? 0 : (P.filters.size() <= 32 ? 1 : 2);
 
+    // ---- roots per query (Section 3.3) ----------------------------------------------------------
+    const int nq = (int)c->queries.size();
+    auto in_sub = [&](int rel, int R) {
+        for (int x = rel; x >= 0; x = P.parent[x])
+            if (x == R) return true;
+        return false;
+    };
+    auto top_of = [&](int r) {
+        while (r != P.root && P.parent[r] != P.root) r = P.parent[r];
+        return r;
+    };
+    auto is_dup = [&](int r) { return r != P.root && c->rels[r].cols[P.pk_col[r]].kind == LMFAO_KEY_MANY; };
+    auto gram_q = [&](int q) { return rq[q].comps.empty() && rq[q].filter < 0; };
+    P.qroot.assign(nq, P.root);
+    if (c->opts.root_policy == LMFAO_ROOT_FIND) {
+        // weights: each grouped or filtered query spreads 1 over the relations holding its group-by
+        // attributes (over all relations when it has none); roots go by decreasing weight, ties to
+        // the larger relation, each to every unassigned query that considered it
+        std::vector<double> W(m, 0.0);
+        for (int q = 0; q < nq; ++q) {
+            if (gram_q(q)) continue;
+            if (rq[q].comps.empty())
+                for (int r = 0; r < m; ++r) W[r] += 1.0 / m;
+            else
+                for (int ci : rq[q].comps) W[P.comps[ci].src.rel] += 1.0 / (double)rq[q].comps.size();
+        }
+        std::vector<int> ord(m);
+        for (int r = 0; r < m; ++r) ord[r] = r;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+            if (W[a] != W[b]) return W[a] > W[b];
+            return c->rels[a].n_rows > c->rels[b].n_rows;
+        });
+        std::vector<int> asg(nq, -1);
+        for (int R : ord) {
+            if (W[R] <= 0.0) continue;
+            for (int q = 0; q < nq; ++q) {
+                if (gram_q(q) || asg[q] >= 0) continue;
+                bool considered = rq[q].comps.empty();
+                for (int ci : rq[q].comps) considered = considered || P.comps[ci].src.rel == R;
+                if (considered) asg[q] = R;
+            }
+        }
+        for (int q = 0; q < nq; ++q)
+            if (asg[q] >= 0) P.qroot[q] = top_of(asg[q]);
+    }
+    // a query that groups by, filters on, or multiplies attributes of one many-to-many child is
+    // evaluated at that child
+    std::vector<char> forced(nq, 0);
+    for (int q = 0; q < nq; ++q) {
+        std::set<int> touched;
+        for (int ci : rq[q].comps)
+            if (is_dup(P.comps[ci].src.rel)) touched.insert(P.comps[ci].src.rel);
+        if (rq[q].filter >= 0)
+            for (auto &cj : P.filters[rq[q].filter])
+                if (is_dup(cj.src.rel)) touched.insert(cj.src.rel);
+        for (auto &ag : rq[q].aggs)
+            for (auto &t : ag) {
+                std::map<int, int> per;
+                for (auto &f : t.second)
+                    if (is_dup(f.rel)) ++per[f.rel];
+                for (auto &kv : per)
+                    if ((!gram_q(q) && kv.second >= 2) || t.second.size() >= 3) touched.insert(kv.first);
+            }
+        if (touched.size() > 1)
+            return fail(c, LMFAO_ERR_UNSUPPORTED, "query " + std::to_string(q) + " groups by, filters on or multiplies "
+                                                  "attributes of two many-to-many relations");
+        if (touched.size() == 1) {
+            P.qroot[q] = *touched.begin();
+            forced[q] = 1;
+        }
+    }
+    // views towards each root other than the tree root
+    std::map<int, int> fk_comp_of;
+    for (int q = 0; q < nq; ++q) {
+        const int R = P.qroot[q];
+        if (R == P.root) continue;
+        TargetPlan T;
+        T.q = q;
+        T.rel = R;
+        T.dup = is_dup(R);
+        T.filter = rq[q].filter;
+        int64_t ocells = 1;
+        for (int ci : rq[q].comps) {
+            T.gb_comp.push_back(ci);
+            T.n_cells *= P.comps[ci].dom;
+            if (in_sub(P.comps[ci].src.rel, R)) {
+                T.gb_o.push_back(-1);
+            } else {
+                T.gb_o.push_back((int)T.o_comps.size());
+                T.o_comps.push_back(ci);
+                ocells *= P.comps[ci].dom;
+            }
+        }
+        int n_terms = 0;
+        for (int a = 0; a < (int)rq[q].aggs.size(); ++a)
+            for (auto &t : rq[q].aggs[a]) {
+                TargetPlan::Term tt;
+                tt.agg = a;
+                tt.coeff = t.first;
+                for (auto &f : t.second) (in_sub(f.rel, R) ? tt.rfac : tt.ofac).push_back(f);
+                T.terms.push_back(tt);
+                ++n_terms;
+            }
+        const bool fits = (int)T.o_comps.size() < kMaxKeyComps && n_terms <= kMaxTargetTerms &&
+                          (double)P.n_keys[R] * (double)ocells <= (double)(1 << 24) &&
+                          (fk_comp_of.count(R) || (int)P.comps.size() < kMaxComp);
+        if (!fits) {
+            if (forced[q])
+                return fail(c, LMFAO_ERR_TOO_LARGE, "query " + std::to_string(q) + " at many-to-many relation " +
+                                                        c->rels[R].name + ": its view would group by more than three "
+                                                        "other attributes, exceed 2^24 cells, carry more than 16 terms "
+                                                        "or need a 33rd group-by component");
+            P.qroot[q] = P.root;
+            continue;
+        }
+        auto it = fk_comp_of.find(R);
+        if (it == fk_comp_of.end()) {
+            Comp cp;
+            cp.src = ARef{P.root, P.fk_col[R]};
+            cp.dom = P.n_keys[R];
+            it = fk_comp_of.emplace(R, (int)P.comps.size()).first;
+            P.comps.push_back(cp);
+        }
+        T.fk_comp = it->second;
+        P.targets.push_back(T);
+    }
+    if (P.targets.size() > 65535) return fail(c, LMFAO_ERR_TOO_LARGE, "more than 65535 queries at other roots");
+
     // ---- staged order: DFS over relations, own columns in column order --------------------
     P.feats.assign(1, ARef{});
     P.own_feats.assign(m, {});
@@ -820,16 +981,20 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         }
         return it->second;
     };
-    for (auto &R : rq)
-        for (auto &ag : R.aggs)
-            for (auto &t : ag) {
-                if (t.second.size() <= 2) continue;
-                std::vector<int> ids;
-                for (auto &f : t.second) ids.push_back(feat_id[f]);
-                std::sort(ids.begin(), ids.end());
-                if (ids.size() == 3) derived_of(ids[1], ids[2]);
-                else { derived_of(ids[0], ids[1]); derived_of(ids[2], ids[3]); }
-            }
+    auto derive_for = [&](const std::vector<ARef> &fs) {
+        if (fs.size() <= 2) return;
+        std::vector<int> ids;
+        for (auto &f : fs) ids.push_back(feat_id[f]);
+        std::sort(ids.begin(), ids.end());
+        if (ids.size() == 3) derived_of(ids[1], ids[2]);
+        else { derived_of(ids[0], ids[1]); derived_of(ids[2], ids[3]); }
+    };
+    for (int q = 0; q < nq; ++q)
+        if (P.qroot[q] == P.root)
+            for (auto &ag : rq[q].aggs)
+                for (auto &t : ag) derive_for(t.second);
+    for (auto &T : P.targets)   // a view towards another root sums the factors outside its subtree
+        for (auto &t : T.terms) derive_for(t.ofac);
     P.n_feat = P.n_base + (int)P.derived.size();
     if (P.n_feat > kMaxFeat)
         return fail(c, LMFAO_ERR_TOO_LARGE, "more than 63 continuous features and products of two of them");
@@ -851,12 +1016,44 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         if (a > b) std::swap(a, b);
         return {a, b};
     };
-    std::map<std::pair<std::vector<int>, int>, int> table_ids;
+    std::map<std::tuple<std::vector<int>, int, int>, int> table_ids;
+    auto table_of = [&](const std::vector<int> &comps, int filter, int wdiv) {
+        auto key = std::make_tuple(comps, filter, wdiv);
+        auto it = table_ids.find(key);
+        if (it == table_ids.end()) {
+            Table T;
+            T.comps = comps;
+            T.filter = filter;
+            T.wdiv = wdiv;
+            for (int ci : comps) T.n_cells *= P.comps[ci].dom;
+            it = table_ids.emplace(key, (int)P.tables.size()).first;
+            P.tables.push_back(T);
+        }
+        return it->second;
+    };
     bool gram_used = false;
     P.outs.resize(c->queries.size());
+    for (size_t ti = 0; ti < P.targets.size(); ++ti) {
+        TargetPlan &T = P.targets[ti];
+        Output &O = P.outs[T.q];
+        O.target = (int)ti;
+        O.n_aggs = (int)rq[T.q].aggs.size();
+        O.n_cells = T.n_cells;
+        std::vector<int> key{T.fk_comp};
+        key.insert(key.end(), T.o_comps.begin(), T.o_comps.end());
+        T.table = table_of(key, T.filter, T.dup ? T.rel : -1);
+        for (auto &t : T.terms) {
+            if (t.ofac.empty()) continue;
+            auto mo = mono(t.ofac);
+            auto &v = P.tables[T.table].vals;
+            if (std::find(v.begin(), v.end(), mo) == v.end()) v.push_back(mo);
+            t.val = mo.first * 1000 + mo.second;   // resolved below
+        }
+    }
     for (size_t qi = 0; qi < c->queries.size(); ++qi) {
         RQ &R = rq[qi];
         Output &O = P.outs[qi];
+        if (O.target >= 0) continue;
         O.n_aggs = (int)R.aggs.size();
         if (R.comps.empty() && R.filter < 0) {
             O.gram = true;
@@ -871,17 +1068,7 @@ static lmfao_status build_logical(lmfao_ctx *c) {
                     }
                 }
         } else {
-            auto key = std::make_pair(R.comps, R.filter);
-            auto it = table_ids.find(key);
-            if (it == table_ids.end()) {
-                Table T;
-                T.comps = R.comps;
-                T.filter = R.filter;
-                for (int ci : R.comps) T.n_cells *= P.comps[ci].dom;
-                it = table_ids.emplace(key, (int)P.tables.size()).first;
-                P.tables.push_back(T);
-            }
-            O.table = it->second;
+            O.table = table_of(R.comps, R.filter, -1);
             O.n_cells = P.tables[O.table].n_cells;
             for (int a = 0; a < O.n_aggs; ++a)
                 for (auto &t : R.aggs[a]) {
@@ -911,7 +1098,7 @@ static lmfao_status build_logical(lmfao_ctx *c) {
             for (size_t u = 0; u < P.tables.size(); ++u) {
                 const Table &U = P.tables[u];
                 const Table &T = P.tables[t];
-                if (U.filter != T.filter || U.comps.size() != T.comps.size() + 1) continue;
+                if (U.filter != T.filter || U.wdiv != T.wdiv || U.comps.size() != T.comps.size() + 1) continue;
                 bool has_vals = true;
                 for (auto &v : T.vals)
                     if (std::find(U.vals.begin(), U.vals.end(), v) == U.vals.end()) has_vals = false;
@@ -948,6 +1135,12 @@ static lmfao_status build_logical(lmfao_ctx *c) {
             T.vmap.push_back((int)(it - uv.begin()));
         }
     }
+    for (auto &T : P.targets)
+        for (auto &t : T.terms) {
+            if (t.val < 0) continue;
+            auto &v = P.tables[T.table].vals;
+            t.val = (int)(std::find(v.begin(), v.end(), std::make_pair(t.val / 1000, t.val % 1000)) - v.begin());
+        }
     for (auto &O : P.outs)
         for (auto &t : O.terms) {
             if (t.src < 0) continue;
@@ -958,41 +1151,47 @@ static lmfao_status build_logical(lmfao_ctx *c) {
                 t.src = (int)(std::find(v.begin(), v.end(), std::make_pair(a, b)) - v.begin());
             }
         }
-    // ---- families: tables with equal value lists and equal key lists across filters ----
-    std::map<std::pair<std::vector<std::pair<int, int>>, int>, std::vector<int>> by_vf;
-    for (size_t t = 0; t < P.tables.size(); ++t)
-        if (P.tables[t].from < 0) by_vf[{P.tables[t].vals, P.tables[t].filter}].push_back((int)t);
-    std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, std::vector<int>> fam_of;
-    std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, bool> fam_unf;
-    for (auto &kv : by_vf) {
-        std::vector<std::vector<int>> keys;
-        for (int t : kv.second) keys.push_back(P.tables[t].comps);
-        auto fk = std::make_pair(kv.first.first, keys);
-        if (kv.first.second < 0) {
+    // ---- families: tables with equal value lists and equal key lists across filters (and equal
+    // row weighting) ----
+    std::set<int> wdivs;
+    for (auto &T : P.tables) wdivs.insert(T.wdiv);
+    for (int wd : wdivs) {
+        std::map<std::pair<std::vector<std::pair<int, int>>, int>, std::vector<int>> by_vf;
+        for (size_t t = 0; t < P.tables.size(); ++t)
+            if (P.tables[t].from < 0 && P.tables[t].wdiv == wd) by_vf[{P.tables[t].vals, P.tables[t].filter}].push_back((int)t);
+        std::map<std::pair<std::vector<std::pair<int, int>>, std::vector<std::vector<int>>>, std::vector<int>> fam_of;
+        for (auto &kv : by_vf) {
+            std::vector<std::vector<int>> keys;
+            for (int t : kv.second) keys.push_back(P.tables[t].comps);
+            auto fk = std::make_pair(kv.first.first, keys);
+            if (kv.first.second < 0) {
+                Family F;
+                F.vals = kv.first.first;
+                F.keys = keys;
+                F.tables = kv.second;
+                F.wdiv = wd;
+                P.fams.push_back(F);
+            } else {
+                fam_of[fk].push_back(kv.first.second);
+            }
+        }
+        for (auto &kv : fam_of) {
             Family F;
             F.vals = kv.first.first;
-            F.keys = keys;
-            F.tables = kv.second;
+            F.keys = kv.first.second;
+            F.filters = kv.second;
+            F.wdiv = wd;
+            std::sort(F.filters.begin(), F.filters.end());
+            for (int f : F.filters)
+                for (auto &k : F.keys) {
+                    auto &lst = by_vf[{F.vals, f}];
+                    int found = -1;
+                    for (int t : lst)
+                        if (P.tables[t].comps == k) found = t;
+                    F.tables.push_back(found);
+                }
             P.fams.push_back(F);
-        } else {
-            fam_of[fk].push_back(kv.first.second);
         }
-    }
-    for (auto &kv : fam_of) {
-        Family F;
-        F.vals = kv.first.first;
-        F.keys = kv.first.second;
-        F.filters = kv.second;
-        std::sort(F.filters.begin(), F.filters.end());
-        for (int f : F.filters)
-            for (auto &k : F.keys) {
-                auto &lst = by_vf[{F.vals, f}];
-                int found = -1;
-                for (int t : lst)
-                    if (P.tables[t].comps == k) found = t;
-                F.tables.push_back(found);
-            }
-        P.fams.push_back(F);
     }
     P.table_cells = 0;
     P.table_vals = 0;
@@ -1024,10 +1223,8 @@ static lmfao_status build_logical(lmfao_ctx *c) {
         const std::string nm = c->rels[r].name;
         if (P.parent[r] != P.root || !P.children[r].empty())
             return fail(c, LMFAO_ERR_UNSUPPORTED, "many-to-many relation " + nm + " must be a leaf child of the root");
-        if (!P.own_comps[r].empty())
-            return fail(c, LMFAO_ERR_UNSUPPORTED, "a group-by attribute of many-to-many relation " + nm);
-        if (!P.own_preds[r].empty())
-            return fail(c, LMFAO_ERR_UNSUPPORTED, "a predicate on many-to-many relation " + nm);
+        // its group-by and predicate attributes belong to queries evaluated at it (the target scan
+        // reads them from its rows; its per-key record carries neither)
         auto own = [&](int f) { return f >= P.sub_feat_lo[r] && f < P.sub_feat_lo[r] + P.sub_feat_n[r]; };
         for (auto &d : P.derived)
             if (own(d.first) || own(d.second))
@@ -1897,6 +2094,11 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         for (int fi : L.fam_ids) {
             const Family &F = P.fams[fi];
             FamilyDesc fd{};
+            {
+                const int wr = L.single_table >= 0 ? P.tables[L.single_table].wdiv : F.wdiv;
+                const auto &kids = P.children[P.root];
+                fd.wdiv = wr < 0 ? -1 : (int)(std::find(kids.begin(), kids.end(), wr) - kids.begin());
+            }
             fd.unfiltered = F.filters.empty();
             fd.n_filt = fd.unfiltered ? 1 : (int)F.filters.size();
             fd.filt_base = (int)fbits.size();
@@ -2152,6 +2354,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     std::vector<TermDesc> terms;
     std::vector<int32_t> tcount;
     for (auto &O : P.outs) {
+        if (O.target >= 0) continue;   // written by the target scan
         OutDesc od{};
         od.kind = O.gram ? SRC_GRAM : SRC_TABLE;
         od.n_aggs = O.n_aggs;
@@ -2183,7 +2386,84 @@ static lmfao_status build_blob(lmfao_ctx *c) {
     ad.res_sum = reinterpret_cast<double *>(c->res);
     c->assemble_off = B.put(&ad, sizeof ad);
     c->assemble_cells = 0;
-    for (auto &O : P.outs) c->assemble_cells = std::max(c->assemble_cells, O.n_cells);
+    for (auto &O : P.outs)
+        if (O.target < 0) c->assemble_cells = std::max(c->assemble_cells, O.n_cells);
+    c->n_assemble = (int)outs.size();
+    // ---- queries at other roots: the view towards R joined with R's keys or rows -----------
+    std::vector<TargetDesc> tdescs;
+    c->target_items = 0;
+    for (auto &T : P.targets) {
+        const int R = T.rel;
+        const Output &O = P.outs[T.q];
+        const Table &V = P.tables[T.table];
+        TargetDesc td{};
+        td.dup = T.dup ? 1 : 0;
+        td.n_gb = (int)T.gb_comp.size();
+        td.n_terms = (int)T.terms.size();
+        td.n_aggs = O.n_aggs;
+        td.n_items = T.dup ? c->rels[R].n_rows : P.n_keys[R];
+        td.n_keys = P.n_keys[R];
+        td.key = static_cast<const int32_t *>(c->rels[R].cols[P.pk_col[R]].data);
+        td.rec = reinterpret_cast<const uint32_t *>(ws + c->off_rec[R]);
+        td.rec_stride = P.rec_stride[R];
+        td.mask_word = -1;
+        if (!T.dup && T.filter >= 0) {
+            td.mask_word = 1 + T.filter / 32;
+            td.mask_bit = 1u << (T.filter % 32);
+        }
+        std::vector<PredSrc> tp;
+        if (T.dup)
+            for (auto &p : preds_of(R))
+                if (p.filter == T.filter) tp.push_back(p);
+        td.n_pred = (int)tp.size();
+        td.preds = reinterpret_cast<const PredSrc *>(dev(B.vec(tp)));
+        std::vector<TargetSrc> gs(T.gb_comp.size());
+        int64_t stride = 1;
+        for (int i = (int)T.gb_comp.size() - 1; i >= 0; --i) {
+            const int ci = T.gb_comp[i];
+            TargetSrc &g = gs[i];
+            g.from_o = T.gb_o[i];
+            g.stride = stride;
+            stride *= P.comps[ci].dom;
+            if (g.from_o >= 0) continue;
+            if (T.dup) g.comp = comp_src(ci);
+            else g.rec_word = P.rec_comp_off[R] + P.comps[ci].slot - P.sub_comp_lo[R];
+        }
+        td.gb = reinterpret_cast<const TargetSrc *>(dev(B.vec(gs)));
+        std::vector<TargetTerm> tt;
+        for (auto &t : T.terms) {
+            TargetTerm x{};
+            x.agg = t.agg;
+            x.val = t.val;
+            x.coeff = t.coeff;
+            x.n_fac = (int)t.rfac.size();
+            for (size_t j = 0; j < t.rfac.size(); ++j) {
+                const ARef &f = t.rfac[j];
+                x.col[j] = static_cast<const float *>(c->rels[f.rel].cols[f.col].data);
+                int fid = 0;
+                for (size_t k = 0; k < P.feats.size(); ++k)
+                    if (P.feats[k] == f) fid = (int)k;
+                x.rec_word[j] = P.rec_feat_off[R] + fid - P.sub_feat_lo[R];
+            }
+            tt.push_back(x);
+        }
+        td.terms = reinterpret_cast<const TargetTerm *>(dev(B.vec(tt)));
+        td.n_o = (int)T.o_comps.size();
+        td.n_ocells = 1;
+        for (int j = 0; j < td.n_o; ++j) {
+            td.o_dom[j] = P.comps[T.o_comps[j]].dom;
+            td.n_ocells *= td.o_dom[j];
+        }
+        td.n_vals = (int)V.vals.size();
+        td.vcnt = gcnt + V.glb_cnt;
+        td.vval = gval + V.glb_val;
+        td.res_cnt = reinterpret_cast<unsigned long long *>(c->res + O.cnt_off);
+        td.res_sum = reinterpret_cast<double *>(c->res + O.sum_off);
+        td.err = err;
+        tdescs.push_back(td);
+        c->target_items = std::max(c->target_items, td.n_items);
+    }
+    c->target_desc_off = B.vec(tdescs);
     // ---- marginal derivation passes ------------------------------------------------------------
     c->rollup_off.clear();
     c->rollup_cells.clear();
@@ -2233,6 +2513,11 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_dsum[r]), nk * (int64_t)P.own_feats[r].size() * 2});
         fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_dscat[r]), nk * (int64_t)P.dup_pairs[r].size() * 2});
         if (!P.dup_pairs[r].empty()) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(ws + c->off_hw[r]), nk * 2});
+    }
+    for (auto &T : P.targets) {   // the target scan adds into the query's result
+        const Output &O = P.outs[T.q];
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(c->res + O.cnt_off), O.n_cells * 2});
+        fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(c->res + O.sum_off), O.n_cells * O.n_aggs * 2});
     }
     if (P.table_cells) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gcnt), P.table_cells * 2});
     if (P.table_vals) fills.push_back(FillDesc{reinterpret_cast<uint32_t *>(gval), P.table_vals * 2});
@@ -2290,7 +2575,7 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     if (o.precision < LMFAO_FP32 || o.precision > LMFAO_BF16X6 || o.schedule < LMFAO_PLAIN || o.schedule > LMFAO_BATCHED ||
         o.planner < LMFAO_HEURISTIC || o.planner > LMFAO_LEARNED || o.block_rows != 0 || o.grid_blocks < 0 ||
         o.scan_every_table < 0 || o.scan_every_table > 1 || o.no_row_codes < 0 || o.no_row_codes > 1 ||
-        o.no_hist < 0 || o.no_hist > 1 ||
+        o.no_hist < 0 || o.no_hist > 1 || o.root_policy < LMFAO_ROOT_TREE || o.root_policy > LMFAO_ROOT_FIND ||
         !(o.gram_block == 0 || o.gram_block == 2 || o.gram_block == 4 || o.gram_block == 6 || o.gram_block == 8))
         return fail(c, LMFAO_ERR_INVALID_ARG, "bad plan options");
     invalidate(c);
@@ -2303,6 +2588,14 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
     cfg.gram_block = o.gram_block;
     cfg.lds_policy = -1;
     return do_plan(c, cfg);
+}
+
+extern "C" lmfao_status lmfao_query_root(const lmfao_ctx *c, int32_t qid, int32_t *rel) {
+    if (!c || !rel) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (qid < 0 || qid >= (int)c->plan.qroot.size()) return LMFAO_ERR_INVALID_ARG;
+    *rel = c->plan.qroot[qid];
+    return LMFAO_OK;
 }
 
 extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
@@ -2323,14 +2616,18 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     s->code_scan = P.codes ? 1 : 0;
     s->hist_scan = P.hist ? 1 : 0;
     s->hist_parts = P.hist ? (int32_t)P.hist_lds_words.size() : 0;
+    s->target_queries = (int32_t)P.targets.size();
     s->table_cells = P.table_cells;
     int launches = 1;   // fill
     for (int L = 0; L < P.levels - 1; ++L) {
         int nrel = 0;
         for (int r = 0; r < (int)c->rels.size(); ++r)
-            if (r != P.root && P.height[r] == L) ++nrel;
+            if (r != P.root && P.height[r] == L && !P.dup[r]) ++nrel;
         launches += P.schedule == LMFAO_BATCHED ? (nrel > 0) : nrel;
     }
+    for (int r = 0; r < (int)c->rels.size(); ++r)
+        if (P.dup[r]) launches += 2 + (P.n_gram > 0 && !P.dup_pairs[r].empty() ? 1 : 0);   // view build, correction
+    launches += P.targets.empty() ? 0 : 1;
     launches += (int)P.root_launches.size() + (P.codes ? 1 : 0) + (P.hist ? 1 : 0);
     if (P.n_gram > 0 || P.need_count) launches += 1;
     launches += (int)P.rollup_passes.size();
@@ -2509,7 +2806,10 @@ static lmfao_status enqueue_all(lmfao_ctx *c, hipStream_t st) {
     for (size_t i = 0; i < c->rollup_off.size(); ++i)
         HIP_TRY(c, launch_rollup(reinterpret_cast<const RollupDesc *>(db + c->rollup_off[i]),
                                  (int)P.rollup_passes[i].size(), c->rollup_cells[i], st));
-    HIP_TRY(c, launch_assemble(reinterpret_cast<const AssembleDesc *>(db + c->assemble_off), (int)P.outs.size(),
+    if (!P.targets.empty())
+        HIP_TRY(c, launch_target(reinterpret_cast<const TargetDesc *>(db + c->target_desc_off), (int)P.targets.size(),
+                                 c->target_items, st));
+    HIP_TRY(c, launch_assemble(reinterpret_cast<const AssembleDesc *>(db + c->assemble_off), c->n_assemble,
                                c->assemble_cells, st));
     return LMFAO_OK;
 }
@@ -3026,6 +3326,10 @@ extern "C" lmfao_status lmfao_choose_learned(lmfao_ctx *c, const char *weights, 
     if (!predict_candidates(c, weights, hip_stream, cands, y, &s)) return s;   // heuristic stays unless an error
     const int bi = (int)(std::min_element(y.begin(), y.end()) - y.begin());
     s = select_cfg(c, cands[bi]);
+    if (s == LMFAO_OK && !c->bound) {   // needs more workspace or result memory than is bound
+        if (best) *best = bi;
+        return LMFAO_OK;
+    }
     if (s == LMFAO_OK) s = lmfao_execute(c, hip_stream);
     if (s == LMFAO_OK) s = lmfao_sync(c);
     if (s != LMFAO_OK) return s;

@@ -254,6 +254,74 @@ __global__ __launch_bounds__(kBlock) void corr_kernel(const CorrDesc *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// queries at another root: the view from the tree root joined with R's keys
+// or rows (grid-stride over R; results accumulated with fp64 / u64 atomics)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void target_scan_kernel(const TargetDesc *__restrict__ dp) {
+    const AS_CONST TargetDesc &d = cst(dp)[blockIdx.y];   // one query per grid row
+    const AS_CONST TargetSrc *gb = cst(d.gb);
+    const AS_CONST TargetTerm *terms = cst(d.terms);
+    for (int64_t item = blockIdx.x * (int64_t)kBlock + threadIdx.x; item < d.n_items;
+         item += (int64_t)gridDim.x * kBlock) {
+        int64_t k;
+        const uint32_t *rec = nullptr;
+        if (d.dup) {
+            k = gld(d.key)[item];
+            if (k < 0 || k >= d.n_keys) continue;   // reported by the many-to-many view build
+            bool ok = true;
+            for (int p = 0; p < d.n_pred && ok; ++p) ok = pred_holds(cst(d.preds)[p], item);
+            if (!ok) continue;
+        } else {
+            k = item;
+            rec = d.rec + k * d.rec_stride;
+            if (gld(rec)[0] == 0u) continue;
+            if (d.mask_word >= 0 && !(gld(rec)[d.mask_word] & d.mask_bit)) continue;
+        }
+        // R's side of the cell and of every term
+        int64_t base = 0;
+        for (int i = 0; i < d.n_gb; ++i) {
+            const AS_CONST TargetSrc &g = gb[i];
+            if (g.from_o >= 0) continue;
+            const int32_t v = d.dup ? comp_value(g.comp, item, d.err) : (int32_t)gld(rec)[g.rec_word];
+            base += (int64_t)v * g.stride;
+        }
+        double rf[kMaxTargetTerms];
+        for (int t = 0; t < d.n_terms && t < kMaxTargetTerms; ++t) {
+            const AS_CONST TargetTerm &T = terms[t];
+            double f = T.coeff;
+            for (int j = 0; j < T.n_fac; ++j)
+                f *= d.dup ? (double)gld(T.col[j])[item] : (double)__uint_as_float(gld(rec)[T.rec_word[j]]);
+            rf[t] = f;
+        }
+        const int64_t v0 = k * d.n_ocells;
+        for (int64_t o = 0; o < d.n_ocells; ++o) {
+            const unsigned long long cnt = gld(d.vcnt)[v0 + o];
+            if (cnt == 0ull) continue;
+            int64_t cell = base, rem = o;
+            int digit[kMaxKeyComps];
+            for (int j = d.n_o - 1; j >= 0; --j) {
+                digit[j] = (int)(rem % d.o_dom[j]);
+                rem /= d.o_dom[j];
+            }
+            for (int i = 0; i < d.n_gb; ++i)
+                if (gb[i].from_o >= 0) cell += (int64_t)digit[gb[i].from_o] * gb[i].stride;
+            gadd(d.res_cnt + cell, cnt);
+            const double *vv = d.vval + (v0 + o) * d.n_vals;
+            for (int a = 0; a < d.n_aggs; ++a) {
+                double s = 0.0;
+                for (int t = 0; t < d.n_terms && t < kMaxTargetTerms; ++t) {
+                    if (terms[t].agg != a) continue;
+                    const int vi = terms[t].val;
+                    s += rf[t] * (vi < 0 ? (double)cnt : gld(vv)[vi]);
+                }
+                if (s != 0.0) gadd(d.res_sum + cell * d.n_aggs + a, s);
+            }
+        }
+    }
+}
+
 template <bool B>
 struct BoolTag {
     static constexpr bool value = B;
@@ -661,13 +729,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             }
         } else if (TABLES && valid) {
             const uint32_t *cr = W + d.w_comp + lane;
-            const double wd = (double)wt;   // 1 unless the plan is weighted; products are exact in fp64
             auto fval = [&](int f) -> double {
                 const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
                 return (double)fsm[L.base + buf * L.step + lane * L.stride];
             };
             for (int fi = 0; fi < d.n_fam; ++fi) {
                 const AS_CONST FamilyDesc &F = fams[fi];
+                // the row's weight: 1 unless the plan is weighted; a view towards a many-to-many
+                // child leaves that child's own count out (products stay exact in fp64)
+                const uint32_t wf = F.wdiv >= 0 ? wt / rb[(children[F.wdiv].quad_base * 64 + lane) * 4] : wt;
+                const double wd = (double)wf;
                 if (F.strided) {
                     // the cell of each key once per row, then one update per filter this row
                     // satisfies, at an address computed from the filter's rank in the partition
@@ -684,7 +755,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                                 const int bi = __ffsll((long long)b) - 1;
                                 b &= b - 1;
                                 const uint32_t u = tb + (uint32_t)__popcll(pm & ((1ull << bi) - 1ull)) * (uint32_t)F.unit_words;
-                                atomicAdd(&smem[u + K.off_cnt + cell], wt);
+                                atomicAdd(&smem[u + K.off_cnt + cell], wf);
                                 if (F.n_vals) {
                                     double *vs = reinterpret_cast<double *>(smem + u + K.off_val) + (int64_t)cell * F.n_vals;
                                     for (int v = 0; v < F.n_vals; ++v) {
@@ -718,14 +789,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         // in fp64 (runs of one dimension key repeat a value thousands of
                         // times in a row, beyond what fp32 sums exactly)
                         if (T.lds_cnt >= 0) {
-                            atomicAdd(&smem[d.lds_tables + T.lds_cnt + cell], wt);
+                            atomicAdd(&smem[d.lds_tables + T.lds_cnt + cell], wf);
                             double *vs = reinterpret_cast<double *>(smem + d.lds_tables + T.lds_val) + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
                                 atomicAdd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                             }
                         } else {
-                            gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wt);
+                            gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wf);
                             double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
@@ -1213,6 +1284,14 @@ hipError_t launch_dup(const DupDesc *desc, int64_t n_rows, int64_t n_keys, hipSt
     const int64_t rb = (n_rows + kBlock - 1) / kBlock, kb = (n_keys + kBlock - 1) / kBlock;
     if (rb > 0) hipLaunchKernelGGL(dup_agg_kernel, dim3((unsigned)rb), dim3(kBlock), 0, st, desc);
     if (kb > 0) hipLaunchKernelGGL(dup_final_kernel, dim3((unsigned)kb), dim3(kBlock), 0, st, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_target(const TargetDesc *descs, int n_targets, int64_t max_items, hipStream_t st) {
+    const int64_t b = (max_items + kBlock - 1) / kBlock;
+    if (b > 0 && n_targets > 0)
+        hipLaunchKernelGGL(target_scan_kernel, dim3(b < 4096 ? (unsigned)b : 4096u, (unsigned)n_targets), dim3(kBlock), 0,
+                           st, descs);
     return hipGetLastError();
 }
 

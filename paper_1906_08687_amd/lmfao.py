@@ -25,6 +25,7 @@ OPS = {"le": 0, "lt": 1, "ge": 2, "gt": 3, "eq": 4, "ne": 5}
 PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x4": 2, "bf16x6": 3}
 SCHEDULE = {"plain": 0, "batched": 1}
 PLANNER = {"heuristic": 0, "autotune": 1, "learned": 2}
+ROOT = {"tree": 0, "find": 1}
 N_FEATURES = 16
 
 
@@ -66,7 +67,7 @@ class _PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("planner", ctypes.c_int32),
                 ("block_rows", ctypes.c_int32), ("grid_blocks", ctypes.c_int32), ("gram_block", ctypes.c_int32),
                 ("cost_model", ctypes.c_char_p), ("scan_every_table", ctypes.c_int32),
-                ("no_row_codes", ctypes.c_int32), ("no_hist", ctypes.c_int32)]
+                ("no_row_codes", ctypes.c_int32), ("no_hist", ctypes.c_int32), ("root_policy", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -78,12 +79,12 @@ class _Stats(ctypes.Structure):
                 ("waves", ctypes.c_int32), ("nbuf", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("dedicated_scan", ctypes.c_int32), ("derived_tables", ctypes.c_int32),
                 ("strided_families", ctypes.c_int32), ("code_scan", ctypes.c_int32),
-                ("hist_scan", ctypes.c_int32), ("hist_parts", ctypes.c_int32)]
+                ("hist_scan", ctypes.c_int32), ("hist_parts", ctypes.c_int32), ("target_queries", ctypes.c_int32)]
 
 
 # every symbol the header declares
 SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relation", "lmfao_set_join_tree",
-           "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_workspace_size", "lmfao_result_size",
+           "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_query_root", "lmfao_workspace_size", "lmfao_result_size",
            "lmfao_result_layout", "lmfao_bind", "lmfao_bind_scratch", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
            "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
@@ -113,6 +114,7 @@ def load(path: str = LIB_PATH):
         "lmfao_add_query": (st, [P, ctypes.POINTER(_Query), ctypes.POINTER(i32)]),
         "lmfao_plan": (st, [P, ctypes.POINTER(_PlanOpts)]),
         "lmfao_plan_stats": (st, [P, ctypes.POINTER(_Stats)]),
+        "lmfao_query_root": (st, [P, i32, ctypes.POINTER(i32)]),
         "lmfao_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "lmfao_result_size": (st, [P, ctypes.POINTER(sz)]),
         "lmfao_result_layout": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz),
@@ -250,8 +252,10 @@ class Context:
 
     # ---- planning --------------------------------------------------------------------
     def plan(self, precision="fp32", schedule="batched", planner="heuristic", grid_blocks=0, gram_block=0,
-             rollup=True, row_codes=True, hist=True):
-        """``rollup``: tables one group-by component short of another table with
+             rollup=True, row_codes=True, hist=True, root="tree"):
+        """``root``: "tree" evaluates every query at the join tree's root, "find"
+        assigns roots per query with the paper's heuristic (``root_policy``).
+        ``rollup``: tables one group-by component short of another table with
         the same filter are summed from it after the scan (``scan_every_table``
         = 0); False makes the scan update every table.  ``row_codes``: filtered
         tables over several LDS partitions are updated from per-row codes when
@@ -259,8 +263,14 @@ class Context:
         tables beyond the root scan's LDS are counted by the count-table scan
         from 16-bit component codes (``no_hist`` = 0)."""
         o = _PlanOpts(PRECISION[precision], SCHEDULE[schedule], PLANNER[planner], 0, grid_blocks, gram_block, None,
-                      0 if rollup else 1, 0 if row_codes else 1, 0 if hist else 1)
+                      0 if rollup else 1, 0 if row_codes else 1, 0 if hist else 1, ROOT[root])
         self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
+
+    def query_root(self, qid: int) -> int:
+        """Relation index at which query ``qid`` is evaluated."""
+        r = ctypes.c_int32()
+        self._check(self.lib.lmfao_query_root(self.ptr, qid, ctypes.byref(r)))
+        return r.value
 
     def stats(self) -> dict:
         s = _Stats()
@@ -350,7 +360,8 @@ class Engine:
     """
 
     def __init__(self, db, queries, precision="fp32", schedule="batched", planner="heuristic", device=0,
-                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True, scratch=False, hist=True):
+                 grid_blocks=0, gram_block=0, columns=None, rollup=True, row_codes=True, scratch=False, hist=True,
+                 root="tree"):
         import torch
         self.torch = torch
         self.db = db
@@ -370,8 +381,8 @@ class Engine:
         for q in self.queries:
             self.ctx.add_query(q)
         self.precision, self.schedule, self.rollup, self.row_codes = precision, schedule, rollup, row_codes
-        self.scratch, self.hist = scratch, hist
-        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes, hist)
+        self.scratch, self.hist, self.root = scratch, hist, root
+        self.ctx.plan(precision, schedule, planner, grid_blocks, gram_block, rollup, row_codes, hist, root)
         self._bind()
 
     def _bind(self):
@@ -397,7 +408,7 @@ class Engine:
         self.precision = precision or self.precision
         self.schedule = schedule or self.schedule
         self.ctx.plan(self.precision, self.schedule, planner, grid_blocks, gram_block, self.rollup, self.row_codes,
-                      self.hist)
+                      self.hist, self.root)
         self._bind()
 
     def run(self, stream=None):

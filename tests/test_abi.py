@@ -482,30 +482,69 @@ def test_polynomial_moments_are_planned_with_derived_products():
 def test_many_to_many_children_plan_as_count_weighted_views():
     """A child whose join key repeats (KEY_MANY) is planned as a
     count-weighted view: FP32 covariance, grouped sums keyed by other
-    relations and sums of its attributes plan; what the weighted view cannot
-    answer is refused at plan time with UNSUPPORTED: a BF16 covariance block,
-    a group-by or predicate on one of its attributes, a grouped sum of a
-    product of two of its attributes, a many-to-many relation below the root's
-    children, and a unique key declared on the parent side only."""
-    from datagen.configs import cont_attrs, covariance_queries, many_to_many_batch, many_to_many_database
+    relations and sums of its attributes plan at the tree root.  A query that
+    groups by, filters on or (grouped) multiplies attributes of the child is
+    evaluated at the child (its root, Section 3.3); one that does so for two
+    such children, and a BF16 covariance block with one, are UNSUPPORTED."""
     import numpy as np
+    from datagen.configs import cont_attrs, covariance_queries, many_to_many_batch, many_to_many_database
     from datagen.schema import Agg, GroupBy, Pred, Query
     db = many_to_many_database(n_fact=2000, n_users=50, n_business=40)
     qs = many_to_many_batch(db)
-    st = _plan_db(db, qs).stats()
-    assert st["launches"] >= 1
+    ctx = _plan_db(db, qs)
+    assert ctx.stats()["target_queries"] == 0
+    assert all(ctx.query_root(i) == 0 for i in range(len(qs)))
     for prec in ("bf16x3", "bf16x6"):
         with pytest.raises(lmfao.LmfaoError) as e:
             _plan_db(db, qs, precision=prec)
         assert e.value.code == "UNSUPPORTED"
     # tables only: any precision (tables are summed in fp64)
     _plan_db(db, qs[len(covariance_queries(cont_attrs(db))):], precision="bf16x6")
-    bad = [Query(groupby=[GroupBy("cw", np.array([0.0, 1.0], np.float32))]),
-           Query(where=[Pred("aw", "gt", 0.0)]),
-           Query(groupby=[GroupBy("bcat")], aggs=[Agg.monomial("cw", "cv")])]
-    for q in bad:
-        with pytest.raises(lmfao.LmfaoError) as e:
-            _plan_db(db, [q])
-        assert e.value.code == "UNSUPPORTED", q
-    # the product of two attributes of one many-to-many child is fine ungrouped (covariance block)
-    _plan_db(db, [Query(aggs=[Agg.monomial("cw", "cv")])])
+    cat, att = db.index("Category"), db.index("Attribute")
+    local = [(Query(groupby=[GroupBy("cw", np.array([0.0, 1.0], np.float32))]), cat),
+             (Query(where=[Pred("aw", "gt", 0.0)], aggs=[Agg.monomial("stars")]), att),
+             (Query(groupby=[GroupBy("bcat")], aggs=[Agg.monomial("cw", "cv")]), cat),
+             (Query(aggs=[Agg.monomial("cw", "cv", "stars")]), cat)]
+    ctx = _plan_db(db, [q for q, _ in local] + [Query(aggs=[Agg.monomial("cw", "cv")])])
+    assert [ctx.query_root(i) for i in range(len(local))] == [r for _, r in local]
+    assert ctx.query_root(len(local)) == 0          # ungrouped pair product: the covariance block
+    assert ctx.stats()["target_queries"] == len(local)
+    with pytest.raises(lmfao.LmfaoError) as e:
+        _plan_db(db, [Query(groupby=[GroupBy("cw", np.array([0.0], np.float32))], where=[Pred("aw", "gt", 0.0)])])
+    assert e.value.code == "UNSUPPORTED"
+
+
+def test_find_roots_assigns_grouped_queries_to_their_relations():
+    """The paper's root assignment (Section 3.3) on workload 2's snowflake:
+    the covariance block stays at the fact; a relation's weight is the sum
+    over grouped queries of the fraction of their group-by attributes it
+    holds; relations become roots in decreasing weight (ties to the larger),
+    each for the unassigned queries grouping by one of its attributes; S,
+    below D3, passes its queries to D3.  Under the tree policy every query
+    stays at the fact."""
+    from datagen import make_batch, make_database
+    db = make_database(2)
+    qs = make_batch(2, db)
+    tree = _plan_db(db, qs)
+    assert tree.stats()["target_queries"] == 0
+    ctx = _plan_db(db, qs, root="find")
+    idx = {r.name: i for i, r in enumerate(db.relations)}
+    owner = {c.attr: r.name for r in db.relations for c in r.columns if c.kind == "cat"}
+    roots = [ctx.query_root(i) for i in range(len(qs))]
+    # expected, from the definition: weights over grouped queries
+    W = {r.name: 0.0 for r in db.relations}
+    for q in qs:
+        if not q.groupby and not q.where:
+            continue
+        for g in q.groupby:
+            W[owner[g.attr]] += 1.0 / len(q.groupby)
+    order = sorted(W, key=lambda n: (-W[n], -db.rel(n).n_rows))
+    parent = {c: p for p, c in db.edges}
+    top = lambda n: n if parent.get(idx[n]) in (None, 0) else db.relations[parent[idx[n]]].name
+    for q, r in zip(qs, roots):
+        if not q.groupby and not q.where:
+            assert r == idx["F"]
+            continue
+        first = next(n for n in order if W[n] > 0 and any(owner[g.attr] == n for g in q.groupby))
+        assert r == idx[top(first)], (q, r, first)
+    assert ctx.stats()["target_queries"] == sum(1 for r in roots if r != idx["F"]) > 0

@@ -1,0 +1,81 @@
+"""Parity of queries evaluated at roots other than the join tree's root
+(Section 3.3 root assignment, Section 3.2 directional views).
+
+Under the paper's root assignment (``root="find"``) grouped queries move to
+the relation holding their group-by attributes: the root scan computes the
+view flowing towards that relation (a table keyed by its join key and the
+query's other group-by attributes) and the target scan joins it with the
+relation's keys.  On many-to-many stars, queries that group by, filter on or
+multiply attributes of a many-to-many child are evaluated at the child under
+either policy, scanning its rows.  Every aggregate is compared with the
+oracle: counts bit for bit, sums under tests/helpers.check_sums (1e-6 fp32,
+1e-5 bf16x6).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from datagen import Agg, GroupBy, Pred, Query, make_batch, make_database
+from datagen.configs import many_to_many_batch, many_to_many_database
+from tests.helpers import compare_results
+
+pytestmark = pytest.mark.gpu
+
+RTOL = {"fp32": 1e-6, "bf16x6": 1e-5}
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("schedule", ["batched", "plain"])
+def test_find_roots_parity(k, schedule):
+    from paper_1906_08687_amd.lmfao import Engine
+    if k == 3 and schedule == "plain":
+        pytest.skip("one launch per table: the tree level's 1,000 tables under both policies take minutes")
+    db = make_database(k)
+    qs = make_batch(k, db)
+    print("case: workload %d find-roots %s" % (k, schedule), flush=True)
+    ref = oracle.evaluate(db, qs)
+    precision = "bf16x6" if k in (1, 2) and schedule == "batched" else "fp32"
+    eng = Engine(db, qs, precision=precision, schedule=schedule, root="find")
+    assert eng.stats()["target_queries"] > 0
+    eng.run()
+    compare_results(eng.results(), ref, qs, RTOL[precision], "workload %d find-roots %s" % (k, schedule))
+    eng.run()
+    compare_results(eng.results(), ref, qs, RTOL[precision], "workload %d find-roots %s, second run" % (k, schedule))
+
+
+def _local_queries():
+    """Queries local to the many-to-many children (group-by, predicates,
+    grouped products, three-factor products), mixed with attributes of the
+    other relations."""
+    b3 = np.array([0.0, 1.5, 3.0], np.float32)
+    return [
+        Query(groupby=[GroupBy("cw", b3)], aggs=[Agg.monomial("stars"), Agg.monomial("cw"), Agg.monomial("u1", "cw")]),
+        Query(groupby=[GroupBy("bcat"), GroupBy("cv", np.array([0.0], np.float32))],
+              aggs=[Agg.monomial("cw", "cv"), Agg([(2.0, ("useful",)), (-1.0, ("cw", "b1"))])]),
+        Query(where=[Pred("aw", "gt", 0.0)], aggs=[Agg.monomial("stars"), Agg.monomial("aw", "aw"), Agg.monomial("cw")]),
+        Query(groupby=[GroupBy("ucat")], where=[Pred("cv", "le", 0.25), Pred("stars", "gt", 2.0)],
+              aggs=[Agg.monomial("cv", "stars"), Agg.monomial("aw")]),
+        Query(groupby=[GroupBy("rcat"), GroupBy("bcat"), GroupBy("ucat")], where=[Pred("aw", "ne", 0.5)]),
+        Query(aggs=[Agg.monomial("cw", "cv", "stars"), Agg.monomial("cw", "cw", "u1", "b1")]),
+        Query(groupby=[GroupBy("aw", np.array([-1.0, 1.0], np.float32))], where=[Pred("b1", "gt", 2.0)],
+              aggs=[Agg.monomial("aw", "cw")]),
+    ]
+
+
+@pytest.mark.parametrize("root", ["tree", "find"])
+@pytest.mark.parametrize("schedule", ["batched", "plain"])
+def test_many_to_many_queries_at_the_child(root, schedule):
+    from paper_1906_08687_amd.lmfao import Engine
+    db = many_to_many_database(n_fact=150_001, n_users=3_000, n_business=1_500, seed=21)
+    qs = many_to_many_batch(db) + _local_queries()
+    print("case: many-to-many local queries, root %s, %s" % (root, schedule), flush=True)
+    ref = oracle.evaluate(db, qs)
+    eng = Engine(db, qs, precision="fp32", schedule=schedule, root=root)
+    n = len(qs)
+    cat, att = db.index("Category"), db.index("Attribute")
+    roots = [eng.ctx.query_root(i) for i in range(n)]
+    assert roots[-7:] == [cat, cat, att, cat, att, cat, att]
+    eng.run()
+    compare_results(eng.results(), ref, qs, RTOL["fp32"], "many-to-many local, %s %s" % (root, schedule))
+    eng.run()
+    compare_results(eng.results(), ref, qs, RTOL["fp32"], "many-to-many local, %s %s, second run" % (root, schedule))

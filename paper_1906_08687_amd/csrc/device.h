@@ -75,15 +75,33 @@ __device__ __forceinline__ void lds_dma16(const void *g, uint32_t *lds_base) {
     __builtin_amdgcn_global_load_lds(g, (lds_void *)lds_base, 16, 0, 0);
 }
 
+// Residuals of the split: x - hi for a packed pair hi = (bf16(x0), bf16(x1)) as one
+// v_dot2c_f32_bf16 per value, hi . (-1, 0) + x0 and hi . (0, -1) + x1, instead of unpacking hi
+// to fp32 and subtracting (two instructions per value).  x - hi is exact in fp32, and the dot
+// product returns it bit for bit: checked on the device for every finite fp32 x below bf16's
+// overflow threshold (about 3.39e38, where hi becomes infinite in either form).  The two
+// selector constants live in registers, made opaque to the compiler, which would otherwise fold
+// them into an inline constant that the instruction reads as (0, -1) for both.
+struct SplitSel {
+    bf16x2 lo, hi;   // (-1, 0) and (0, -1)
+};
+__device__ __forceinline__ SplitSel split_sel() {
+    uint32_t a = 0x0000BF80u, b = 0xBF800000u;
+    asm("" : "+v"(a), "+v"(b));
+    return SplitSel{__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b)};
+}
+__device__ __forceinline__ f32x2 residual(const SplitSel &k, bf16x2 h, f32x2 v) {
+    return f32x2{__builtin_amdgcn_fdot2_f32_bf16(h, k.lo, v.x, false), __builtin_amdgcn_fdot2_f32_bf16(h, k.hi, v.y, false)};
+}
+
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), both round-to-nearest-even
-__device__ __forceinline__ void split_bf16x8(const float *x, bf16x8 &hi, bf16x8 &lo) {
+__device__ __forceinline__ void split_bf16x8(const SplitSel &k, const float *x, bf16x8 &hi, bf16x8 &lo) {
     uint32_t h[4], l[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const f32x2 v = {x[2 * i], x[2 * i + 1]};
         const bf16x2 hb = __builtin_convertvector(v, bf16x2);
-        const f32x2 hf = __builtin_convertvector(hb, f32x2);
-        const bf16x2 lb = __builtin_convertvector(v - hf, bf16x2);
+        const bf16x2 lb = __builtin_convertvector(residual(k, hb, v), bf16x2);
         h[i] = __builtin_bit_cast(uint32_t, hb);
         l[i] = __builtin_bit_cast(uint32_t, lb);
     }
@@ -94,16 +112,15 @@ __device__ __forceinline__ void split_bf16x8(const float *x, bf16x8 &hi, bf16x8 
 // x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), each round to
 // nearest even; x - hi and x - hi - mid are exact in fp32, and hi + mid + lo carries x to within
 // 2^-24 |x| (8 significant bits per piece)
-__device__ __forceinline__ void split3_bf16x8(const float *x, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo) {
+__device__ __forceinline__ void split3_bf16x8(const SplitSel &k, const float *x, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo) {
     uint32_t h[4], m[4], l[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const f32x2 v = {x[2 * i], x[2 * i + 1]};
         const bf16x2 hb = __builtin_convertvector(v, bf16x2);
-        const f32x2 r1 = v - __builtin_convertvector(hb, f32x2);
+        const f32x2 r1 = residual(k, hb, v);
         const bf16x2 mb = __builtin_convertvector(r1, bf16x2);
-        const f32x2 r2 = r1 - __builtin_convertvector(mb, f32x2);
-        const bf16x2 lb = __builtin_convertvector(r2, bf16x2);
+        const bf16x2 lb = __builtin_convertvector(residual(k, mb, r1), bf16x2);
         h[i] = __builtin_bit_cast(uint32_t, hb);
         m[i] = __builtin_bit_cast(uint32_t, mb);
         l[i] = __builtin_bit_cast(uint32_t, lb);

@@ -15,6 +15,12 @@ namespace lmfao {
 // covariance-only root scan (BF16 hi+lo split on matrix cores)
 // ---------------------------------------------------------------------------
 
+// Pair-row record buffers hold row r = 16b + 4g + i at position 16b + 4i + g (a transpose of
+// each 4 x 4 block of rows; the map is its own inverse).  The four lane groups g of an MFMA
+// operand read rows 4g + i together: at positions 4i + g they are 8 words apart instead of 32,
+// on different LDS banks.
+__device__ __forceinline__ int pair_row_of(int p) { return (p & ~15) | ((p & 3) << 2) | ((p >> 2) & 3); }
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
     // raw buffer: stride 0, range `bytes`; loads beyond the range return zeros
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
@@ -194,13 +200,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                 } else {
                     held_ok &= ~(1u << c);
                     if (PR) {
-                        // lane l of request i reads quad l % 2 of row 32 i + l / 2: a row's two
-                        // quads are one contiguous 32-byte piece on neighbouring lanes, so the
-                        // memory pipeline handles one address per row, not one per row and quad
+                        // lane l of request i reads quad l % 2 of the row kept at position
+                        // 32 i + l / 2 (pair_row_of): a row's two quads are one contiguous 32-byte
+                        // piece on neighbouring lanes, so the memory pipeline handles one address
+                        // per row, not one per row and quad
 #pragma unroll
                         for (int i = 0; i < 2; ++i) {
                             const uint32_t f = 64u * (uint32_t)i + (uint32_t)lane;
-                            const uint32_t kr = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(4u * (f >> 1)), (int)key[c]);
+                            const uint32_t kr = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(4u * pair_row_of(f >> 1)), (int)key[c]);
                             const uint32_t ko = (f & 1u) < (uint32_t)cnq[c] ? __umul24(min(kr, nkey[c]), rbytes[c]) + 16u * (f & 1u)
                                                                            : nkey[c] * rbytes[c];
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(rrs[c], (lds_void *)(dst + 1024 * i), 16, ko, 0, 0, 0);
@@ -260,12 +267,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     // registers, so the next copies can be issued before phase 2 (the MFMAs) runs.
     constexpr int NMID = PM == 6 ? NT : 1;
     bf16x8 oph[2][NT], opl[2][NT], opm[2][NMID];
+    const SplitSel sel = split_sel();
     auto phase1 = [&](int t) -> bool {
         const int r0 = tile_row(t);
         bool valid = r0 + lane < blk_end;
         uint32_t cnt[kGramMaxChild];
 #pragma unroll
-        for (int c = 0; c < kGramMaxChild; ++c) cnt[c] = c < n_child ? smem[cdst[c] / 4 + kRowWords * lane] : 1u;
+        for (int c = 0; c < kGramMaxChild; ++c)
+            cnt[c] = c < n_child ? smem[cdst[c] / 4 + kRowWords * (PR ? pair_row_of(lane) : lane)] : 1u;
 #pragma unroll
         for (int c = 0; c < kGramMaxChild; ++c)
             if (cnt[c] == 0u) valid = false;
@@ -291,7 +300,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     }
                 }
                 if (t2 >= NF || (t2 == NF - 1 && mixed)) {
-                    if (t2 >= NF || !is_fact[t2]) {
+                    if ((t2 >= NF || !is_fact[t2]) && PR) {
+                        // row 32ks + 4g + i sits at position 32ks + 4i + g (see pair_row_of)
+                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) + lds_off[t2]) +
+                                         8 * lg + 256 * ks;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            x[i] = p[32 * i];
+                            x[4 + i] = p[128 + 32 * i];
+                        }
+                    } else if (t2 >= NF || !is_fact[t2]) {
                         const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
                                                                          lds_off[t2] + 16 * kRowWords * lg + 128 * kRowWords * ks);
 #pragma unroll
@@ -306,8 +324,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
                     for (int i = 0; i < 8; ++i)
                         if (!((vbits >> i) & 1u)) x[i] = 0.f;
                 }
-                if (PM == 6) split3_bf16x8(x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
-                else split_bf16x8(x, oph[ks][t2], opl[ks][t2]);
+                if (PM == 6) split3_bf16x8(sel, x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
+                else split_bf16x8(sel, x, oph[ks][t2], opl[ks][t2]);
             }
         }
         return true;

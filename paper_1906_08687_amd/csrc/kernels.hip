@@ -455,6 +455,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     }
     int tiles_since_flush = 0;
     unsigned long long my_count = 0;
+    const SplitSel sel = split_sel();
 
     // ---- tile copies ------------------------------------------------------------------------
     int32_t fk[kMaxChild];
@@ -660,8 +661,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                         for (int i = 0; i < 8; ++i)
                             if (!((vbits >> i) & 1u)) x[i] = 0.f;
                     }
-                    if (MODE == 4) split3_bf16x8(x, fh[t2], fm[MODE == 4 ? t2 : 0], fl[t2]);
-                    else split_bf16x8(x, fh[t2], fl[t2]);
+                    if (MODE == 4) split3_bf16x8(sel, x, fh[t2], fm[MODE == 4 ? t2 : 0], fl[t2]);
+                    else split_bf16x8(sel, x, fh[t2], fl[t2]);
                 }
                 int ih = 0;
 #pragma unroll

@@ -95,6 +95,62 @@ def profiled_kernel(kernel_file: str, kernel: str):
     return {"traffic": rec["read_bytes"] + rec["write_bytes"], "kernel_ms": rec.get("kernel_trace_avg_ms")}
 
 
+def time_app(batch, eng, db, qs, stream, reps=5):
+    """Median host time of the application loop on the device over the engine's resident results
+    (through the binding: its argument marshalling and one synchronisation are included)."""
+    import torch
+    from datagen.configs import cat_attrs, cont_attrs, tree_level
+    from paper_1906_08687_amd import lmfao
+    if batch in ("w1", "w2"):
+        attrs = cont_attrs(db)
+        name = "ridge regression (batch gradient descent with Barzilai-Borwein steps, lambda 0.1) of %s on the " \
+               "other %d attributes, from the covariance block" % (attrs[0], len(attrs) - 1)
+
+        def run():
+            theta, info = lmfao.ridge_bgd(lmfao.covariance_matrix(eng, attrs), 1, 0.1, 5000, 1e-12)
+            return {"iterations": int(info[1]), "objective": float(info[0])}
+    elif batch == "w5":
+        cats = cat_attrs(db)
+        pairs = [i for i, q in enumerate(qs) if len(q.groupby) == 2]
+        name = "mutual information of the %d pair-count tables and the Chow-Liu tree over %d attributes" % (len(pairs), len(cats))
+
+        def run():
+            mi = lmfao.mutual_information(eng, pairs)
+            m = torch.zeros((len(cats), len(cats)), dtype=torch.float64, device=mi.device)
+            for k, i in enumerate(pairs):
+                a, b = cats.index(qs[i].groupby[0].attr), cats.index(qs[i].groupby[1].attr)
+                m[a, b] = m[b, a] = mi[k]
+            edges, total = lmfao.chow_liu(m)
+            return {"edges": len(edges), "total_mi": total}
+    elif batch in ("w3", "ctree"):
+        level = tree_level(db, seed=3)
+        crit = "variance" if batch == "w3" else "gini"
+        name = "best %s split of each of the %d nodes over every split attribute and threshold" % (crit, len(level.nodes))
+        # variance: every query of a node (COUNT, SUM(y), SUM(y^2) by attribute); gini: its
+        # label-split counts; queries are laid out node after node
+        qids = [i for i, q in enumerate(qs) if crit == "variance" or len(q.groupby) == 2]
+        per = len(qs) // len(level.nodes)
+        nodes = [i // per for i in qids]
+
+        def run():
+            res = lmfao.best_splits(eng, qids, nodes, crit, db.column("g3").domain if crit == "gini" else 0)
+            return {"nodes": len(res)}
+    else:
+        return None
+    info = run()
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t) * 1e3)
+    out = {"loop": name, "ms_median": float(np.median(times)), "reps": reps}
+    out.update(info)
+    print("[bench] application loop: %s: %.3f ms" % (name, out["ms_median"]), file=sys.stderr, flush=True)
+    return out
+
+
 def time_steps(eng, stream, steps, warmup, median=False):
     """Mean seconds per step over `steps` executions after `warmup` (host clock around all of
     them, synchronised on both sides); with `median`, also the median of per-step HIP-event
@@ -198,7 +254,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", default="covariance", choices=["covariance", "cube", "ctree", "w1", "w2", "w3", "w5"],
+    ap.add_argument("--batch", default="covariance", choices=["covariance", "cube", "ctree", "w1", "w2", "w3", "w5", "m2m"],
                     help="covariance: the 861-aggregate covariance batch (workload 4, the benchmark); cube: data "
                          "cube; ctree: classification-tree level; wK: workload K's batch at full size")
     ap.add_argument("--n-fact", type=int, default=None, help="fact rows (default: the batch's full size)")
@@ -219,6 +275,12 @@ def main():
                     help="full: skip the plain form (profiling runs)")
     ap.add_argument("--peaks", action="store_true", help="print the measured unit rates alone and exit")
     ap.add_argument("--no-ablation", action="store_true", help="skip the one-choice-at-a-time forms")
+    ap.add_argument("--root", default="tree", choices=["tree", "find"],
+                    help="root of each query in the full form: the join tree's root, or the paper's root assignment")
+    ap.add_argument("--app", action="store_true",
+                    help="also time the application loop on the device over the full form's results: ridge "
+                         "regression by gradient descent (w1, w2), mutual information and the Chow-Liu tree (w5), "
+                         "best regression-tree splits (w3) or classification-tree splits (ctree)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 2 GiB (a plain copy kernel of known size, "
                          "used to scale HBM byte counters)")
@@ -230,7 +292,8 @@ def main():
 
     import torch
     from datagen import make_batch, make_database
-    from datagen.configs import classification_tree_batch, data_cube_batch, tree_level
+    from datagen.configs import (classification_tree_batch, data_cube_batch, many_to_many_batch, many_to_many_database,
+                                 many_to_many_join_size, many_to_many_local_queries, tree_level)
     from paper_1906_08687_amd.lmfao import Engine, upload_columns
 
     if args.peaks:
@@ -256,6 +319,18 @@ def main():
         workload = ("data cube: 3 dimensions (c0 of the fact, c1 and c4 of two dimensions; 60/65/112 values "
                     "at this seed) x 5 measures, 8 group-bys, over workload 2's snowflake at 10M fact rows")
         cpu_rows = 10_000_000
+    elif args.batch == "m2m":
+        db = many_to_many_database(n_fact=args.n_fact or 6_000_000, n_users=1_300_000, n_business=170_000,
+                                   mean_cat=4, mean_attr=15)
+        qs = many_to_many_batch(db) + many_to_many_local_queries()
+        precision = "fp32"       # a covariance block over count-weighted views runs in FP32
+        metric = "join tuples aggregated/sec (many-to-many star, %s reviews)" % "{:,}".format(db.relations[0].n_rows)
+        workload = ("many-to-many star (Yelp-like): Review (Zipf(1.1) user and business keys) joined with User "
+                    "(1.3M) and Business (170k) on unique keys and with Category and Attribute on the repeated "
+                    "business key (0-8 and 0-30 rows per business); covariance of 8 attributes, grouped sums, and "
+                    "queries that group by, filter on or multiply the many-to-many attributes (evaluated at those "
+                    "relations)")
+        cpu_rows = 200_000
     elif args.batch in WORKLOADS:
         k = int(args.batch[1])
         db = make_database(k, "full", **over)
@@ -280,7 +355,7 @@ def main():
     cols = upload_columns(db, dev)
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
-    n_join = db.relations[0].n_rows
+    n_join = many_to_many_join_size(db) if args.batch == "m2m" else db.relations[0].n_rows
 
     if args.copy_calibration:
         src = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
@@ -319,7 +394,7 @@ def main():
     # full form: BF16 split on MFMA, batched in a hipGraph; tiles chosen by the cost model, its top
     # candidates judged by timing (every way of choosing is timed and reported; the one the
     # --plan option names runs last, so it is the plan the timed steps use)
-    full = Engine(db, qs, precision=precision, schedule="batched", columns=cols)
+    full = Engine(db, qs, precision=precision, schedule="batched", columns=cols, root=args.root)
     full.ctx.execute(stream)
     full.ctx.sync()
     plans = {}
@@ -374,6 +449,8 @@ def main():
     print("[bench] full %s/batched/%s: %.3f ms/step (median %.3f), root scan %.3f ms" %
           (precision, chosen, t_full * 1e3, t_full_median * 1e3, root_ms), file=sys.stderr, flush=True)
 
+    app = time_app(args.batch, full, db, qs, stream) if args.app else None
+
     # ablation: each of the three choices alone over the plain form (fp32, one launch per view,
     # heuristic tiles; the tables as the full form plans them)
     ablation = None
@@ -403,14 +480,21 @@ def main():
     cpu, errors = None, None
     if not args.no_cpu_baseline:
         import oracle
-        rows = min(n_join, cpu_rows)        # about 10 s of the oracle on 16 host threads
+        rows = min(db.relations[0].n_rows, cpu_rows)        # about 10 s of the oracle on 16 host threads
         threads = os.cpu_count() or 1
         t = time.time()
         oracle.evaluate(db, qs, n_threads=threads, root_range=(0, rows))
         dt = time.time() - t
-        cpu = {"value": rows / dt, "unit": "join tuples/s", "cores": threads, "kind": "oracle",
-               "sample": "first %d fact rows (of %d) joined with every dimension, all %d queries" %
-                         (rows, n_join, len(qs))}
+        tuples = rows
+        if args.batch == "m2m":   # the sample's join tuples: its reviews times their businesses' row counts
+            b = db.rel("Review").col("business").data[:rows]
+            nb = db.rel("Business").n_rows
+            c = np.bincount(db.rel("Category").col("business").data, minlength=nb).astype(np.int64)
+            a = np.bincount(db.rel("Attribute").col("business").data, minlength=nb).astype(np.int64)
+            tuples = int(np.sum(c[b] * a[b]))
+        cpu = {"value": tuples / dt, "unit": "join tuples/s", "cores": threads, "kind": "oracle",
+               "sample": "first %d fact rows (of %d; %d join tuples) joined with every other relation, all %d queries" %
+                         (rows, db.relations[0].n_rows, tuples, len(qs))}
         print("[bench] cpu oracle: %.3g tuples/s on %d threads" % (cpu["value"], threads), file=sys.stderr, flush=True)
         rng = np.random.default_rng(2024)
         sample = sorted(set([0] + [int(i) for i in rng.choice(np.arange(1, len(qs)), min(ERR_SAMPLE, len(qs) - 1),
@@ -463,8 +547,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ("%s-split/f32-acc/f64-merge" % precision) if precision != "fp32" else "f32/u64-counts/f64-merge",
-        "data": "synthetic (seeded; %s recipe)" % {"covariance": "workload 4", "cube": "workload 2",
-                                                    "ctree": "workload 3"}.get(args.batch, "workload " + args.batch[1:]),
+        "data": "synthetic (seeded; %s recipe)" % {"covariance": "workload 4", "cube": "workload 2", "ctree": "workload 3",
+                                                    "m2m": "many-to-many star"}.get(args.batch, "workload " + args.batch[1:]),
         "config": {"workload": workload,
                    "fact_rows": n_join, "aggregates": len(qs), "plan": chosen, "candidate": best,
                    "plan_choices": plans,
@@ -472,12 +556,14 @@ def main():
                    "waves_per_workgroup": stats["waves"], "staging_buffers": stats["nbuf"],
                    "lds_bytes": stats["lds_bytes"], "grouped_tables": stats["tables"],
                    "derived_tables": stats["derived_tables"], "count_table_scan": stats["hist_scan"],
+                   "root_policy": args.root, "queries_at_other_roots": stats["target_queries"],
                    "launches": stats["launches"]},
         "speedup_vs_plain_fp32": (t_plain / t_full) if t_plain else None,
         "plain_fp32": ({"ms_per_step": t_plain * 1e3, "value": n_join / t_plain, "root_scan_ms": plain_root_ms,
                         "launches": plain_stats["launches"]} if t_plain else None),
         "ablation": ablation,
         "errors_vs_oracle": errors,
+        "application_loop": app,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -484,6 +484,35 @@ def many_to_many_batch(db: Database) -> List[Query]:
     return qs
 
 
+def many_to_many_local_queries() -> List[Query]:
+    """Queries local to the many-to-many children of many_to_many_database: group-bys and
+    predicates on their attributes, grouped products of two of them, three- and four-factor
+    products, mixed with attributes of the other relations."""
+    b3 = np.array([0.0, 1.5, 3.0], np.float32)
+    return [
+        Query(groupby=[GroupBy("cw", b3)], aggs=[Agg.monomial("stars"), Agg.monomial("cw"), Agg.monomial("u1", "cw")]),
+        Query(groupby=[GroupBy("bcat"), GroupBy("cv", np.array([0.0], np.float32))],
+              aggs=[Agg.monomial("cw", "cv"), Agg([(2.0, ("useful",)), (-1.0, ("cw", "b1"))])]),
+        Query(where=[Pred("aw", "gt", 0.0)], aggs=[Agg.monomial("stars"), Agg.monomial("aw", "aw"), Agg.monomial("cw")]),
+        Query(groupby=[GroupBy("ucat")], where=[Pred("cv", "le", 0.25), Pred("stars", "gt", 2.0)],
+              aggs=[Agg.monomial("cv", "stars"), Agg.monomial("aw")]),
+        Query(groupby=[GroupBy("rcat"), GroupBy("ucat")], where=[Pred("aw", "ne", 0.5)]),
+        Query(aggs=[Agg.monomial("cw", "cv", "stars"), Agg.monomial("cw", "cw", "u1", "b1")]),
+        Query(groupby=[GroupBy("aw", np.array([-1.0, 1.0], np.float32))], where=[Pred("b1", "gt", 2.0)],
+              aggs=[Agg.monomial("aw", "cw")]),
+    ]
+
+
+def many_to_many_join_size(db: Database) -> int:
+    """|J| of many_to_many_database: per review, the product of its business's category and
+    attribute rows (users and businesses are unique keys covering every foreign key)."""
+    b = db.rel("Review").col("business").data
+    n = db.rel("Business").n_rows
+    c = np.bincount(db.rel("Category").col("business").data, minlength=n).astype(np.int64)
+    a = np.bincount(db.rel("Attribute").col("business").data, minlength=n).astype(np.int64)
+    return int(np.sum(c[b] * a[b]))
+
+
 def make_database(k: int, size: str = "small", **override) -> Database:
     params = dict((FULL if size == "full" else SMALL)[k])
     params.update(override)

@@ -150,6 +150,8 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
     int32_t code_base;    // per-row codes: column of this family's first key
     int32_t wdiv;         // weighted plans: root child whose record count divides the row weight
                           // (views towards a many-to-many child), -1 none
+    int32_t has_global;   // some table of the family is in global memory (non-strided families)
+    int32_t pad_g;
 };
 
 constexpr int kColPitch = 68;     // words per 64-row LDS column (64 rows + 4 words of bank padding)
@@ -227,7 +229,8 @@ struct RootDesc {
     int32_t weighted;
     int32_t w_wgt;                     // wave-relative: one LDS column of row weights (fp32)
     uint32_t max_weight;               // larger weights raise kErrWeight (u32 LDS counts, fp32)
-    int32_t pad_w;
+    int32_t global_fams;               // non-strided families with tables in global memory: their global
+                                       // tables are updated in a convergent pass (see the root scan)
 };
 
 // ---- many-to-many child views ------------------------------------------------------
@@ -271,6 +274,7 @@ struct TargetSrc {        // one group-by position of the query, in query order
 
 constexpr int kMaxTermFactors = 4;
 constexpr int kMaxTargetTerms = 16;   // terms of a query evaluated at another root
+constexpr int kTargetLdsCells = 3072; // result words (8 bytes) a target scan workgroup keeps in LDS
 
 struct TargetTerm {
     int32_t agg;
@@ -300,7 +304,9 @@ struct TargetDesc {
     int32_t o_dom[kMaxKeyComps];     // their domains, in key order
     int32_t n_vals;                  // sums per view cell
     int32_t n_keys;                  // key domain of R
-    int32_t pad;
+    int32_t lds;                     // 1: the result (cells x (count + aggregates) <= kTargetLdsCells) is
+                                     // accumulated per workgroup in LDS and added to global memory once
+    int64_t n_cells;                 // cells of the query's result
     const unsigned long long *vcnt;  // the view: counts [n_keys * n_ocells]
     const double *vval;              // sums [n_keys * n_ocells][n_vals]
     unsigned long long *res_cnt;     // the query's result cells

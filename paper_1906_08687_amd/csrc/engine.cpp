@@ -2122,6 +2122,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                 td.part = 0;
                 td.lds_cnt = T.lds_cnt >= 0 ? 0 : -1;
                 td.lds_val = T.lds_cnt >= 0 ? T.val_off() : -1;
+                fd.has_global = T.lds_cnt < 0 ? 1 : 0;
                 td.glb_cnt = T.glb_cnt;
                 td.glb_val = T.glb_val;
                 tdesc.push_back(td);
@@ -2144,6 +2145,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                     td.glb_cnt = T.glb_cnt;
                     td.glb_val = T.glb_val;
                     tdesc.push_back(td);
+                    if (T.lds_cnt < 0) fd.has_global = 1;
                     if (T.filter >= 0) fd.part_mask[T.part] |= 1ull << T.filter;
                     if (T.lds_cnt >= 0) {
                         flushes[T.part].push_back(FlushDesc{T.lds_cnt, T.lds_val, (int)T.n_cells, (int)T.vals.size(), T.glb_cnt, T.glb_val});
@@ -2160,6 +2162,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                 }
             }
             fdesc.push_back(fd);
+            if (fd.has_global && !fd.strided) ++D.global_fams;
         }
         for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, pw[p]);
         std::vector<FlushDesc> fl;
@@ -2457,6 +2460,8 @@ static lmfao_status build_blob(lmfao_ctx *c) {
         td.n_vals = (int)V.vals.size();
         td.vcnt = gcnt + V.glb_cnt;
         td.vval = gval + V.glb_val;
+        td.n_cells = O.n_cells;
+        td.lds = O.n_cells * (1 + (int64_t)O.n_aggs) <= kTargetLdsCells ? 1 : 0;
         td.res_cnt = reinterpret_cast<unsigned long long *>(c->res + O.cnt_off);
         td.res_sum = reinterpret_cast<double *>(c->res + O.sum_off);
         td.err = err;

@@ -263,6 +263,18 @@ __global__ __launch_bounds__(kBlock) void target_scan_kernel(const TargetDesc *_
     const AS_CONST TargetDesc &d = cst(dp)[blockIdx.y];   // one query per grid row
     const AS_CONST TargetSrc *gb = cst(d.gb);
     const AS_CONST TargetTerm *terms = cst(d.terms);
+    // small results (a few query cells hit by every item) are summed per workgroup in LDS first:
+    // global atomics on a handful of addresses would serialise
+    __shared__ unsigned long long lcnt_words[kTargetLdsCells];
+    unsigned long long *lcnt = lcnt_words;
+    double *lsum = reinterpret_cast<double *>(lcnt_words);   // after the counts
+    const int64_t n_res = d.lds ? d.n_cells : 0;
+    if (d.lds) {
+        for (int i = threadIdx.x; i < kTargetLdsCells; i += kBlock) lcnt_words[i] = 0ull;
+        __syncthreads();
+    }
+    unsigned long long *rcnt = d.lds ? lcnt : d.res_cnt;
+    double *rsum = d.lds ? lsum + n_res : d.res_sum;
     for (int64_t item = blockIdx.x * (int64_t)kBlock + threadIdx.x; item < d.n_items;
          item += (int64_t)gridDim.x * kBlock) {
         int64_t k;
@@ -307,8 +319,9 @@ __global__ __launch_bounds__(kBlock) void target_scan_kernel(const TargetDesc *_
             }
             for (int i = 0; i < d.n_gb; ++i)
                 if (gb[i].from_o >= 0) cell += (int64_t)digit[gb[i].from_o] * gb[i].stride;
-            gadd(d.res_cnt + cell, cnt);
             const double *vv = d.vval + (v0 + o) * d.n_vals;
+            if (d.lds) atomicAdd(rcnt + cell, cnt);
+            else gadd(rcnt + cell, cnt);
             for (int a = 0; a < d.n_aggs; ++a) {
                 double s = 0.0;
                 for (int t = 0; t < d.n_terms && t < kMaxTargetTerms; ++t) {
@@ -316,8 +329,19 @@ __global__ __launch_bounds__(kBlock) void target_scan_kernel(const TargetDesc *_
                     const int vi = terms[t].val;
                     s += rf[t] * (vi < 0 ? (double)cnt : gld(vv)[vi]);
                 }
-                if (s != 0.0) gadd(d.res_sum + cell * d.n_aggs + a, s);
+                if (s == 0.0) continue;
+                if (d.lds) atomicAdd(rsum + cell * d.n_aggs + a, s);
+                else gadd(rsum + cell * d.n_aggs + a, s);
             }
+        }
+    }
+    if (d.lds) {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n_res; i += kBlock) {
+            if (lcnt[i] == 0ull) continue;
+            gadd(d.res_cnt + i, lcnt[i]);
+            for (int a = 0; a < d.n_aggs; ++a)
+                if (rsum[i * d.n_aggs + a] != 0.0) gadd(d.res_sum + i * d.n_aggs + a, rsum[i * d.n_aggs + a]);
         }
     }
 }
@@ -552,14 +576,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             if (valid && w64 > d.max_weight) gor(d.err, kErrWeight);
             wt = valid ? (uint32_t)min(w64, (unsigned long long)d.max_weight) : 0u;
             if (MODE == 1 && do_gram) W[d.w_wgt + lane] = __float_as_uint((float)wt);
-            if (do_gram && valid) {
-                // per key of a many-to-many child: the tuples reaching it over its own count
+            if (do_gram) {
+                // per key of a many-to-many child: the tuples reaching it over its own count.  The
+                // fact is sorted by its keys, so a tile's valid rows mostly share one key: then the
+                // wave adds once (a wave's 64 atomics on one address would serialise)
 #pragma unroll
                 for (int c = 0; c < kMaxChild; ++c) {
                     if (c < s.n_child && children[c].hw) {
                         const uint32_t n = rb[(children[c].quad_base * 64 + lane) * 4];
-                        const int32_t k = gld(children[c].fk)[row];
-                        gadd(children[c].hw + k, (double)wt / (double)n);
+                        const int32_t k = gld(children[c].fk)[min(row, last_row)];
+                        const double h = valid ? (double)wt / (double)n : 0.0;
+                        const uint64_t vb = __ballot(valid);
+                        if (vb == 0ull) continue;
+                        const int32_t k0 = __builtin_amdgcn_readlane(k, __ffsll((long long)vb) - 1);
+                        if (__ballot(valid && k != k0) == 0ull) {
+                            const double tot = wave_sum_f64(h);
+                            if (lane == 0) gadd(children[c].hw + k0, tot);
+                        } else if (valid) {
+                            gadd(children[c].hw + k, h);
+                        }
                     }
                 }
             }
@@ -704,6 +739,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 gst(hc)[(int64_t)j * d.hcode_pitch] = (uint16_t)v;
             }
         }
+        if (TABLES && !d.codes && d.global_fams > 0) {
+            // global tables, in code every lane runs: on the sorted fact the rows of a wave often
+            // update one cell (a table keyed by the key a run shares), and then the wave sums its
+            // rows and adds once instead of 64 atomics on one address, which serialise
+            const uint32_t *cr = W + d.w_comp + lane;
+            auto fval = [&](int f) -> double {
+                const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
+                return (double)fsm[L.base + buf * L.step + lane * L.stride];
+            };
+            for (int fi = 0; fi < d.n_fam; ++fi) {
+                const AS_CONST FamilyDesc &F = fams[fi];
+                if (F.strided || !F.has_global) continue;
+                uint32_t wf = 0u;
+                if (valid) wf = F.wdiv >= 0 ? wt / rb[(children[F.wdiv].quad_base * 64 + lane) * 4] : wt;
+                const double wd = (double)wf;
+                for (int j = 0; j < F.n_filt; ++j) {
+                    const bool on = valid && (F.unfiltered || ((mask >> cst(d.filt_bits)[F.filt_base + j]) & 1ull));
+                    const uint64_t ob = __ballot(on);
+                    if (ob == 0ull) continue;
+                    for (int k = 0; k < F.n_keys; ++k) {
+                        const AS_GLOBAL TabDesc &T = gld(d.tabs)[F.tab_base + j * F.n_keys + k];
+                        if (T.part != part || T.lds_cnt >= 0) continue;
+                        const AS_CONST KeyDesc &K = keys[F.key_base + k];
+                        int32_t cell = 0;
+                        for (int c = 0; c < K.n_comp; ++c) cell += (int32_t)cr[K.c[c] * 64] * K.s[c];
+                        const int32_t c0 = __builtin_amdgcn_readlane(cell, __ffsll((long long)ob) - 1);
+                        if (__ballot(on && cell != c0) == 0ull) {
+                            const unsigned long long tc = wave_sum_u64(on ? (unsigned long long)wf : 0ull);
+                            if (lane == 0) gadd(d.g_cnt + T.glb_cnt + c0, tc);
+                            double *vs = d.g_val + T.glb_val + (int64_t)c0 * F.n_vals;
+                            for (int v = 0; v < F.n_vals; ++v) {
+                                const AS_CONST ValDesc &vd = vals[F.val_base + v];
+                                const double tv = wave_sum_f64(on ? fval(vd.a) * fval(vd.b) * wd : 0.0);
+                                if (lane == 0) gadd(vs + v, tv);
+                            }
+                        } else if (on) {
+                            gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wf);
+                            double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
+                            for (int v = 0; v < F.n_vals; ++v) {
+                                const AS_CONST ValDesc &vd = vals[F.val_base + v];
+                                gadd(vs + v, fval(vd.a) * fval(vd.b) * wd);
+                            }
+                        }
+                    }
+                }
+            }
+        }
         if (TABLES && d.codes) {
             // per-row codes for the partitioned table scan; rows past the range write nothing
             if (row < w_end) {
@@ -796,7 +878,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
                                 atomicAdd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                             }
-                        } else {
+                        } else if (d.global_fams == 0) {   // otherwise done by the convergent pass
                             gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wf);
                             double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {
@@ -1291,7 +1373,7 @@ hipError_t launch_dup(const DupDesc *desc, int64_t n_rows, int64_t n_keys, hipSt
 hipError_t launch_target(const TargetDesc *descs, int n_targets, int64_t max_items, hipStream_t st) {
     const int64_t b = (max_items + kBlock - 1) / kBlock;
     if (b > 0 && n_targets > 0)
-        hipLaunchKernelGGL(target_scan_kernel, dim3(b < 4096 ? (unsigned)b : 4096u, (unsigned)n_targets), dim3(kBlock), 0,
+        hipLaunchKernelGGL(target_scan_kernel, dim3(b < 1024 ? (unsigned)b : 1024u, (unsigned)n_targets), dim3(kBlock), 0,
                            st, descs);
     return hipGetLastError();
 }

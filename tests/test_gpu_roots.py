@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from datagen import Agg, GroupBy, Pred, Query, make_batch, make_database
-from datagen.configs import many_to_many_batch, many_to_many_database
+from datagen.configs import many_to_many_batch, many_to_many_database, many_to_many_local_queries
 from tests.helpers import compare_results
 
 pytestmark = pytest.mark.gpu
@@ -43,31 +43,12 @@ def test_find_roots_parity(k, schedule):
     compare_results(eng.results(), ref, qs, RTOL[precision], "workload %d find-roots %s, second run" % (k, schedule))
 
 
-def _local_queries():
-    """Queries local to the many-to-many children (group-by, predicates,
-    grouped products, three-factor products), mixed with attributes of the
-    other relations."""
-    b3 = np.array([0.0, 1.5, 3.0], np.float32)
-    return [
-        Query(groupby=[GroupBy("cw", b3)], aggs=[Agg.monomial("stars"), Agg.monomial("cw"), Agg.monomial("u1", "cw")]),
-        Query(groupby=[GroupBy("bcat"), GroupBy("cv", np.array([0.0], np.float32))],
-              aggs=[Agg.monomial("cw", "cv"), Agg([(2.0, ("useful",)), (-1.0, ("cw", "b1"))])]),
-        Query(where=[Pred("aw", "gt", 0.0)], aggs=[Agg.monomial("stars"), Agg.monomial("aw", "aw"), Agg.monomial("cw")]),
-        Query(groupby=[GroupBy("ucat")], where=[Pred("cv", "le", 0.25), Pred("stars", "gt", 2.0)],
-              aggs=[Agg.monomial("cv", "stars"), Agg.monomial("aw")]),
-        Query(groupby=[GroupBy("rcat"), GroupBy("bcat"), GroupBy("ucat")], where=[Pred("aw", "ne", 0.5)]),
-        Query(aggs=[Agg.monomial("cw", "cv", "stars"), Agg.monomial("cw", "cw", "u1", "b1")]),
-        Query(groupby=[GroupBy("aw", np.array([-1.0, 1.0], np.float32))], where=[Pred("b1", "gt", 2.0)],
-              aggs=[Agg.monomial("aw", "cw")]),
-    ]
-
-
 @pytest.mark.parametrize("root", ["tree", "find"])
 @pytest.mark.parametrize("schedule", ["batched", "plain"])
 def test_many_to_many_queries_at_the_child(root, schedule):
     from paper_1906_08687_amd.lmfao import Engine
     db = many_to_many_database(n_fact=150_001, n_users=3_000, n_business=1_500, seed=21)
-    qs = many_to_many_batch(db) + _local_queries()
+    qs = many_to_many_batch(db) + many_to_many_local_queries()
     print("case: many-to-many local queries, root %s, %s" % (root, schedule), flush=True)
     ref = oracle.evaluate(db, qs)
     eng = Engine(db, qs, precision="fp32", schedule=schedule, root=root)

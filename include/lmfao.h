@@ -288,6 +288,18 @@ lmfao_status lmfao_plan_stats(const lmfao_ctx *ctx, lmfao_stats *stats);
  * lmfao_plan.  Errors: STATE before planning, INVALID_ARG for a bad qid. */
 lmfao_status lmfao_query_root(const lmfao_ctx *ctx, int32_t qid, int32_t *rel);
 
+/* Root assignment chosen by measurement (Section 3.3): plans the batch with
+ * every query at the join tree's root and with the paper's root assignment
+ * (LMFAO_ROOT_TREE, LMFAO_ROOT_FIND of lmfao_plan_opts.root_policy), each with
+ * the heuristic tile configuration, times `reps` whole executions of each on
+ * `hip_stream` (a plan that needs more workspace or result memory than is
+ * bound, or that puts no query elsewhere, is not timed), keeps the faster,
+ * executes it once and stores its policy in *policy.  When the kept plan
+ * needs more memory than is bound, the context is left planned and unbound:
+ * query the sizes and bind again.  Errors: INVALID_ARG for reps below 1;
+ * STATE before lmfao_bind. */
+lmfao_status lmfao_choose_root(lmfao_ctx *ctx, void *hip_stream, int32_t reps, int32_t *policy);
+
 /* ---- memory -------------------------------------------------------------- */
 
 /* Device scratch the plan needs (views, partials, tables, descriptors). */

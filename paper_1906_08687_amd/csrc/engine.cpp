@@ -2896,6 +2896,56 @@ extern "C" lmfao_status lmfao_time_root_group(lmfao_ctx *c, void *hip_stream, in
     return LMFAO_OK;
 }
 
+static lmfao_status select_cfg(lmfao_ctx *c, const TileCfg &t);
+
+// The root of each query chosen by measurement: the plan with every query at the tree root and
+// the plan of the paper's root assignment, each with the heuristic configuration, are timed
+// whole (every launch of an execution) and the faster is kept.
+extern "C" lmfao_status lmfao_choose_root(lmfao_ctx *c, void *hip_stream, int32_t reps, int32_t *policy) {
+    if (!c || reps <= 0) return LMFAO_ERR_INVALID_ARG;
+    if (!c->bound) return fail(c, LMFAO_ERR_STATE, "bind buffers before choosing");
+    if (check_scratch_owner(c) != LMFAO_OK) return LMFAO_ERR_STATE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    TileCfg heur;
+    heur.grid_x = c->opts.grid_blocks;
+    heur.gram_block = c->opts.gram_block;
+    heur.lds_policy = -1;
+    double best_ms = 1e300;
+    int best = c->opts.root_policy;
+    for (int pol : {LMFAO_ROOT_TREE, LMFAO_ROOT_FIND}) {
+        c->opts.root_policy = pol;
+        lmfao_status s = select_cfg(c, heur);
+        if (s != LMFAO_OK || !c->bound) continue;             // does not fit the bound buffers
+        if (pol == LMFAO_ROOT_FIND && c->plan.targets.empty()) continue;   // the same plan as the tree root's
+        s = enqueue_all(c, st);
+        if (s != LMFAO_OK) continue;
+        hipEvent_t a, b;
+        HIP_TRY(c, hipEventCreate(&a));
+        HIP_TRY(c, hipEventCreate(&b));
+        HIP_TRY(c, hipEventRecord(a, st));
+        for (int i = 0; i < reps && s == LMFAO_OK; ++i) s = enqueue_all(c, st);
+        HIP_TRY(c, hipEventRecord(b, st));
+        HIP_TRY(c, hipEventSynchronize(b));
+        float t = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&t, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (s == LMFAO_OK && (double)t / reps < best_ms) {
+            best_ms = (double)t / reps;
+            best = pol;
+        }
+    }
+    c->opts.root_policy = best;
+    lmfao_status s = select_cfg(c, heur);
+    if (s != LMFAO_OK) return s;
+    if (policy) *policy = best;
+    if (!c->bound) return LMFAO_OK;   // the chosen plan needs more memory than is bound: bind again
+    s = lmfao_execute(c, hip_stream);
+    if (s == LMFAO_OK) s = lmfao_sync(c);
+    return s;
+}
+
 // ============================================================================
 // candidates, autotuner, learned choice
 // ============================================================================

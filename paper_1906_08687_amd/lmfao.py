@@ -84,7 +84,7 @@ class _Stats(ctypes.Structure):
 
 # every symbol the header declares
 SYMBOLS = ["lmfao_create", "lmfao_destroy", "lmfao_last_error", "lmfao_add_relation", "lmfao_set_join_tree",
-           "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_query_root", "lmfao_workspace_size", "lmfao_result_size",
+           "lmfao_add_query", "lmfao_plan", "lmfao_plan_stats", "lmfao_query_root", "lmfao_choose_root", "lmfao_workspace_size", "lmfao_result_size",
            "lmfao_result_layout", "lmfao_bind", "lmfao_bind_scratch", "lmfao_execute", "lmfao_sync", "lmfao_time_root_group",
            "lmfao_candidates", "lmfao_candidate", "lmfao_candidate_features", "lmfao_select_candidate",
            "lmfao_autotune", "lmfao_choose_learned", "lmfao_choose_learned_verified", "lmfao_mlp_param_count", "lmfao_mlp_forward",
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "lmfao_plan": (st, [P, ctypes.POINTER(_PlanOpts)]),
         "lmfao_plan_stats": (st, [P, ctypes.POINTER(_Stats)]),
         "lmfao_query_root": (st, [P, i32, ctypes.POINTER(i32)]),
+        "lmfao_choose_root": (st, [P, P, i32, ctypes.POINTER(i32)]),
         "lmfao_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "lmfao_result_size": (st, [P, ctypes.POINTER(sz)]),
         "lmfao_result_layout": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(sz),
@@ -266,6 +267,12 @@ class Context:
                       0 if rollup else 1, 0 if row_codes else 1, 0 if hist else 1, ROOT[root])
         self._check(self.lib.lmfao_plan(self.ptr, ctypes.byref(o)))
 
+    def choose_root(self, stream=None, reps: int = 3) -> str:
+        """Time the tree-root plan and the paper's root assignment, keep the faster ("tree" or "find")."""
+        r = ctypes.c_int32()
+        self._check(self.lib.lmfao_choose_root(self.ptr, _stream_handle(stream), reps, ctypes.byref(r)))
+        return {v: k for k, v in ROOT.items()}[r.value]
+
     def query_root(self, qid: int) -> int:
         """Relation index at which query ``qid`` is evaluated."""
         r = ctypes.c_int32()
@@ -403,6 +410,14 @@ class Engine:
         base = _ptr(self.ws)
         self.ws_base = (base + 255) // 256 * 256
         self.ctx.bind(self.ws_base, self.ws.numel() - (self.ws_base - base), _ptr(self.res), self.res.numel())
+
+    def choose_root(self, stream=None, reps: int = 3) -> str:
+        """Keep the faster of the tree-root plan and the paper's root assignment (timed whole);
+        returns "tree" or "find"."""
+        self.root = self.ctx.choose_root(stream, reps)
+        self._bind()
+        self.run(stream)
+        return self.root
 
     def replan(self, precision=None, schedule=None, planner="heuristic", grid_blocks=0, gram_block=0):
         self.precision = precision or self.precision

@@ -182,12 +182,13 @@ def test_bind_and_execute_need_a_device_and_a_plan():
     assert e.value.code == "HIP"                     # no device
     for call in (lambda: ctx.execute(None), lambda: ctx.sync(), lambda: ctx.time_root_group(None, 1, 1),
                  lambda: ctx.autotune(None, None, 1), lambda: ctx.choose_learned("w.bin", None),
-                 lambda: ctx.choose_learned_verified("w.bin", None, 3, 1)):
+                 lambda: ctx.choose_learned_verified("w.bin", None, 3, 1), lambda: ctx.choose_root(None, 1)):
         with pytest.raises(lmfao.LmfaoError) as e:
             call()
         assert e.value.code == "STATE"
     for k, reps in ((0, 1), (3, 0)):
         expect("INVALID_ARG", lambda: ctx.choose_learned_verified("w.bin", None, k, reps))
+    expect("INVALID_ARG", lambda: ctx.choose_root(None, 0))
 
 
 # --------------------------------------------------------------------------

@@ -60,3 +60,28 @@ def test_many_to_many_queries_at_the_child(root, schedule):
     compare_results(eng.results(), ref, qs, RTOL["fp32"], "many-to-many local, %s %s" % (root, schedule))
     eng.run()
     compare_results(eng.results(), ref, qs, RTOL["fp32"], "many-to-many local, %s %s, second run" % (root, schedule))
+
+
+@pytest.mark.parametrize("case", ["w2", "m2m"])
+def test_measured_root_choice_keeps_parity(case):
+    """lmfao_choose_root times the tree-root plan and the paper's root assignment whole and keeps
+    the faster: the kept plan's results match the oracle, and its queries sit at the roots the
+    chosen policy assigns."""
+    import torch
+    from paper_1906_08687_amd.lmfao import Engine
+    if case == "w2":
+        db = make_database(2)
+        qs = make_batch(2, db)
+    else:
+        db = many_to_many_database(n_fact=100_003, n_users=2_000, n_business=1_000, seed=22)
+        qs = many_to_many_batch(db) + many_to_many_local_queries()
+    print("case: measured root choice, %s" % case, flush=True)
+    ref = oracle.evaluate(db, qs)
+    stream = torch.cuda.Stream()
+    eng = Engine(db, qs, precision="fp32")
+    eng.run(stream)
+    pol = eng.choose_root(stream, 3)
+    assert pol in ("tree", "find")
+    other = Engine(db, qs, precision="fp32", root=pol)
+    assert [eng.ctx.query_root(i) for i in range(len(qs))] == [other.ctx.query_root(i) for i in range(len(qs))]
+    compare_results(eng.results(), ref, qs, RTOL["fp32"], "measured root choice %s (%s)" % (case, pol))

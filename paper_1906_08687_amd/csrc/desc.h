@@ -150,7 +150,8 @@ struct FamilyDesc {       // tables sharing one list of summed monomials
     int32_t code_base;    // per-row codes: column of this family's first key
     int32_t wdiv;         // weighted plans: root child whose record count divides the row weight
                           // (views towards a many-to-many child), -1 none
-    int32_t has_global;   // some table of the family is in global memory (non-strided families)
+    int32_t conv;         // updated by the root scan's convergent pass (a non-strided family with
+                          // tables in global memory)
     int32_t pad_g;
 };
 
@@ -229,8 +230,7 @@ struct RootDesc {
     int32_t weighted;
     int32_t w_wgt;                     // wave-relative: one LDS column of row weights (fp32)
     uint32_t max_weight;               // larger weights raise kErrWeight (u32 LDS counts, fp32)
-    int32_t global_fams;               // non-strided families with tables in global memory: their global
-                                       // tables are updated in a convergent pass (see the root scan)
+    int32_t conv_fams;                 // families updated by the convergent pass (see the root scan)
 };
 
 // ---- many-to-many child views ------------------------------------------------------

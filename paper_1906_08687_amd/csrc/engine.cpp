@@ -2122,7 +2122,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                 td.part = 0;
                 td.lds_cnt = T.lds_cnt >= 0 ? 0 : -1;
                 td.lds_val = T.lds_cnt >= 0 ? T.val_off() : -1;
-                fd.has_global = T.lds_cnt < 0 ? 1 : 0;
+                fd.conv = T.lds_cnt < 0 ? 1 : 0;   // a table in global memory
                 td.glb_cnt = T.glb_cnt;
                 td.glb_val = T.glb_val;
                 tdesc.push_back(td);
@@ -2145,7 +2145,7 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                     td.glb_cnt = T.glb_cnt;
                     td.glb_val = T.glb_val;
                     tdesc.push_back(td);
-                    if (T.lds_cnt < 0) fd.has_global = 1;
+                    if (T.lds_cnt < 0) fd.conv = 1;
                     if (T.filter >= 0) fd.part_mask[T.part] |= 1ull << T.filter;
                     if (T.lds_cnt >= 0) {
                         flushes[T.part].push_back(FlushDesc{T.lds_cnt, T.lds_val, (int)T.n_cells, (int)T.vals.size(), T.glb_cnt, T.glb_val});
@@ -2161,8 +2161,13 @@ static lmfao_status build_blob(lmfao_ctx *c) {
                     }
                 }
             }
+            // the convergent pass takes families with global tables: one atomic per wave on the
+            // sorted fact's shared cells (a wave's 64 global atomics on one address serialise);
+            // for LDS tables the wave sums cost more than the atomics they save (workload 2:
+            // 10.9 -> 14.4 ms when unfiltered LDS families went through it too)
+            if (fd.strided) fd.conv = 0;
+            if (fd.conv) ++D.conv_fams;
             fdesc.push_back(fd);
-            if (fd.has_global && !fd.strided) ++D.global_fams;
         }
         for (int p = 0; p < kMaxParts; ++p) max_words = std::max(max_words, pw[p]);
         std::vector<FlushDesc> fl;

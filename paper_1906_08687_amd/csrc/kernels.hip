@@ -739,10 +739,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                 gst(hc)[(int64_t)j * d.hcode_pitch] = (uint16_t)v;
             }
         }
-        if (TABLES && !d.codes && d.global_fams > 0) {
-            // global tables, in code every lane runs: on the sorted fact the rows of a wave often
-            // update one cell (a table keyed by the key a run shares), and then the wave sums its
-            // rows and adds once instead of 64 atomics on one address, which serialise
+        if (TABLES && !d.codes && d.conv_fams > 0) {
+            // families with global tables, in code every lane runs: on the sorted fact the rows of
+            // a wave often update one cell (a table keyed by the key a run shares), and then the
+            // wave sums its rows and adds once instead of 64 atomics on one address, which
+            // serialise
             const uint32_t *cr = W + d.w_comp + lane;
             auto fval = [&](int f) -> double {
                 const FeatLoc L = feat_loc(d, f, f < d.n_feat ? feat_src[f] : 0, wbase);
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             };
             for (int fi = 0; fi < d.n_fam; ++fi) {
                 const AS_CONST FamilyDesc &F = fams[fi];
-                if (F.strided || !F.has_global) continue;
+                if (!F.conv) continue;
                 uint32_t wf = 0u;
                 if (valid) wf = F.wdiv >= 0 ? wt / rb[(children[F.wdiv].quad_base * 64 + lane) * 4] : wt;
                 const double wd = (double)wf;
@@ -760,26 +761,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                     if (ob == 0ull) continue;
                     for (int k = 0; k < F.n_keys; ++k) {
                         const AS_GLOBAL TabDesc &T = gld(d.tabs)[F.tab_base + j * F.n_keys + k];
-                        if (T.part != part || T.lds_cnt >= 0) continue;
+                        if (T.part != part) continue;
                         const AS_CONST KeyDesc &K = keys[F.key_base + k];
                         int32_t cell = 0;
                         for (int c = 0; c < K.n_comp; ++c) cell += (int32_t)cr[K.c[c] * 64] * K.s[c];
+                        const bool lds = T.lds_cnt >= 0;
+                        unsigned long long *gc = d.g_cnt + T.glb_cnt;
+                        double *gv = d.g_val + T.glb_val;
+                        uint32_t *lc = smem + d.lds_tables + T.lds_cnt;
+                        double *lv = reinterpret_cast<double *>(smem + d.lds_tables + T.lds_val);
                         const int32_t c0 = __builtin_amdgcn_readlane(cell, __ffsll((long long)ob) - 1);
                         if (__ballot(on && cell != c0) == 0ull) {
                             const unsigned long long tc = wave_sum_u64(on ? (unsigned long long)wf : 0ull);
-                            if (lane == 0) gadd(d.g_cnt + T.glb_cnt + c0, tc);
-                            double *vs = d.g_val + T.glb_val + (int64_t)c0 * F.n_vals;
+                            if (lane == 0) {
+                                if (lds) atomicAdd(lc + c0, (uint32_t)tc);
+                                else gadd(gc + c0, tc);
+                            }
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
                                 const double tv = wave_sum_f64(on ? fval(vd.a) * fval(vd.b) * wd : 0.0);
-                                if (lane == 0) gadd(vs + v, tv);
+                                if (lane == 0) {
+                                    if (lds) atomicAdd(lv + (int64_t)c0 * F.n_vals + v, tv);
+                                    else gadd(gv + (int64_t)c0 * F.n_vals + v, tv);
+                                }
                             }
                         } else if (on) {
-                            gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wf);
-                            double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
+                            if (lds) atomicAdd(lc + cell, wf);
+                            else gadd(gc + cell, (unsigned long long)wf);
                             for (int v = 0; v < F.n_vals; ++v) {
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
-                                gadd(vs + v, fval(vd.a) * fval(vd.b) * wd);
+                                const double x = fval(vd.a) * fval(vd.b) * wd;
+                                if (lds) atomicAdd(lv + (int64_t)cell * F.n_vals + v, x);
+                                else gadd(gv + (int64_t)cell * F.n_vals + v, x);
                             }
                         }
                     }
@@ -851,6 +864,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                     }
                     continue;
                 }
+                if (F.conv) continue;   // done by the convergent pass
                 uint64_t bits = F.unfiltered ? 1ull : (mask & F.part_mask[part]);
                 while (bits) {
                     int f;
@@ -878,7 +892,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
                                 const AS_CONST ValDesc &vd = vals[F.val_base + v];
                                 atomicAdd(vs + v, fval(vd.a) * fval(vd.b) * wd);
                             }
-                        } else if (d.global_fams == 0) {   // otherwise done by the convergent pass
+                        } else {
                             gadd(d.g_cnt + T.glb_cnt + cell, (unsigned long long)wf);
                             double *vs = d.g_val + T.glb_val + (int64_t)cell * F.n_vals;
                             for (int v = 0; v < F.n_vals; ++v) {

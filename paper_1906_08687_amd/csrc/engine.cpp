@@ -1567,9 +1567,20 @@ static void plan_hist(const lmfao_ctx *c, Plan &P, int budget) {
     }
     P.hist_part_begin.push_back((int32_t)P.hist_slices.size());
     P.hist_lds_bytes = (size_t)max_words * 4;
-    // two rounds of workgroups over the chip (one resident per CU when a partition fills LDS)
+    // about two rounds of workgroups over the chip (one resident per CU when a partition fills
+    // LDS), with the last round as full as it can be: among 3/4x to 2x that many row blocks per
+    // partition, the fewest whose last round leaves under 5% of the chip idle, else the fullest
+    // (every block also flushes its partition's nonzero cells, so more blocks cost atomics)
     const int nparts = (int)parts.size();
-    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2 * (int64_t)c->n_cu, nparts), ceil_div(root.n_rows, 8192)));
+    const int64_t gmin = std::max<int64_t>(1, std::min<int64_t>(ceil_div(2 * (int64_t)c->n_cu, nparts), ceil_div(root.n_rows, 8192)));
+    int64_t gx = gmin;
+    double best_idle = 1.0;
+    for (int64_t g = std::max<int64_t>(1, 3 * gmin / 4); g <= 2 * gmin && g <= std::max<int64_t>(1, ceil_div(root.n_rows, 8192)); ++g) {
+        const double r = (double)(g * nparts) / c->n_cu;
+        const double idle = (std::ceil(r) - r) / std::ceil(r);
+        if (idle < best_idle - 1e-9) { best_idle = idle; gx = g; }
+        if (idle < 0.05) break;
+    }
     P.hist_rows_per_block = round_up((int)ceil_div(root.n_rows, gx), 8);
     P.hist_grid = (int)ceil_div(root.n_rows, P.hist_rows_per_block);
     for (int f : elig) P.fams[f].hist = true;

@@ -409,6 +409,12 @@ static lmfao_status fail(lmfao_ctx *c, lmfao_status s, const std::string &msg) {
     return s;
 }
 
+// The read-only accessors record their message too (every context is created writable by
+// lmfao_create, so the cast is sound).
+static lmfao_status fail(const lmfao_ctx *c, lmfao_status s, const std::string &msg) {
+    return fail(const_cast<lmfao_ctx *>(c), s, msg);
+}
+
 #define HIP_TRY(ctx, call)                                                                                \
     do {                                                                                                  \
         hipError_t e_ = (call);                                                                           \
@@ -2613,15 +2619,15 @@ extern "C" lmfao_status lmfao_plan(lmfao_ctx *c, const lmfao_plan_opts *opts) {
 
 extern "C" lmfao_status lmfao_query_root(const lmfao_ctx *c, int32_t qid, int32_t *rel) {
     if (!c || !rel) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
-    if (qid < 0 || qid >= (int)c->plan.qroot.size()) return LMFAO_ERR_INVALID_ARG;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
+    if (qid < 0 || qid >= (int)c->plan.qroot.size()) return fail(c, LMFAO_ERR_INVALID_ARG, "bad query id");
     *rel = c->plan.qroot[qid];
     return LMFAO_OK;
 }
 
 extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
     if (!c || !s) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     const Plan &P = c->plan;
     memset(s, 0, sizeof *s);
     s->app_aggregates = P.app_aggs;
@@ -2669,14 +2675,14 @@ extern "C" lmfao_status lmfao_plan_stats(const lmfao_ctx *c, lmfao_stats *s) {
 
 extern "C" lmfao_status lmfao_workspace_size(const lmfao_ctx *c, size_t *bytes) {
     if (!c || !bytes) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     *bytes = c->plan.ws_bytes;
     return LMFAO_OK;
 }
 
 extern "C" lmfao_status lmfao_result_size(const lmfao_ctx *c, size_t *bytes) {
     if (!c || !bytes) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     *bytes = c->plan.res_bytes;
     return LMFAO_OK;
 }
@@ -2684,8 +2690,8 @@ extern "C" lmfao_status lmfao_result_size(const lmfao_ctx *c, size_t *bytes) {
 extern "C" lmfao_status lmfao_result_layout(const lmfao_ctx *c, int32_t qid, int64_t *n_cells, int32_t *n_sums,
                                             size_t *counts_off, size_t *sums_off) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
-    if (qid < 0 || qid >= (int)c->plan.outs.size()) return fail(const_cast<lmfao_ctx *>(c), LMFAO_ERR_INVALID_ARG, "bad query id");
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
+    if (qid < 0 || qid >= (int)c->plan.outs.size()) return fail(c, LMFAO_ERR_INVALID_ARG, "bad query id");
     const Output &O = c->plan.outs[qid];
     if (n_cells) *n_cells = O.n_cells;
     if (n_sums) *n_sums = O.n_aggs;
@@ -3019,16 +3025,16 @@ static std::vector<TileCfg> enumerate_candidates(const lmfao_ctx *c) {
 
 extern "C" lmfao_status lmfao_candidates(const lmfao_ctx *c, int32_t *n) {
     if (!c || !n) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     *n = (int32_t)enumerate_candidates(c).size();
     return LMFAO_OK;
 }
 
 extern "C" lmfao_status lmfao_candidate(const lmfao_ctx *c, int32_t i, int32_t cfg[5]) {
     if (!c || !cfg) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     auto v = enumerate_candidates(c);
-    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    if (i < 0 || i >= (int)v.size()) return fail(c, LMFAO_ERR_INVALID_ARG, "bad candidate index");
     cfg[0] = v[i].waves;
     cfg[1] = v[i].nbuf;
     cfg[2] = v[i].grid_x;
@@ -3086,9 +3092,9 @@ static void features_of(const lmfao_ctx *c, const TileCfg &t, float *f) {
 
 extern "C" lmfao_status lmfao_candidate_features(const lmfao_ctx *c, int32_t i, float *features) {
     if (!c || !features) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     auto v = enumerate_candidates(c);
-    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    if (i < 0 || i >= (int)v.size()) return fail(c, LMFAO_ERR_INVALID_ARG, "bad candidate index");
     features_of(c, v[i], features);
     return LMFAO_OK;
 }
@@ -3110,9 +3116,9 @@ static lmfao_status select_cfg(lmfao_ctx *c, const TileCfg &t) {
 
 extern "C" lmfao_status lmfao_select_candidate(lmfao_ctx *c, int32_t i) {
     if (!c) return LMFAO_ERR_INVALID_ARG;
-    if (!c->plan.ok) return LMFAO_ERR_STATE;
+    if (!c->plan.ok) return fail(c, LMFAO_ERR_STATE, "no plan: call lmfao_plan first");
     auto v = enumerate_candidates(c);
-    if (i < 0 || i >= (int)v.size()) return LMFAO_ERR_INVALID_ARG;
+    if (i < 0 || i >= (int)v.size()) return fail(c, LMFAO_ERR_INVALID_ARG, "bad candidate index");
     return select_cfg(c, v[i]);
 }
 

@@ -549,3 +549,38 @@ def test_find_roots_assigns_grouped_queries_to_their_relations():
         first = next(n for n in order if W[n] > 0 and any(owner[g.attr] == n for g in q.groupby))
         assert r == idx[top(first)], (q, r, first)
     assert ctx.stats()["target_queries"] == sum(1 for r in roots if r != idx["F"]) > 0
+
+
+def test_root_assignment_falls_back_and_forced_views_are_bounded():
+    """A query the paper's root assignment sends to a dimension stays at the tree root when
+    its view towards that dimension would exceed 2^24 cells (the dimension's key domain times
+    the query's other group-by cells); a query forced to a many-to-many child by such a view
+    is TOO_LARGE instead."""
+    from datagen.schema import GroupBy, Query
+    big = 1 << 23
+    ctx = new_ctx()
+    ctx.add_relation("F", 1 << 20, [("k", lmfao.I32, lmfao.KEY, big, FAKE), ("fc", lmfao.I32, lmfao.CAT, 4, FAKE)])
+    ctx.add_relation("D", big, [("k", lmfao.I32, lmfao.KEY, big, FAKE), ("dc", lmfao.I32, lmfao.CAT, 9, FAKE)])
+    ctx.set_join_tree([(0, 1)])
+    qs = [Query(groupby=[GroupBy("dc")]), Query(groupby=[GroupBy("dc")]),
+          Query(groupby=[GroupBy("dc"), GroupBy("fc")])]
+    for q in qs:
+        ctx.add_query(q)
+    ctx.plan("fp32", "batched", root="find")
+    # D carries the larger weight (2.5 against 0.5): the two dc queries go there (views of 2^23
+    # cells); the (dc, fc) query's view would be 2^25 cells, so it stays at F
+    assert [ctx.query_root(i) for i in range(3)] == [1, 1, 0]
+    assert ctx.stats()["target_queries"] == 2
+    ctx.plan("fp32", "batched", root="tree")
+    assert [ctx.query_root(i) for i in range(3)] == [0, 0, 0]
+    expect("INVALID_ARG", lambda: ctx.query_root(3))
+
+    ctx = new_ctx()
+    ctx.add_relation("F", 1 << 20, [("k", lmfao.I32, lmfao.KEY, big, FAKE), ("fc", lmfao.I32, lmfao.CAT, 4, FAKE)])
+    ctx.add_relation("C", 1 << 24, [("k", lmfao.I32, lmfao.KEY_MANY, big, FAKE), ("cc", lmfao.I32, lmfao.CAT, 3, FAKE)])
+    ctx.set_join_tree([(0, 1)])
+    ctx.add_query(Query(groupby=[GroupBy("cc")]))
+    ctx.plan("fp32", "batched")
+    assert ctx.query_root(0) == 1
+    ctx.add_query(Query(groupby=[GroupBy("cc"), GroupBy("fc")]))
+    expect("TOO_LARGE", lambda: ctx.plan("fp32", "batched"))

@@ -6,6 +6,8 @@
 // v_mfma_f32_16x16x32_bf16 (see the per-tile steps below).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "desc.h"
 #include "device.h"
 
@@ -268,7 +270,70 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     constexpr int NMID = PM == 6 ? NT : 1;
     bf16x8 oph[2][NT], opl[2][NT], opm[2][NMID];
     const SplitSel sel = split_sel();
-    auto phase1 = [&](int t) -> bool {
+    // The 8 values of slot tile t2 this lane feeds in k-step ks: rows 32ks + 4g + {0..3} and
+    // 32ks + 16 + 4g + {0..3} of its slot.  Whole fact tiles and record tiles read one source for
+    // every lane; only the last fact tile of a fact whose features do not fill it (wave-uniform
+    // `mixed`) chooses per lane.
+    auto read_slot = [&](int ks, int t2, float *x) {
+        const char *sm = reinterpret_cast<const char *>(smem);
+        auto read_fact = [&]() {
+            const char *base = sm + lds_off[t2] + 128 * ks + 16 * lg;
+            const f32x4 lo4 = *reinterpret_cast<const f32x4 *>(base);
+            const f32x4 hi4 = *reinterpret_cast<const f32x4 *>(base + 64);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                x[e] = lo4[e];
+                x[4 + e] = hi4[e];
+            }
+        };
+        auto read_rec = [&]() {
+            if (PR) {
+                // row 32ks + 4g + i sits at position 32ks + 4i + g (see pair_row_of)
+                const float *p = reinterpret_cast<const float *>(sm + lds_off[t2]) + 8 * lg + 256 * ks;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    x[i] = p[32 * i];
+                    x[4 + i] = p[128 + 32 * i];
+                }
+            } else {
+                const float *p = reinterpret_cast<const float *>(sm + lds_off[t2] + 16 * kRowWords * lg + 128 * kRowWords * ks);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    x[i] = p[kRowWords * i];
+                    x[4 + i] = p[16 * kRowWords + kRowWords * i];
+                }
+            }
+        };
+        if (t2 >= NF) read_rec();
+        else if (!(t2 == NF - 1 && mixed)) read_fact();
+        else if (is_fact[t2]) read_fact();
+        else read_rec();
+    };
+    // every operand of both k-steps split into bf16 pieces; with `masked`, the values of rows
+    // outside the tile's valid rows vm are zeroed first (a separate copy, so that tiles whose rows
+    // are all valid, nearly all of them, spend no instructions on the mask)
+    auto split_tile = [&](uint64_t vm, auto masked) {
+        constexpr bool M = decltype(masked)::value;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const uint32_t vbits = M ? (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
+                                           ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4)
+                                     : 0xFFu;
+#pragma unroll
+            for (int t2 = 0; t2 < NT; ++t2) {
+                float x[8];
+                read_slot(ks, t2, x);
+                if (M) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((vbits >> i) & 1u)) x[i] = 0.f;
+                }
+                if (PM == 6) split3_bf16x8(sel, x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
+                else split_bf16x8(sel, x, oph[ks][t2], opl[ks][t2]);
+            }
+        }
+    };
+    auto phase1 = [&](int t) {
         const int r0 = tile_row(t);
         bool valid = r0 + lane < blk_end;
         uint32_t cnt[kGramMaxChild];
@@ -280,55 +345,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             if (cnt[c] == 0u) valid = false;
         const uint64_t vm = __ballot(valid);
         count += (unsigned long long)__popcll(vm);
-        const bool all_rows = vm == ~0ull;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const uint32_t vbits = (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
-                                   ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4);
-#pragma unroll
-            for (int t2 = 0; t2 < NT; ++t2) {
-                float x[8];
-                if (t2 < NF && is_fact[t2]) {
-                    // rows 32ks + 4g + {0..3} and 32ks + 16 + 4g + {0..3} of the slot's column
-                    const char *base = reinterpret_cast<const char *>(smem) + lds_off[t2] + 128 * ks + 16 * lg;
-                    const f32x4 lo4 = *reinterpret_cast<const f32x4 *>(base);
-                    const f32x4 hi4 = *reinterpret_cast<const f32x4 *>(base + 64);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        x[e] = lo4[e];
-                        x[4 + e] = hi4[e];
-                    }
-                }
-                if (t2 >= NF || (t2 == NF - 1 && mixed)) {
-                    if ((t2 >= NF || !is_fact[t2]) && PR) {
-                        // row 32ks + 4g + i sits at position 32ks + 4i + g (see pair_row_of)
-                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) + lds_off[t2]) +
-                                         8 * lg + 256 * ks;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            x[i] = p[32 * i];
-                            x[4 + i] = p[128 + 32 * i];
-                        }
-                    } else if (t2 >= NF || !is_fact[t2]) {
-                        const float *p = reinterpret_cast<const float *>(reinterpret_cast<const char *>(smem) +
-                                                                         lds_off[t2] + 16 * kRowWords * lg + 128 * kRowWords * ks);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            x[i] = p[kRowWords * i];
-                            x[4 + i] = p[16 * kRowWords + kRowWords * i];
-                        }
-                    }
-                }
-                if (!all_rows) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (!((vbits >> i) & 1u)) x[i] = 0.f;
-                }
-                if (PM == 6) split3_bf16x8(sel, x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
-                else split_bf16x8(sel, x, oph[ks][t2], opl[ks][t2]);
-            }
-        }
-        return true;
+        if (vm == ~0ull) split_tile(vm, std::false_type{});
+        else split_tile(vm, std::true_type{});
     };
     // Phase 2: the MFMAs of both k-steps, from registers only.
     auto mfma_pass = [&](const bf16x8 *A, const bf16x8 *B) {

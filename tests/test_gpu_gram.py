@@ -3,8 +3,8 @@ layouts it distinguishes: fact-only tiles, a fact tile shared with record
 lanes, two fact tiles, four tiles, no fact features at all, a fact without a
 ragged tail, records of one to five quads (a key uniform over a tile is
 gathered once, others row by row), a key that changes on nearly every row,
-fact keys without a dimension row, and every tile candidate of the
-autotuner.  Record buffers take both layouts: pair rows when every record has
+large dimensions beside small ones, fact keys without a dimension row, and
+every tile candidate of the autotuner (also over a 40,000-row dimension).  Record buffers take both layouts: pair rows when every record has
 at most two quads (facts-only-tile, whole-tiles, distinct-keys, whose first
 dimension has one-quad records), quad-major otherwise.
 
@@ -48,6 +48,9 @@ SHAPES = [
     ("wide-record", 30_007, 4, [(400, 18), (50, 5)], 1.1),
     # 400k keys under 40k rows: the key changes on nearly every row
     ("distinct-keys", 40_009, 3, [(50, 2), (400_000, 5)], 0.0),
+    # two large dimensions (records gathered row by row) beside two small ones whose keys stay
+    # the same over runs of the sorted fact (gathered once per tile, or kept from the last one)
+    ("large-and-small-dims", 120_011, 12, [(60_000, 6), (300, 6), (20_000, 4), (9, 2)], 1.1),
 ]
 
 
@@ -122,9 +125,11 @@ def test_dedicated_scan_dangling_keys():
     assert int(eng.results()[0].counts[0]) < 20_011
 
 
-def test_dedicated_scan_every_candidate_agrees():
+@pytest.mark.parametrize("dims", [[(3000, 6), (200, 6), (20, 6)], [(40_000, 6), (200, 6), (20, 6)]],
+                         ids=["small-dims", "large-dim"])
+def test_dedicated_scan_every_candidate_agrees(dims):
     from paper_1906_08687_amd.lmfao import Engine
-    db = _star(13, 90_001, 16, [(3000, 6), (200, 6), (20, 6)], 1.2)
+    db = _star(13, 90_001, 16, dims, 1.2)
     qs = covariance_queries(cont_attrs(db))
     eng = Engine(db, qs, precision=FULL, schedule="batched")
     cands = eng.ctx.candidates()

@@ -399,10 +399,11 @@ struct HistDesc {
 // the block is computed in BF16 on matrix cores, a dedicated scan runs it.  Its
 // features live in "slots": [fact features][child record features][the
 // constant 1][zero padding], so that a 16-wide MFMA tile draws all of its
-// lanes from one kind of source where the counts allow.  Fact slots are loaded
-// from HBM straight into registers in the MFMA operand layout; record slots
-// and the constant slot are read out of LDS, where child view records are
-// gathered with buffer loads that bypass registers.
+// lanes from one kind of source where the counts allow.  Fact columns are
+// loaded from HBM in 256-byte runs per column and staged in a per-wave LDS fact
+// tile; child view records are gathered into LDS with buffer loads that bypass
+// registers; every slot's operand (fact, record or the constant) is read from
+// LDS in the MFMA operand layout.
 
 constexpr int kGramMaxChild = 4;
 constexpr int kGramMaxSlots = 64;

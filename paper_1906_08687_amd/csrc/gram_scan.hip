@@ -1,9 +1,10 @@
 // The covariance-only root scan of the aggregate-batch engine, written for
 // gfx950 (CDNA4): when the root relation's view group is the covariance
-// block (Section 2, equation (2)) and the total count alone, computed in
-// BF16 hi+lo split on matrix cores, this kernel scans the fact once,
-// gathers the child view records, and accumulates the block on
-// v_mfma_f32_16x16x32_bf16 (see the per-tile steps below).
+// block (Section 2, equation (2)) and the total count alone, computed from
+// bf16 pieces of every value (hi + lo, or hi + mid + lo) on matrix cores,
+// this kernel scans the fact once, gathers the child view records, and
+// accumulates the block on v_mfma_f32_16x16x32_bf16 (see the per-tile steps
+// below).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -14,7 +15,7 @@
 namespace lmfao {
 
 // ---------------------------------------------------------------------------
-// covariance-only root scan (BF16 hi+lo split on matrix cores)
+// covariance-only root scan (bf16 pieces on matrix cores)
 // ---------------------------------------------------------------------------
 
 // Pair-row record buffers hold row r = 16b + 4g + i at position 16b + 4i + g (a transpose of
@@ -38,9 +39,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 //   2. spread records gathered once for a uniform key to every row; write tile
 //      t's facts (loaded as 256 contiguous bytes per column) from registers to
 //      the wave's LDS fact tile, and request tile t+1's facts into them;
-//   3. find the tile's valid rows and split every slot value x = hi + lo in
-//      bf16 into operand registers (from the fact tile, the record buffer and
-//      the constant block);
+//   3. find the tile's valid rows and split every slot value into its bf16
+//      pieces (x = hi + lo, or hi + mid + lo) in operand registers, read from
+//      the fact tile, the record buffer and the constant block (rows outside
+//      the valid ones are zeroed first, in a copy of this step that only tiles
+//      with such rows run);
 //   4. gather tile t+1's child records into the record buffer with buffer
 //      loads that bypass registers (a key outside [0, n_keys) reads past the
 //      buffer range and lands as zeros: no join), then request the keys of

@@ -315,27 +315,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
     // every operand of both k-steps split into bf16 pieces; with `masked`, the values of rows
     // outside the tile's valid rows vm are zeroed first (a separate copy, so that tiles whose rows
     // are all valid, nearly all of them, spend no instructions on the mask)
-    auto split_tile = [&](uint64_t vm, auto masked) {
-        constexpr bool M = decltype(masked)::value;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const uint32_t vbits = M ? (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
-                                           ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4)
-                                     : 0xFFu;
-#pragma unroll
-            for (int t2 = 0; t2 < NT; ++t2) {
-                float x[8];
-                read_slot(ks, t2, x);
-                if (M) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (!((vbits >> i) & 1u)) x[i] = 0.f;
-                }
-                if (PM == 6) split3_bf16x8(sel, x, oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
-                else split_bf16x8(sel, x, oph[ks][t2], opl[ks][t2]);
-            }
-        }
-    };
+    // Phase 1 reads every operand value of both k-steps out of LDS (then the tile's LDS buffers
+    // are free for the next copies) and zeroes the values of rows outside the tile's valid rows,
+    // in a branch that tiles whose 64 rows are all valid, nearly all of them, skip; the split
+    // into bf16 pieces follows the copies, where the compiler interleaves it with the MFMAs.
+    float xv[2][NT][8];
     auto phase1 = [&](int t) {
         const int r0 = tile_row(t);
         bool valid = r0 + lane < blk_end;
@@ -348,8 +332,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             if (cnt[c] == 0u) valid = false;
         const uint64_t vm = __ballot(valid);
         count += (unsigned long long)__popcll(vm);
-        if (vm == ~0ull) split_tile(vm, std::false_type{});
-        else split_tile(vm, std::true_type{});
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int t2 = 0; t2 < NT; ++t2) read_slot(ks, t2, xv[ks][t2]);
+        if (vm != ~0ull) {
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const uint32_t vbits = (uint32_t)((vm >> (32 * ks + 4 * lg)) & 0xFull) |
+                                       ((uint32_t)((vm >> (32 * ks + 16 + 4 * lg)) & 0xFull) << 4);
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((vbits >> i) & 1u)) xv[ks][t2][i] = 0.f;
+            }
+        }
+    };
+    auto split_all = [&]() {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int t2 = 0; t2 < NT; ++t2) {
+                if (PM == 6) split3_bf16x8(sel, xv[ks][t2], oph[ks][t2], opm[ks][t2 < NMID ? t2 : 0], opl[ks][t2]);
+                else split_bf16x8(sel, xv[ks][t2], oph[ks][t2], opl[ks][t2]);
+            }
     };
     // Phase 2: the MFMAs of both k-steps, from registers only.
     auto mfma_pass = [&](const bf16x8 *A, const bf16x8 *B) {
@@ -440,7 +447,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         wave_sync();
         issue_rec();                                    // tile t+1 (keys loaded last step)
         load_keys(min(t + 2, n_tiles - 1));
-        if (live) phase2();                             // MFMAs while the copies are in flight
+        if (live) {
+            split_all();
+            phase2();                                   // MFMAs while the copies are in flight
+        }
     };
 
     if (n_tiles > 0) {

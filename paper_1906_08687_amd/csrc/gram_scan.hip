@@ -39,17 +39,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, 
 //   2. spread records gathered once for a uniform key to every row; write tile
 //      t's facts (loaded as 256 contiguous bytes per column) from registers to
 //      the wave's LDS fact tile, and request tile t+1's facts into them;
-//   3. find the tile's valid rows and split every slot value into its bf16
-//      pieces (x = hi + lo, or hi + mid + lo) in operand registers, read from
-//      the fact tile, the record buffer and the constant block (rows outside
-//      the valid ones are zeroed first, in a copy of this step that only tiles
-//      with such rows run);
+//   3. find the tile's valid rows and read every slot value of both k-steps
+//      into registers, from the fact tile, the record buffer and the constant
+//      block (values of rows outside the valid ones are zeroed, in a branch
+//      that only tiles with such rows take);
 //   4. gather tile t+1's child records into the record buffer with buffer
 //      loads that bypass registers (a key outside [0, n_keys) reads past the
 //      buffer range and lands as zeros: no join), then request the keys of
 //      tile t+2 (after the last tile these requests repeat it, unused);
-//   5. accumulate the products of the split (see PM) for every upper-triangle
-//      16x16 tile pair on MFMA while those copies are in flight.
+//   5. split every value into its bf16 pieces (x = hi + lo, or hi + mid + lo)
+//      and accumulate their products (see PM) for every upper-triangle 16x16
+//      tile pair on MFMA while those copies are in flight.
 // Fact columns and keys are streamed once: their loads are non-temporal, so
 // they do not push the gathered view records out of the caches.  Each wave
 // writes its own fp64 partial of the upper triangle (no LDS reduction).
@@ -267,9 +267,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
             for (int q = 0; q < 4; ++q) *reinterpret_cast<f32x4 *>(reinterpret_cast<char *>(smem) + fst[f][q]) = F[f][q];
     };
 
-    // Phase 1 of a tile: validity, then every operand of both k-steps split into bf16 hi/lo
-    // registers.  After it the tile needs neither its LDS record buffer nor its fact
-    // registers, so the next copies can be issued before phase 2 (the MFMAs) runs.
+    // the operands of both k-steps: bf16 pieces of every slot value (hi, lo, and mid in the
+    // six-product form)
     constexpr int NMID = PM == 6 ? NT : 1;
     bf16x8 oph[2][NT], opl[2][NT], opm[2][NMID];
     const SplitSel sel = split_sel();
@@ -312,9 +311,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NT >= 4 
         else if (is_fact[t2]) read_fact();
         else read_rec();
     };
-    // every operand of both k-steps split into bf16 pieces; with `masked`, the values of rows
-    // outside the tile's valid rows vm are zeroed first (a separate copy, so that tiles whose rows
-    // are all valid, nearly all of them, spend no instructions on the mask)
     // Phase 1 reads every operand value of both k-steps out of LDS (then the tile's LDS buffers
     // are free for the next copies) and zeroes the values of rows outside the tile's valid rows,
     // in a branch that tiles whose 64 rows are all valid, nearly all of them, skip; the split
